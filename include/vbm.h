@@ -1,0 +1,292 @@
+/*
+ * vbm.h -- C ABI of the MI355X (gfx950) Variable Basis Mapping library, libvbm.so.
+ *
+ * Variable Basis Mapping (VBM) turns a volume into a 3D Gaussian Splatting scene: a transfer
+ * function maps the scalar field to RGBA (Sec. 3), a J-level 3D DWT decomposes it (Sec. 3,
+ * Sec. 4.3 eq. mul_wavelet_coff), every kept coefficient becomes one Gaussian by a lookup in the
+ * Wavelet-to-Gaussian Transition Bank (Sec. 4.2, Sec. 4.3), and an image-space fine-tuning loop
+ * refines the Gaussians against direct-volume-rendered images (Sec. 4.4).  This library runs that
+ * path on the GPU: vbm_dwt3d, vbm_build_gaussians, vbm_render_fwd, vbm_render_bwd, plus the loss,
+ * optimiser and supervision-renderer kernels of the fine-tuning loop.
+ *
+ * Conventions for every call:
+ *   - Pointers are DEVICE pointers unless the parameter name ends in "_host".
+ *   - The caller owns all memory.  The library never allocates device memory: each call that
+ *     needs scratch space takes a workspace sized by the matching *_workspace_size() function or
+ *     by vbm_plan_make().
+ *   - Every call enqueues on the given HIP stream (a hipStream_t passed as void*, NULL = the null
+ *     stream) and returns without synchronising, except vbm_render_fwd in VBM_MODE_EXACT, which
+ *     synchronises once to read the pair count.
+ *   - Argument checks run on the host before anything is enqueued, so a call that returns an
+ *     error has launched nothing.  vbm_last_error() returns a thread-local message.
+ *   - Conditions found on the device (pair-list overflow) are reported through caller-provided
+ *     device flags, never by aborting.
+ *   - Volumes are float32 [z][y][x] (x fastest), G^3 values, covering [-1, 1]^3 with voxel i
+ *     centred at -1 + (2/G)(i + 1/2).
+ */
+#ifndef VBM_H
+#define VBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vbm_status;
+#define VBM_OK 0
+#define VBM_ERR_INVALID (-1)     /* bad argument (null pointer, size, range) */
+#define VBM_ERR_UNSUPPORTED (-2) /* wavelet, tile size or device not supported */
+#define VBM_ERR_WORKSPACE (-3)   /* workspace smaller than required */
+#define VBM_ERR_HIP (-4)         /* a HIP runtime call failed */
+#define VBM_ERR_CAPACITY (-5)    /* a fixed capacity was exceeded (host-detected) */
+
+#define VBM_WAVELET_HAAR 0   /* Haar, the paper's ablation basis (Sec. 5.4) */
+#define VBM_WAVELET_BIOR44 1 /* biorthogonal 4.4 = CDF 9/7, the paper's default (Sec. 4.2) */
+
+const char* vbm_version(void);
+const char* vbm_last_error(void);
+
+/* ------------------------------------------------------------------------------------------
+ * Transfer function (Sec. 3, Transfer Function): RF = TF(F), scalar -> RGBA.  Piecewise linear
+ * through n_points ascending control points x[i] with values rgba[i][0..3]; constant beyond the
+ * end points.  Host struct, passed by pointer, copied at call time.
+ * ------------------------------------------------------------------------------------------ */
+#define VBM_TF_MAX_POINTS 16
+typedef struct {
+  int32_t n_points;
+  float x[VBM_TF_MAX_POINTS];
+  float rgba[VBM_TF_MAX_POINTS][4];
+} vbm_tf;
+
+/* ------------------------------------------------------------------------------------------
+ * vbm_dwt3d -- RGBA wavelet coefficients A_{j,o,k,c} of TF(vol) (Sec. 4.3, eq. mul_wavelet_coff).
+ *
+ *   vol     float32 [G][G][G] scalar field (tf != NULL), or float32 [4][G^3] planar RGBA (tf == NULL)
+ *   G, J    grid size and levels; G % 2^J == 0, 2 <= G/2^J, 1 <= J <= 10, G <= 1024
+ *   wavelet VBM_WAVELET_HAAR or VBM_WAVELET_BIOR44; periodised separable analysis, x then y then z
+ *           per level, the next level on LLL
+ *   coeffs  float32 [4][G^3] output, per channel in the packed subband layout
+ *           [LLL_J][level J: o=1..7][level J-1: o=1..7]...[level 1: o=1..7],
+ *           block (j, o) = [n^3] in [kz][ky][kx] order, n = G/2^j; orientation o has bit d set
+ *           when the high-pass was taken along axis d (bit 0 = x, 1 = y, 2 = z)
+ *   ws      workspace of vbm_dwt3d_workspace_size(G, J) bytes
+ * Errors: VBM_ERR_INVALID on null pointers or sizes, VBM_ERR_UNSUPPORTED on an unknown wavelet
+ * or more than VBM_TF_MAX_POINTS control points, VBM_ERR_WORKSPACE if ws_bytes is too small.
+ * ------------------------------------------------------------------------------------------ */
+size_t vbm_dwt3d_workspace_size(int32_t G, int32_t J);
+vbm_status vbm_dwt3d(const float* vol, int32_t G, int32_t J, int32_t wavelet, const vbm_tf* tf_host,
+                     float* coeffs, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Transition bank (Sec. 4.2: eq. canonical_wavelet, eq. roi, eq. moment, eq. canonical_gaussian,
+ * eq. ridge_regression), computed on the host in double precision.  One entry per subband in the
+ * packed block order above: 7J + 1 entries (seven orientations per level plus the final LLL).
+ *   u      centroid of the dominant lobe, voxel-index units relative to the impulse origin 2^j k
+ *   sigma  weighted covariance over the ROI {W > tau max W}: xx, yy, zz, xy, xz, yz
+ *   w      ridge-regression amplitude <G,|Y|> / (<G,G> + lambda)
+ *   scale, quat  sigma = R(quat) diag(scale^2) R(quat)^T; quat (w, x, y, z), w >= 0; identity and
+ *          scale = sqrt(diag sigma) when sigma is diagonal
+ * vbm_bank_pack writes VBM_BANK_FLOATS floats per entry (w, u[3], scale[3], quat[4], pad) into
+ * host memory; the caller uploads them for vbm_build_gaussians.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+  int32_t j, o, roi_size, pad;
+  double w;
+  double u[3];
+  double sigma[6];
+  double scale[3];
+  double quat[4];
+} vbm_bank_entry;
+
+#define VBM_BANK_FLOATS 12
+int32_t vbm_bank_size(int32_t J);
+vbm_status vbm_bank_build(int32_t wavelet, int32_t J, double tau, double lambda, vbm_bank_entry* out_host);
+vbm_status vbm_bank_pack(const vbm_bank_entry* entries_host, int32_t n_entries, float* out_host);
+
+/* ------------------------------------------------------------------------------------------
+ * Gaussian parameter sets.  Structure of arrays, float32, one plane per component with plane
+ * stride `stride` (>= number of Gaussians):
+ *   means [3][stride] world x, y, z         scales  [3][stride] > 0 (activated)
+ *   quats [4][stride] w, x, y, z (any norm) opacity [stride] in (0, 1) (activated)
+ *   rgb   [3][stride]
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+  float* means;
+  float* scales;
+  float* quats;
+  float* opacity;
+  float* rgb;
+  int64_t stride;
+} vbm_gaussians;
+
+typedef struct {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opacity;
+  const float* rgb;
+  int64_t stride;
+} vbm_gaussians_c;
+
+/* ------------------------------------------------------------------------------------------
+ * vbm_build_gaussians -- joint-norm top-K selection and analytical construction (Sec. 4.3:
+ * eq. per_location_weight, eq. wavelet_gaussian_kernel, eq. translation_operator; joint norm of
+ * Supp. A).  Keeps the K locations with the largest float32 joint norm
+ * sqrt(((R^2 + G^2) + B^2) + A^2) (ties to the lower packed index) and emits them in ascending
+ * packed-index order, one Gaussian each:
+ *   mean  = -1 + h (u_{j,o} + 2^j k + delta), h = 2/G;  scale = h scale_{j,o};  quat = quat_{j,o}
+ *   amp   = s_j |A_{j,o,k,:}| w_{j,o}, s_j = 2^{-3j/2} (s_mode 0) or 1 (s_mode 1)
+ *   opacity = clamp(amp_A, opacity_min, opacity_max), rgb = clamp(amp_RGB, 0, 1)
+ *   coeffs      float32 [4][G^3] as written by vbm_dwt3d
+ *   bank_dev    VBM_BANK_FLOATS * (7J+1) floats from vbm_bank_pack
+ *   kept_index  optional int64 [K] output of the kept packed indices (NULL to skip)
+ * Errors: VBM_ERR_INVALID for K < 1 or K > G^3, null pointers or bad opts.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+  int32_t s_mode;
+  float delta;
+  float opacity_min;
+  float opacity_max;
+} vbm_build_opts;
+
+size_t vbm_build_workspace_size(int32_t G, int32_t J);
+vbm_status vbm_build_gaussians(const float* coeffs, int32_t G, int32_t J, const float* bank_dev, int64_t K,
+                               const vbm_build_opts* opts_host, vbm_gaussians out, int64_t* kept_index, void* ws,
+                               size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Rendering batches.  A batch renders n_views views; view v shows scene `scene` of a
+ * concatenated Gaussian set whose scene s occupies Gaussians [scene_offsets[s], scene_offsets[s+1]).
+ * Pinhole camera, OpenCV axes (x right, y down, z forward); viewmat is world->camera [R|t],
+ * 3x4 row-major; pixel (i, j) samples the image plane at (i + 0.5, j + 0.5).
+ *
+ * Rasteriser (the paper cites 3DGS for it, Sec. 4.4): EWA projection with 0.3 px dilation and
+ * a 1.3x field-of-view clamp in the Jacobian, near-plane cull, 3-sigma tile rectangles, pairs in
+ * ascending (global tile, float32 depth bits, item) order, front-to-back compositing per pixel with
+ * alpha = min(0.99, o exp(power)), skip alpha < 1/255, stop before adding once T would drop below
+ * 1e-4.  Images are planar float32 [3][H][W] per view, concatenated in view order;
+ * final_T and n_contrib are [H][W] per view, concatenated.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+  int32_t scene;
+  int32_t width, height;
+  int32_t pad;
+  float fx, fy, cx, cy;
+  float near_plane;
+  float viewmat[12];
+  float bg[3];
+} vbm_view;
+
+#define VBM_MODE_BATCHED 0 /* counts stay on the device: no host sync, graph-capturable */
+#define VBM_MODE_EXACT 1   /* one host sync per call to read the pair count; sort sized exactly */
+
+typedef struct {
+  int32_t tile;          /* tile edge in pixels: 8, 16 or 32 */
+  int32_t sort_bits;     /* radix digit width for the tile sort: 4..8 */
+  int64_t pair_capacity; /* pair slots reserved in the workspace (> 0) */
+  int32_t mode;          /* VBM_MODE_BATCHED or VBM_MODE_EXACT */
+  int32_t pad;
+} vbm_schedule;
+
+#define VBM_WS_REGIONS 24
+typedef struct {
+  int32_t n_views, n_scenes, tile, mode;
+  int32_t sort_bits, tile_key_bits, pad0, pad1;
+  int64_t n_gaussians, n_items, n_tiles, n_pixels, pair_capacity;
+  size_t view_table_bytes; /* device view table written by vbm_plan_make into view_table_host */
+  size_t ws_bytes;         /* workspace needed by vbm_render_fwd + vbm_render_bwd */
+  size_t region_offset[VBM_WS_REGIONS];
+  size_t region_bytes[VBM_WS_REGIONS];
+} vbm_plan;
+
+/* Workspace regions a test may read back after vbm_render_fwd (offsets into ws). */
+#define VBM_REGION_COUNTERS 0    /* uint32 [16]: [0] visible items, [1] pairs, [2] overflow */
+#define VBM_REGION_ITEM_DEPTH 1  /* float32 [n_items] camera depth (0 when culled) */
+#define VBM_REGION_ITEM_RECT 2   /* uint32 [2][n_items]: x0 | x1 << 16, y0 | y1 << 16 */
+#define VBM_REGION_ITEM_NTILES 3 /* uint32 [n_items] */
+#define VBM_REGION_ITEM_REC 4    /* float32 [n_items][8]: mean2d.xy, conic.abc, opacity, r, g */
+#define VBM_REGION_ITEM_BLUE 5   /* float32 [n_items]: blue */
+#define VBM_REGION_PAIR_TILE 6   /* uint32 [pair_capacity]: sorted global tile of each pair */
+#define VBM_REGION_PAIR_ITEM 7   /* uint32 [pair_capacity]: sorted item of each pair */
+#define VBM_REGION_RANGES 8      /* uint32 [n_tiles][2]: [start, end) of each tile's list */
+#define VBM_REGION_GRAD2D 9      /* float32 [9][n_items]: dmean2d.xy, dconic.abc, dopacity, drgb */
+
+/* Plans a batch (host only).  scene_offsets_host is int64 [n_scenes + 1].  If view_table_host
+ * is not NULL it receives plan->view_table_bytes bytes that the caller copies to the device and
+ * passes as view_table_dev.  Item i of view v is Gaussian scene_offsets[scene_v] + (i - item_offset_v). */
+vbm_status vbm_plan_make(const vbm_view* views_host, int32_t n_views, const int64_t* scene_offsets_host,
+                         int32_t n_scenes, const vbm_schedule* sched_host, vbm_plan* plan_out,
+                         void* view_table_host);
+
+/* ------------------------------------------------------------------------------------------
+ * vbm_render_fwd -- project (all views), bin, depth-sort, tile-sort and composite.
+ *   status    device int32 [4]: [0] set to 1 if the pair list overflowed pair_capacity (the images
+ *             are then incomplete; re-plan with a larger capacity), [1] pair count, [2] visible items
+ *   ws        plan->ws_bytes; holds the state vbm_render_bwd needs, keep it unchanged between
+ * ------------------------------------------------------------------------------------------ */
+vbm_status vbm_render_fwd(const vbm_plan* plan_host, const void* view_table_dev, vbm_gaussians_c g, float* image,
+                          float* final_T, int32_t* n_contrib, int32_t* status, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/* ------------------------------------------------------------------------------------------
+ * vbm_render_bwd -- gradient of sum <dL_dimg, image> w.r.t. the activated parameters, by
+ * reverse-order compositing that recomputes each pixel's transmittance from final_T by division,
+ * then the chain through the EWA projection, summed over views.
+ *   grads       same SoA layout as the parameters; written (accumulate = 0) or added to (1)
+ * ------------------------------------------------------------------------------------------ */
+vbm_status vbm_render_bwd(const vbm_plan* plan_host, const void* view_table_dev, vbm_gaussians_c g,
+                          const float* dL_dimg, const float* final_T, const int32_t* n_contrib, vbm_gaussians grads,
+                          int32_t accumulate, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------------------------
+ * vbm_image_loss -- fine-tuning loss (Sec. 4.4, "as in 3DGS") and its gradient w.r.t. the image.
+ *   kind 0: L1 = mean |I - I_ref| over all views, channels and pixels
+ *   kind 1: (1 - lambda) L1 + lambda (1 - SSIM), SSIM per channel with an 11x11 Gaussian window
+ *           (sigma 1.5), zero-padded "same" filtering, C1 = 0.01^2, C2 = 0.03^2, averaged over all
+ *           views, channels and pixels
+ *   view_dims_host int32 [n_views][2] = (width, height); images laid out as for vbm_render_fwd
+ *   dL_dimg  written; loss_dev float32 [1] written
+ * ------------------------------------------------------------------------------------------ */
+size_t vbm_image_loss_workspace_size(const int32_t* view_dims_host, int32_t n_views, int32_t kind);
+vbm_status vbm_image_loss(const float* image, const float* target, const int32_t* view_dims_host, int32_t n_views,
+                          int32_t kind, float lambda, float* dL_dimg, float* loss_dev, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/* ------------------------------------------------------------------------------------------
+ * vbm_adam_step -- Adam (Sec. 5, Implementation Details) on the raw parameters.
+ *   raw, m, v  float32 [14][stride]: rows 0-2 means, 3-5 log scales, 6-9 quats, 10 logit opacity,
+ *              11-13 rgb
+ *   grads      activated-parameter gradients (from vbm_render_bwd), chained through
+ *              scale = exp(raw) and opacity = sigmoid(raw) inside the kernel
+ *   act        written with the updated activated parameters
+ *   lr         per group: means, log scales, quats, logit opacity, rgb
+ *   step_dev   optional device int32 step counter: when non-NULL the call first increments it and the
+ *              kernel reads the step from it (so a captured graph replays with advancing steps);
+ *              when NULL, opts->step (1-based) is used
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+  float lr[5];
+  float beta1, beta2, eps;
+  int32_t step; /* 1-based step count */
+  int32_t pad;
+} vbm_adam_opts;
+
+vbm_status vbm_adam_step(int64_t n, int64_t stride, float* raw, float* m, float* v, vbm_gaussians_c grads,
+                         vbm_gaussians act, const vbm_adam_opts* opts_host, int32_t* step_dev, void* stream);
+
+/* ------------------------------------------------------------------------------------------
+ * vbm_dvr_render -- supervision images by ray marching (Sec. 4.4: the method fine-tunes against
+ * volume-rendered images).  One ray per pixel centre, clipped to [-1,1]^3, a sample every
+ * step_vox voxels from the entry point, trilinear interpolation of the scalar field, the transfer
+ * function after interpolation, opacity corrected to the step (1 - (1 - a)^step_vox),
+ * front-to-back until T < 1e-4, background bg.  Output layout as vbm_render_fwd's image.
+ * ------------------------------------------------------------------------------------------ */
+vbm_status vbm_dvr_render(const float* vol, int32_t G, const vbm_tf* tf_host, const vbm_view* views_host,
+                          int32_t n_views, float step_vox, float* image, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VBM_H */

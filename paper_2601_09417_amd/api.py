@@ -1,0 +1,284 @@
+"""Torch-tensor front end of libvbm.  PyTorch supplies device memory and streams; every step of the
+fine-tuning path runs in the library's HIP kernels.
+
+Gaussian parameters live in one float32 tensor ``P`` of shape [14, stride] on the GPU with rows
+means 0-2, scales 3-5, quats 6-9 (w, x, y, z), opacity 10, rgb 11-13 (activated values); raw
+optimiser parameters use the same rows with log scales and logit opacity.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+ROWS = dict(means=slice(0, 3), scales=slice(3, 6), quats=slice(6, 10), opacity=slice(10, 11), rgb=slice(11, 14))
+N_ROWS = 14
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(device=None) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _require_cuda(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("libvbm operates on GPU tensors only")
+
+
+def gaussians_struct(P: torch.Tensor) -> L.vbm_gaussians:
+    """SoA pointer struct over a [14, stride] float32 tensor."""
+    assert P.dtype == torch.float32 and P.dim() == 2 and P.shape[0] == N_ROWS and P.is_contiguous()
+    base, stride = P.data_ptr(), P.shape[1]
+    row = lambda r: base + 4 * r * stride  # noqa: E731
+    return L.vbm_gaussians(row(0), row(3), row(6), row(10), row(11), stride)
+
+
+def pack_params(means, scales, quats, opacity, rgb, device="cuda") -> torch.Tensor:
+    arr = np.concatenate([np.asarray(means, np.float32), np.asarray(scales, np.float32), np.asarray(quats, np.float32),
+                          np.asarray(opacity, np.float32)[None], np.asarray(rgb, np.float32)], 0)
+    return torch.from_numpy(np.ascontiguousarray(arr)).to(device)
+
+
+def make_tf(xs, rgba) -> L.vbm_tf:
+    xs = np.asarray(xs, np.float32)
+    rgba = np.asarray(rgba, np.float32)
+    if xs.shape[0] > L.VBM_TF_MAX_POINTS:
+        raise ValueError("too many transfer-function control points")
+    t = L.vbm_tf()
+    t.n_points = xs.shape[0]
+    for i in range(xs.shape[0]):
+        t.x[i] = float(xs[i])
+        for c in range(4):
+            t.rgba[i][c] = float(rgba[i, c])
+    return t
+
+
+# ----------------------------------------------------------------------------- DWT + construction
+
+def dwt3d(vol: torch.Tensor, J: int, wavelet: str, tf=None) -> torch.Tensor:
+    """vol float32 [G, G, G] (with tf = (xs, rgba)) or [4, G^3] RGBA (tf None) -> coefficients [4, G^3]."""
+    lib = L.load()
+    _require_cuda(vol)
+    G = vol.shape[-1] if tf is not None else round(vol.shape[1] ** (1 / 3))
+    coeffs = torch.empty(4, G ** 3, dtype=torch.float32, device=vol.device)
+    ws = torch.empty(lib.vbm_dwt3d_workspace_size(G, J), dtype=torch.uint8, device=vol.device)
+    tfs = make_tf(*tf) if tf is not None else None
+    st = lib.vbm_dwt3d(vol.contiguous().data_ptr(), G, J, L.WAVELETS[wavelet], C.byref(tfs) if tfs else None,
+                       coeffs.data_ptr(), ws.data_ptr(), ws.numel(), _stream(vol.device))
+    L.check(st, "vbm_dwt3d")
+    return coeffs
+
+
+def bank_build(wavelet: str, J: int, tau: float = 0.1, lam: float = 1e-8):
+    """Returns (list of entry dicts, packed float32 numpy [7J+1, 12]) from the host FP64 bank build."""
+    lib = L.load()
+    n = lib.vbm_bank_size(J)
+    arr = (L.vbm_bank_entry * n)()
+    L.check(lib.vbm_bank_build(L.WAVELETS[wavelet], J, tau, lam, arr), "vbm_bank_build")
+    packed = np.zeros((n, L.VBM_BANK_FLOATS), np.float32)
+    L.check(lib.vbm_bank_pack(arr, n, packed.ctypes.data_as(C.POINTER(C.c_float))), "vbm_bank_pack")
+    entries = [dict(j=e.j, o=e.o, w=e.w, u=np.array(e.u[:]), sigma=np.array(e.sigma[:]), scale=np.array(e.scale[:]),
+                    quat=np.array(e.quat[:]), roi_size=e.roi_size) for e in arr]
+    return entries, packed
+
+
+def build_gaussians(coeffs: torch.Tensor, G: int, J: int, bank_packed, K: int, s_mode: str = "paper",
+                    delta: float = 0.5, opacity_min: float = 1e-3, opacity_max: float = 0.99, stride: int | None = None):
+    """Top-K + construction.  Returns (P [14, stride] activated parameters, kept int64 [K])."""
+    lib = L.load()
+    _require_cuda(coeffs)
+    dev = coeffs.device
+    bank = torch.as_tensor(np.ascontiguousarray(bank_packed, dtype=np.float32)).to(dev)
+    stride = stride or K
+    P = torch.zeros(N_ROWS, stride, dtype=torch.float32, device=dev)
+    kept = torch.empty(K, dtype=torch.int64, device=dev)
+    ws = torch.empty(lib.vbm_build_workspace_size(G, J), dtype=torch.uint8, device=dev)
+    opts = L.vbm_build_opts(0 if s_mode == "paper" else 1, delta, opacity_min, opacity_max)
+    st = lib.vbm_build_gaussians(coeffs.data_ptr(), G, J, bank.data_ptr(), K, C.byref(opts), gaussians_struct(P),
+                                 kept.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev))
+    L.check(st, "vbm_build_gaussians")
+    return P, kept
+
+
+# ----------------------------------------------------------------------------- rendering
+
+def make_view(cam, scene: int = 0) -> L.vbm_view:
+    v = L.vbm_view()
+    v.scene = scene
+    v.width, v.height = int(cam.width), int(cam.height)
+    v.fx, v.fy, v.cx, v.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    v.near_plane = float(cam.near)
+    vm = np.asarray(cam.viewmat, np.float32).reshape(-1)
+    for i in range(12):
+        v.viewmat[i] = float(vm[i])
+    for i in range(3):
+        v.bg[i] = float(cam.bg[i])
+    return v
+
+
+@dataclasses.dataclass
+class RenderPlan:
+    """A planned batch: host plan struct, device view table and the render workspace."""
+    plan: L.vbm_plan
+    views: object
+    table: torch.Tensor
+    ws: torch.Tensor
+    cams: list
+    view_scene: list
+    scene_offsets: np.ndarray
+
+    @property
+    def n_pixels(self) -> int:
+        return int(self.plan.n_pixels)
+
+    def view_dims(self) -> np.ndarray:
+        return np.array([[c.width, c.height] for c in self.cams], dtype=np.int32)
+
+    def pixel_offsets(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum([c.width * c.height for c in self.cams])]).astype(np.int64)
+
+    def region(self, name: str, dtype=torch.uint8) -> torch.Tensor:
+        r = L.REGION[name]
+        off, nb = int(self.plan.region_offset[r]), int(self.plan.region_bytes[r])
+        return self.ws[off:off + nb].view(dtype)
+
+
+def plan_batch(cams, scene_offsets=None, view_scene=None, tile: int = 16, sort_bits: int = 8,
+               pair_capacity: int = 1 << 20, mode: str = "batched", device="cuda") -> RenderPlan:
+    lib = L.load()
+    V = len(cams)
+    view_scene = list(view_scene) if view_scene is not None else [0] * V
+    scene_offsets = np.asarray(scene_offsets, dtype=np.int64)
+    S = scene_offsets.shape[0] - 1
+    views = (L.vbm_view * V)(*[make_view(c, s) for c, s in zip(cams, view_scene)])
+    sch = L.vbm_schedule(tile, sort_bits, int(pair_capacity), L.MODE_EXACT if mode == "exact" else L.MODE_BATCHED, 0)
+    plan = L.vbm_plan()
+    so = np.ascontiguousarray(scene_offsets)
+    L.check(lib.vbm_plan_make(views, V, so.ctypes.data_as(C.POINTER(C.c_int64)), S, C.byref(sch), C.byref(plan), None),
+            "vbm_plan_make")
+    host = np.zeros(plan.view_table_bytes, dtype=np.uint8)
+    L.check(lib.vbm_plan_make(views, V, so.ctypes.data_as(C.POINTER(C.c_int64)), S, C.byref(sch), C.byref(plan),
+                              host.ctypes.data), "vbm_plan_make")
+    table = torch.from_numpy(host).to(device)
+    ws = torch.empty(plan.ws_bytes, dtype=torch.uint8, device=device)
+    return RenderPlan(plan, views, table, ws, list(cams), view_scene, scene_offsets)
+
+
+@dataclasses.dataclass
+class FwdOut:
+    image: torch.Tensor      # float32 [3 * n_pixels] (per view [3][H][W], concatenated)
+    final_T: torch.Tensor    # float32 [n_pixels]
+    n_contrib: torch.Tensor  # int32 [n_pixels]
+    status: torch.Tensor     # int32 [4]: overflow, pairs, visible items
+
+
+def render_fwd(rp: RenderPlan, P: torch.Tensor, out: FwdOut | None = None) -> FwdOut:
+    lib = L.load()
+    _require_cuda(P)
+    dev = P.device
+    if out is None:
+        out = FwdOut(torch.empty(3 * rp.n_pixels, dtype=torch.float32, device=dev),
+                     torch.empty(rp.n_pixels, dtype=torch.float32, device=dev),
+                     torch.empty(rp.n_pixels, dtype=torch.int32, device=dev),
+                     torch.zeros(4, dtype=torch.int32, device=dev))
+    st = lib.vbm_render_fwd(C.byref(rp.plan), rp.table.data_ptr(), gaussians_struct(P), out.image.data_ptr(),
+                            out.final_T.data_ptr(), out.n_contrib.data_ptr(), out.status.data_ptr(), rp.ws.data_ptr(),
+                            rp.ws.numel(), _stream(dev))
+    L.check(st, "vbm_render_fwd")
+    return out
+
+
+def render_bwd(rp: RenderPlan, P: torch.Tensor, dL_dimg: torch.Tensor, fwd: FwdOut, grads: torch.Tensor | None = None,
+               accumulate: bool = False) -> torch.Tensor:
+    lib = L.load()
+    _require_cuda(P, dL_dimg)
+    if grads is None:
+        grads = torch.zeros_like(P)
+    st = lib.vbm_render_bwd(C.byref(rp.plan), rp.table.data_ptr(), gaussians_struct(P), dL_dimg.data_ptr(),
+                            fwd.final_T.data_ptr(), fwd.n_contrib.data_ptr(), gaussians_struct(grads),
+                            1 if accumulate else 0, rp.ws.data_ptr(), rp.ws.numel(), _stream(P.device))
+    L.check(st, "vbm_render_bwd")
+    return grads
+
+
+def split_views(flat: torch.Tensor, cams, channels: int = 3) -> list:
+    """Concatenated per-view planar buffer -> list of [channels, H, W] views."""
+    out, off = [], 0
+    for c in cams:
+        n = channels * c.width * c.height
+        out.append(flat[off:off + n].view(channels, c.height, c.width) if channels > 1 else
+                   flat[off:off + n].view(c.height, c.width))
+        off += n
+    return out
+
+
+# ----------------------------------------------------------------------------- loss, optimiser, DVR
+
+class ImageLoss:
+    """Preallocated loss workspace for a fixed set of view sizes."""
+
+    def __init__(self, view_dims, kind: str = "l1", lam: float = 0.2, device="cuda"):
+        lib = L.load()
+        self.dims = np.ascontiguousarray(np.asarray(view_dims, dtype=np.int32).reshape(-1, 2))
+        self.kind = 0 if kind == "l1" else 1
+        self.lam = float(lam)
+        nb = lib.vbm_image_loss_workspace_size(self.dims.ctypes.data_as(C.POINTER(C.c_int32)), self.dims.shape[0],
+                                               self.kind)
+        self.ws = torch.empty(max(int(nb), 1), dtype=torch.uint8, device=device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+
+    def __call__(self, image: torch.Tensor, target: torch.Tensor, grad: torch.Tensor) -> torch.Tensor:
+        lib = L.load()
+        st = lib.vbm_image_loss(image.data_ptr(), target.data_ptr(), self.dims.ctypes.data_as(C.POINTER(C.c_int32)),
+                                self.dims.shape[0], self.kind, self.lam, grad.data_ptr(), self.loss.data_ptr(),
+                                self.ws.data_ptr(), self.ws.numel(), _stream(image.device))
+        L.check(st, "vbm_image_loss")
+        return self.loss
+
+
+LR_DEFAULT = (1e-3, 5e-3, 1e-3, 5e-3, 2.5e-3)  # means, log scales, quats, logit opacity, rgb
+
+
+def raw_from_activated(P: torch.Tensor) -> torch.Tensor:
+    """Raw optimiser parameters (log scales, logit opacity) from activated ones (setup, not on the hot path)."""
+    raw = P.clone()
+    raw[ROWS["scales"]] = torch.log(P[ROWS["scales"]])
+    op = P[ROWS["opacity"]].clamp(1e-6, 1 - 1e-6)
+    raw[ROWS["opacity"]] = torch.log(op / (1 - op))
+    return raw
+
+
+def adam_step(raw, m, v, grads, act, lr=LR_DEFAULT, step: int = 1, step_dev: torch.Tensor | None = None,
+              betas=(0.9, 0.999), eps=1e-15, n: int | None = None):
+    lib = L.load()
+    o = L.vbm_adam_opts()
+    for k in range(5):
+        o.lr[k] = float(lr[k])
+    o.beta1, o.beta2, o.eps, o.step = betas[0], betas[1], eps, int(step)
+    n = raw.shape[1] if n is None else n
+    st = lib.vbm_adam_step(n, raw.shape[1], raw.data_ptr(), m.data_ptr(), v.data_ptr(), gaussians_struct(grads),
+                           gaussians_struct(act), C.byref(o), _ptr(step_dev), _stream(raw.device))
+    L.check(st, "vbm_adam_step")
+
+
+def dvr_render(vol: torch.Tensor, tf, cams, step_vox: float = 0.5) -> torch.Tensor:
+    """Ray-marched images of vol [G, G, G] for each camera, concatenated planar [3][H][W] per view."""
+    lib = L.load()
+    _require_cuda(vol)
+    G = vol.shape[0]
+    views = (L.vbm_view * len(cams))(*[make_view(c) for c in cams])
+    n = sum(3 * c.width * c.height for c in cams)
+    out = torch.empty(n, dtype=torch.float32, device=vol.device)
+    t = make_tf(*tf)
+    st = lib.vbm_dvr_render(vol.contiguous().data_ptr(), G, C.byref(t), views, len(cams), step_vox, out.data_ptr(),
+                            _stream(vol.device))
+    L.check(st, "vbm_dvr_render")
+    return out

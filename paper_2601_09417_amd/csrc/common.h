@@ -1,0 +1,96 @@
+// Internal declarations shared by the libvbm translation units (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/vbm.h"
+
+namespace vbm {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...);
+vbm_status hip_check(hipError_t e, const char* what);
+#define VBM_LAUNCH_CHECK(name)                                         \
+  do {                                                                 \
+    hipError_t _e = hipGetLastError();                                 \
+    if (_e != hipSuccess) return ::vbm::hip_check(_e, name);           \
+  } while (0)
+#define VBM_TRY(expr)                                                  \
+  do {                                                                 \
+    vbm_status _s = (expr);                                            \
+    if (_s != VBM_OK) return _s;                                       \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Bump allocator over a caller-provided workspace (sizing pass when base == nullptr).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    off = align_up(off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// ------------------------------------------------------------------ device view table
+// One record per view, written by vbm_plan_make on the host and read by every render kernel.
+struct DevView {
+  float R[9];            // world->camera rotation, row-major
+  float t[3];
+  float fx, fy, cx, cy;
+  float near_plane;
+  float bg[3];
+  int32_t width, height, tiles_x, tiles_y;
+  int32_t item_offset;   // first item of this view
+  int32_t gauss_offset;  // first Gaussian of the view's scene
+  int32_t n_gauss;       // Gaussians in the view's scene
+  int32_t tile_offset;   // first global tile of this view
+  int32_t pixel_offset;  // first pixel of this view
+  int32_t scene;
+  int32_t pad[2];
+};
+static_assert(sizeof(DevView) % 16 == 0, "DevView must stay 16-byte aligned");
+
+// Scene table appended after the views in the device view table.
+struct DevScene {
+  int32_t gauss_offset, n_gauss;
+};
+
+// ------------------------------------------------------------------ wave helpers
+__device__ __forceinline__ uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+// Number of set bits of `mask` in lanes below the calling lane.
+__device__ __forceinline__ uint32_t popc_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+// ------------------------------------------------------------------ scan / sort primitives (scan_sort.hip)
+// Exclusive prefix sum of n u32 values (n read from *n_dev when non-null, else n_max), with the
+// total written to *total_dev.  Scratch from scan_scratch_bytes(n_max).
+size_t scan_scratch_bytes(int64_t n_max);
+vbm_status scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n_max, const uint32_t* n_dev,
+                              uint32_t* total_dev, void* scratch, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs over key bits [0, end_bit), digit width 4..8 bits.
+// Passes ping-pong between (k0, v0) and (k1, v1); returns in *result_in_k1 whether the sorted data
+// ends in the second buffer.  The element count is read from *n_dev (<= n_max) when non-null.
+size_t radix_scratch_bytes(int64_t n_max, int digit_bits);
+template <class K>
+vbm_status radix_sort_pairs(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t n_max, const uint32_t* n_dev,
+                            int end_bit, int digit_bits, void* scratch, hipStream_t s, bool* result_in_k1);
+
+// Device fill (used instead of memset nodes so every step stays capturable).
+vbm_status fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
+
+}  // namespace vbm

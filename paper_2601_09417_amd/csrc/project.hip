@@ -1,0 +1,377 @@
+// EWA projection, binning and the projection backward of the fine-tuning renderer (Sec. 4.4
+// fine-tunes with the 3DGS rasteriser the paper cites; Sec. 3 defines the Gaussian set).
+//
+// Every decision that fixes the pair lists -- camera depth, culling, the 2D covariance, the radius
+// and the tile rectangle -- is computed in float32 in one fixed order with contraction disabled and
+// correctly rounded division and square root, so that the lists are reproducible bit for bit by
+// any implementation following the same order.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+#pragma clang fp contract(off)
+
+namespace vbm {
+
+struct ProjResult {
+  float depth;
+  float px, py;
+  float ca, cb, cc;
+  uint32_t x0, y0, x1, y1;
+  bool visible;
+};
+
+__device__ __forceinline__ void rot_from_quat(float qw, float qx, float qy, float qz, float Rq[3][3], float qn[4]) {
+  const float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+  const float nq = __fsqrt_rn(n2);
+  const float w = __fdiv_rn(qw, nq), x = __fdiv_rn(qx, nq), y = __fdiv_rn(qy, nq), z = __fdiv_rn(qz, nq);
+  qn[0] = w;
+  qn[1] = x;
+  qn[2] = y;
+  qn[3] = z;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  const float xy = x * y, xz = x * z, yz = y * z;
+  const float wx = w * x, wy = w * y, wz = w * z;
+  Rq[0][0] = 1.0f - 2.0f * (yy + zz);
+  Rq[0][1] = 2.0f * (xy - wz);
+  Rq[0][2] = 2.0f * (xz + wy);
+  Rq[1][0] = 2.0f * (xy + wz);
+  Rq[1][1] = 1.0f - 2.0f * (xx + zz);
+  Rq[1][2] = 2.0f * (yz - wx);
+  Rq[2][0] = 2.0f * (xz - wy);
+  Rq[2][1] = 2.0f * (yz + wx);
+  Rq[2][2] = 1.0f - 2.0f * (xx + yy);
+}
+
+__device__ __forceinline__ ProjResult project_one(const DevView& v, int tile, float mx, float my, float mz, float sx,
+                                                  float sy, float sz, float qw, float qx, float qy, float qz) {
+  ProjResult o;
+  const float* R = v.R;
+  const float Xc = ((R[0] * mx + R[1] * my) + R[2] * mz) + v.t[0];
+  const float Yc = ((R[3] * mx + R[4] * my) + R[5] * mz) + v.t[1];
+  const float Zc = ((R[6] * mx + R[7] * my) + R[8] * mz) + v.t[2];
+  bool vis = Zc > v.near_plane;
+  float Rq[3][3], qn[4];
+  rot_from_quat(qw, qx, qy, qz, Rq, qn);
+  const float s[3] = {sx, sy, sz};
+  float M[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) M[i][k] = Rq[i][k] * s[k];
+  const float limx = 1.3f * __fdiv_rn(0.5f * static_cast<float>(v.width), v.fx);
+  const float limy = 1.3f * __fdiv_rn(0.5f * static_cast<float>(v.height), v.fy);
+  const float txz = __fdiv_rn(Xc, Zc);
+  const float tyz = __fdiv_rn(Yc, Zc);
+  const float Xt = fminf(limx, fmaxf(-limx, txz)) * Zc;
+  const float Yt = fminf(limy, fmaxf(-limy, tyz)) * Zc;
+  const float z2 = Zc * Zc;
+  const float J00 = __fdiv_rn(v.fx, Zc);
+  const float J02 = -__fdiv_rn(v.fx * Xt, z2);
+  const float J11 = __fdiv_rn(v.fy, Zc);
+  const float J12 = -__fdiv_rn(v.fy * Yt, z2);
+  float A0[3], A1[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    A0[k] = J00 * R[k] + J02 * R[6 + k];
+    A1[k] = J11 * R[3 + k] + J12 * R[6 + k];
+  }
+  float V0[3], V1[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    V0[k] = (A0[0] * M[0][k] + A0[1] * M[1][k]) + A0[2] * M[2][k];
+    V1[k] = (A1[0] * M[0][k] + A1[1] * M[1][k]) + A1[2] * M[2][k];
+  }
+  const float a = ((V0[0] * V0[0] + V0[1] * V0[1]) + V0[2] * V0[2]) + 0.3f;
+  const float b = (V0[0] * V1[0] + V0[1] * V1[1]) + V0[2] * V1[2];
+  const float c = ((V1[0] * V1[0] + V1[1] * V1[1]) + V1[2] * V1[2]) + 0.3f;
+  const float det = a * c - b * b;
+  vis = vis && det > 0.0f;
+  const float mid = 0.5f * (a + c);
+  const float disc = fmaxf(0.1f, mid * mid - det);
+  const float lam = mid + __fsqrt_rn(disc);
+  const float r = ceilf(3.0f * __fsqrt_rn(lam));
+  const float px = v.fx * txz + v.cx;
+  const float py = v.fy * tyz + v.cy;
+  const float Tf = static_cast<float>(tile);
+  const float fx0 = fminf(fmaxf(floorf(__fdiv_rn(px - r, Tf)), 0.0f), static_cast<float>(v.tiles_x));
+  const float fx1 = fminf(fmaxf(floorf(__fdiv_rn(px + r, Tf)) + 1.0f, 0.0f), static_cast<float>(v.tiles_x));
+  const float fy0 = fminf(fmaxf(floorf(__fdiv_rn(py - r, Tf)), 0.0f), static_cast<float>(v.tiles_y));
+  const float fy1 = fminf(fmaxf(floorf(__fdiv_rn(py + r, Tf)) + 1.0f, 0.0f), static_cast<float>(v.tiles_y));
+  vis = vis && isfinite(px) && isfinite(py) && isfinite(r);
+  o.x0 = vis ? static_cast<uint32_t>(fx0) : 0u;
+  o.x1 = vis ? static_cast<uint32_t>(fx1) : 0u;
+  o.y0 = vis ? static_cast<uint32_t>(fy0) : 0u;
+  o.y1 = vis ? static_cast<uint32_t>(fy1) : 0u;
+  o.visible = vis && (o.x1 > o.x0) && (o.y1 > o.y0);
+  o.depth = Zc;
+  o.px = px;
+  o.py = py;
+  o.ca = __fdiv_rn(c, det);
+  o.cb = -__fdiv_rn(b, det);
+  o.cc = __fdiv_rn(a, det);
+  return o;
+}
+
+// grid: x over Gaussians of the view's scene, y over views.  Writes the per-item records and the
+// visibility flag consumed by the compaction scan.
+__global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ views, int tile, vbm_gaussians_c g,
+                                                 float* __restrict__ depth, uint32_t* __restrict__ rect,
+                                                 uint32_t* __restrict__ ntiles, float4* __restrict__ rec,
+                                                 float* __restrict__ blue, uint32_t* __restrict__ vis_flag,
+                                                 int64_t n_items) {
+  const DevView& v = views[blockIdx.y];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= v.n_gauss) return;
+  const int64_t gi = v.gauss_offset + i;
+  const int64_t item = v.item_offset + i;
+  const int64_t S = g.stride;
+  const ProjResult p = project_one(v, tile, g.means[gi], g.means[S + gi], g.means[2 * S + gi], g.scales[gi],
+                                   g.scales[S + gi], g.scales[2 * S + gi], g.quats[gi], g.quats[S + gi],
+                                   g.quats[2 * S + gi], g.quats[3 * S + gi]);
+  const uint32_t nt = p.visible ? (p.x1 - p.x0) * (p.y1 - p.y0) : 0u;
+  depth[item] = p.visible ? p.depth : 0.0f;
+  rect[item] = p.x0 | (p.x1 << 16);
+  rect[n_items + item] = p.y0 | (p.y1 << 16);
+  ntiles[item] = nt;
+  vis_flag[item] = nt ? 1u : 0u;
+  rec[2 * item] = make_float4(p.px, p.py, p.ca, p.cb);
+  rec[2 * item + 1] = make_float4(p.cc, g.opacity[gi], g.rgb[gi], g.rgb[S + gi]);
+  blue[item] = g.rgb[2 * S + gi];
+}
+
+// Stable compaction of visible items into (view << 32 | depth bits, item) pairs.
+__global__ __launch_bounds__(256) void k_compact_visible(const DevView* __restrict__ views,
+                                                         const uint32_t* __restrict__ ntiles,
+                                                         const float* __restrict__ depth,
+                                                         const uint32_t* __restrict__ pos,
+                                                         uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const DevView& v = views[blockIdx.y];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= v.n_gauss) return;
+  const int64_t item = v.item_offset + i;
+  if (ntiles[item] == 0) return;
+  const uint32_t p = pos[item];
+  keys[p] = (static_cast<uint64_t>(blockIdx.y) << 32) | __float_as_uint(depth[item]);
+  vals[p] = static_cast<uint32_t>(item);
+}
+
+__global__ __launch_bounds__(256) void k_gather_ntiles(const uint32_t* __restrict__ vals,
+                                                       const uint32_t* __restrict__ ntiles,
+                                                       const uint32_t* __restrict__ counters, int64_t n_max,
+                                                       uint32_t* __restrict__ out) {
+  const int64_t n = min(static_cast<int64_t>(counters[0]), n_max);
+  for (int64_t p = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; p < n;
+       p += static_cast<int64_t>(gridDim.x) * 256)
+    out[p] = ntiles[vals[p]];
+}
+
+// Writes each visible item's tiles in (view, depth, item) order.  Pairs past the capacity are
+// dropped and flagged.
+__global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views, const uint64_t* __restrict__ keys,
+                                              const uint32_t* __restrict__ vals, const uint32_t* __restrict__ offs,
+                                              const uint32_t* __restrict__ rect, int64_t n_items,
+                                              uint32_t* __restrict__ counters, int64_t n_max, int64_t capacity,
+                                              uint32_t* __restrict__ pair_tile, uint32_t* __restrict__ pair_item) {
+  const int64_t n = min(static_cast<int64_t>(counters[0]), n_max);
+  for (int64_t p = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; p < n;
+       p += static_cast<int64_t>(gridDim.x) * 256) {
+    const uint32_t item = vals[p];
+    const DevView& v = views[keys[p] >> 32];
+    const uint32_t rx = rect[item], ry = rect[n_items + item];
+    const uint32_t x0 = rx & 0xFFFFu, x1 = rx >> 16, y0 = ry & 0xFFFFu, y1 = ry >> 16;
+    int64_t o = offs[p];
+    bool over = false;
+    for (uint32_t ty = y0; ty < y1; ++ty)
+      for (uint32_t tx = x0; tx < x1; ++tx) {
+        if (o < capacity) {
+          pair_tile[o] = static_cast<uint32_t>(v.tile_offset) + ty * static_cast<uint32_t>(v.tiles_x) + tx;
+          pair_item[o] = item;
+        } else {
+          over = true;
+        }
+        ++o;
+      }
+    if (over) counters[2] = 1u;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ pair_tile,
+                                                const uint32_t* __restrict__ counters, int64_t capacity,
+                                                uint2* __restrict__ ranges) {
+  const int64_t P = min(static_cast<int64_t>(counters[1]), capacity);
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < P;
+       i += static_cast<int64_t>(gridDim.x) * 256) {
+    const uint32_t t = pair_tile[i];
+    if (i == 0 || pair_tile[i - 1] != t) ranges[t].x = static_cast<uint32_t>(i);
+    if (i == P - 1 || pair_tile[i + 1] != t) ranges[t].y = static_cast<uint32_t>(i + 1);
+  }
+}
+
+__global__ void k_status(const uint32_t* __restrict__ counters, int32_t* __restrict__ status) {
+  if (threadIdx.x == 0) {
+    status[0] = static_cast<int32_t>(counters[2]);
+    status[1] = static_cast<int32_t>(counters[1]);
+    status[2] = static_cast<int32_t>(counters[0]);
+    status[3] = 0;
+  }
+}
+
+// ------------------------------------------------------------------ projection backward
+// Chain rule from the per-item 2D gradients (mean2d, conic, opacity, rgb) to the activated 3D
+// parameters, summed over the views that show the Gaussian's scene (deterministic: one thread per
+// Gaussian walks its views in order).
+__device__ __forceinline__ void project_bwd_one(const DevView& v, const float m[3], const float s[3], const float q[4],
+                                                const float g2[5], float dm[3], float ds[3], float dq[4]) {
+  const float* R = v.R;
+  const float X = ((R[0] * m[0] + R[1] * m[1]) + R[2] * m[2]) + v.t[0];
+  const float Y = ((R[3] * m[0] + R[4] * m[1]) + R[5] * m[2]) + v.t[1];
+  const float Z = ((R[6] * m[0] + R[7] * m[1]) + R[8] * m[2]) + v.t[2];
+  const float fx = v.fx, fy = v.fy;
+  const float limx = 1.3f * (0.5f * static_cast<float>(v.width) / fx);
+  const float limy = 1.3f * (0.5f * static_cast<float>(v.height) / fy);
+  const float txz = X / Z, tyz = Y / Z;
+  const bool clx = txz < -limx || txz > limx;
+  const bool cly = tyz < -limy || tyz > limy;
+  const float cx_ = fminf(limx, fmaxf(-limx, txz));
+  const float cy_ = fminf(limy, fmaxf(-limy, tyz));
+  const float z2 = Z * Z, z3 = z2 * Z;
+  const float J00 = fx / Z, J02 = -fx * cx_ / Z, J11 = fy / Z, J12 = -fy * cy_ / Z;
+  float A[2][3];
+  for (int k = 0; k < 3; ++k) {
+    A[0][k] = J00 * R[k] + J02 * R[6 + k];
+    A[1][k] = J11 * R[3 + k] + J12 * R[6 + k];
+  }
+  float Rq[3][3], qn[4];
+  rot_from_quat(q[0], q[1], q[2], q[3], Rq, qn);
+  float M[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) M[i][k] = Rq[i][k] * s[k];
+  float V[2][3];
+  for (int a = 0; a < 2; ++a)
+    for (int k = 0; k < 3; ++k) V[a][k] = A[a][0] * M[0][k] + A[a][1] * M[1][k] + A[a][2] * M[2][k];
+  const float a = V[0][0] * V[0][0] + V[0][1] * V[0][1] + V[0][2] * V[0][2] + 0.3f;
+  const float b = V[0][0] * V[1][0] + V[0][1] * V[1][1] + V[0][2] * V[1][2];
+  const float c = V[1][0] * V[1][0] + V[1][1] * V[1][1] + V[1][2] * V[1][2] + 0.3f;
+  const float det = a * c - b * b;
+  const float id2 = 1.0f / (det * det);
+  const float gA = g2[2], gB = g2[3], gC = g2[4];
+  // conic = (c, -b, a) / det
+  const float ga = (-c * c * gA + b * c * gB - b * b * gC) * id2;
+  const float gb = (2.0f * b * c * gA - (a * c + b * b) * gB + 2.0f * a * b * gC) * id2;
+  const float gc = (-b * b * gA + a * b * gB - a * a * gC) * id2;
+  // Sigma2 = V V^T + 0.3 I
+  float dV[2][3];
+  for (int k = 0; k < 3; ++k) {
+    dV[0][k] = 2.0f * ga * V[0][k] + gb * V[1][k];
+    dV[1][k] = gb * V[0][k] + 2.0f * gc * V[1][k];
+  }
+  // V = A M
+  float dM[3][3], dA[2][3];
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) dM[i][k] = A[0][i] * dV[0][k] + A[1][i] * dV[1][k];
+  for (int a2 = 0; a2 < 2; ++a2)
+    for (int i = 0; i < 3; ++i) dA[a2][i] = dV[a2][0] * M[i][0] + dV[a2][1] * M[i][1] + dV[a2][2] * M[i][2];
+  // A = J R_view
+  const float dJ00 = dA[0][0] * R[0] + dA[0][1] * R[1] + dA[0][2] * R[2];
+  const float dJ02 = dA[0][0] * R[6] + dA[0][1] * R[7] + dA[0][2] * R[8];
+  const float dJ11 = dA[1][0] * R[3] + dA[1][1] * R[4] + dA[1][2] * R[5];
+  const float dJ12 = dA[1][0] * R[6] + dA[1][1] * R[7] + dA[1][2] * R[8];
+  float dX = 0.0f, dY = 0.0f, dZ = 0.0f;
+  dZ += -fx / z2 * dJ00 - fy / z2 * dJ11;
+  if (!clx) {
+    dX += -fx / z2 * dJ02;
+    dZ += 2.0f * fx * X / z3 * dJ02;
+  } else {
+    dZ += fx * cx_ / z2 * dJ02;
+  }
+  if (!cly) {
+    dY += -fy / z2 * dJ12;
+    dZ += 2.0f * fy * Y / z3 * dJ12;
+  } else {
+    dZ += fy * cy_ / z2 * dJ12;
+  }
+  // mean2d = (fx X/Z + cx, fy Y/Z + cy)
+  dX += fx / Z * g2[0];
+  dZ += -fx * X / z2 * g2[0];
+  dY += fy / Z * g2[1];
+  dZ += -fy * Y / z2 * g2[1];
+  dm[0] = R[0] * dX + R[3] * dY + R[6] * dZ;
+  dm[1] = R[1] * dX + R[4] * dY + R[7] * dZ;
+  dm[2] = R[2] * dX + R[5] * dY + R[8] * dZ;
+  // M = R_q diag(s)
+  float dR[3][3];
+  for (int k = 0; k < 3; ++k) {
+    ds[k] = Rq[0][k] * dM[0][k] + Rq[1][k] * dM[1][k] + Rq[2][k] * dM[2][k];
+    for (int i = 0; i < 3; ++i) dR[i][k] = dM[i][k] * s[k];
+  }
+  const float w = qn[0], x = qn[1], y = qn[2], z = qn[3];
+  float dqn[4];
+  dqn[0] = 2.0f * (-z * dR[0][1] + y * dR[0][2] + z * dR[1][0] - x * dR[1][2] - y * dR[2][0] + x * dR[2][1]);
+  dqn[1] = 2.0f * (y * dR[0][1] + z * dR[0][2] + y * dR[1][0] - 2.0f * x * dR[1][1] - w * dR[1][2] + z * dR[2][0] +
+                   w * dR[2][1] - 2.0f * x * dR[2][2]);
+  dqn[2] = 2.0f * (-2.0f * y * dR[0][0] + x * dR[0][1] + w * dR[0][2] + x * dR[1][0] + z * dR[1][2] - w * dR[2][0] +
+                   z * dR[2][1] - 2.0f * y * dR[2][2]);
+  dqn[3] = 2.0f * (-2.0f * z * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] - 2.0f * z * dR[1][1] +
+                   y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
+  const float nq = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  const float dot = w * dqn[0] + x * dqn[1] + y * dqn[2] + z * dqn[3];
+  for (int i = 0; i < 4; ++i) dq[i] = (dqn[i] - qn[i] * dot) / nq;
+}
+
+__global__ __launch_bounds__(256) void k_project_bwd(const DevView* __restrict__ views, int n_views,
+                                                     const DevScene* __restrict__ scenes, int n_scenes,
+                                                     vbm_gaussians_c g, const float* __restrict__ grad2d,
+                                                     int64_t n_items, const uint32_t* __restrict__ ntiles,
+                                                     vbm_gaussians grads, int accumulate, int64_t n_total) {
+  const int64_t gi = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (gi >= n_total) return;
+  int sc = 0;
+  for (int s = 1; s < n_scenes; ++s)
+    if (scenes[s].gauss_offset <= gi) sc = s;
+  const int64_t S = g.stride;
+  const float m[3] = {g.means[gi], g.means[S + gi], g.means[2 * S + gi]};
+  const float sc3[3] = {g.scales[gi], g.scales[S + gi], g.scales[2 * S + gi]};
+  const float q[4] = {g.quats[gi], g.quats[S + gi], g.quats[2 * S + gi], g.quats[3 * S + gi]};
+  float am[3] = {0, 0, 0}, as[3] = {0, 0, 0}, aq[4] = {0, 0, 0, 0}, ao = 0.0f, ac[3] = {0, 0, 0};
+  for (int vi = 0; vi < n_views; ++vi) {
+    const DevView& v = views[vi];
+    if (v.scene != sc) continue;
+    const int64_t item = v.item_offset + (gi - v.gauss_offset);
+    if (ntiles[item] == 0) continue;
+    float g2[9];
+    for (int k = 0; k < 9; ++k) g2[k] = grad2d[k * n_items + item];
+    ao += g2[5];
+    ac[0] += g2[6];
+    ac[1] += g2[7];
+    ac[2] += g2[8];
+    if (g2[0] == 0.0f && g2[1] == 0.0f && g2[2] == 0.0f && g2[3] == 0.0f && g2[4] == 0.0f) continue;
+    float dm[3], ds[3], dq[4];
+    project_bwd_one(v, m, sc3, q, g2, dm, ds, dq);
+    for (int k = 0; k < 3; ++k) {
+      am[k] += dm[k];
+      as[k] += ds[k];
+    }
+    for (int k = 0; k < 4; ++k) aq[k] += dq[k];
+  }
+  const int64_t GS = grads.stride;
+  if (accumulate) {
+    for (int k = 0; k < 3; ++k) {
+      grads.means[k * GS + gi] += am[k];
+      grads.scales[k * GS + gi] += as[k];
+      grads.rgb[k * GS + gi] += ac[k];
+    }
+    for (int k = 0; k < 4; ++k) grads.quats[k * GS + gi] += aq[k];
+    grads.opacity[gi] += ao;
+  } else {
+    for (int k = 0; k < 3; ++k) {
+      grads.means[k * GS + gi] = am[k];
+      grads.scales[k * GS + gi] = as[k];
+      grads.rgb[k * GS + gi] = ac[k];
+    }
+    for (int k = 0; k < 4; ++k) grads.quats[k * GS + gi] = aq[k];
+    grads.opacity[gi] = ao;
+  }
+}
+
+}  // namespace vbm

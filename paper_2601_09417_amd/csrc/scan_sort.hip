@@ -1,0 +1,267 @@
+// Device-wide exclusive scan and stable LSD radix sort (gfx950, wave64, 256-thread blocks).
+//
+// Scan: reduce -> single-workgroup scan of the block sums -> per-block scan with the block
+// offset added.  Sort: per pass a digit histogram per 4096-key tile, an exclusive scan of the
+// digit-major histogram (digit * n_tiles + tile), then a stable scatter that ranks equal digits
+// inside each wave with ballots (a lane's rank = set bits of its digit-match mask below it) and
+// across the block's waves and rounds through LDS counters.
+#include <hip/hip_runtime.h>
+
+#include "block_scan.h"
+#include "common.h"
+
+namespace vbm {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 16;
+constexpr int kChunk = kThreads * kItems;  // elements per block
+constexpr int kWaves = kThreads / 64;
+
+__device__ __forceinline__ int64_t active_count(int64_t n_max, const uint32_t* n_dev) {
+  if (!n_dev) return n_max;
+  int64_t n = static_cast<int64_t>(*n_dev);
+  return n < n_max ? n : n_max;
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const T* __restrict__ in, T* __restrict__ block_sums,
+                                                          int64_t n_max, const uint32_t* n_dev) {
+  const int64_t n = active_count(n_max, n_dev);
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kChunk;
+  T acc = 0;
+  if (base < n) {
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      int64_t i = base + r * kThreads + threadIdx.x;
+      if (i < n) acc += in[i];
+    }
+  }
+  T tot;
+  block_excl_scan(acc, &tot);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+// One workgroup scans all block sums in place (exclusive), carrying across 4096-entry chunks.
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_scan_top(T* __restrict__ sums, int64_t nb, T* __restrict__ total) {
+  T carry = 0;
+  for (int64_t base = 0; base < nb; base += kChunk) {
+    T items[kItems];
+    T acc = 0;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      int64_t i = base + static_cast<int64_t>(threadIdx.x) * kItems + r;
+      items[r] = i < nb ? sums[i] : T(0);
+      acc += items[r];
+    }
+    T tot;
+    T ex = block_excl_scan(acc, &tot) + carry;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      int64_t i = base + static_cast<int64_t>(threadIdx.x) * kItems + r;
+      if (i < nb) sums[i] = ex;
+      ex += items[r];
+    }
+    carry += tot;
+  }
+  if (total && threadIdx.x == 0) *total = carry;
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_scan_down(const T* __restrict__ in, T* __restrict__ out,
+                                                        const T* __restrict__ block_offsets, int64_t n_max,
+                                                        const uint32_t* n_dev) {
+  const int64_t n = active_count(n_max, n_dev);
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kChunk;
+  if (base >= n) return;  // uniform per block
+  T items[kItems];
+  T acc = 0;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    int64_t i = base + static_cast<int64_t>(threadIdx.x) * kItems + r;
+    items[r] = i < n ? in[i] : T(0);
+    acc += items[r];
+  }
+  T tot;
+  T ex = block_excl_scan(acc, &tot) + block_offsets[blockIdx.x];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    int64_t i = base + static_cast<int64_t>(threadIdx.x) * kItems + r;
+    if (i < n) out[i] = ex;
+    ex += items[r];
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+// ------------------------------------------------------------------ radix sort
+template <class K>
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const K* __restrict__ keys, uint32_t* __restrict__ hist,
+                                                         int64_t n_max, const uint32_t* n_dev, int shift,
+                                                         int bits, int64_t n_blocks) {
+  __shared__ uint32_t s_hist[256];
+  const int radix = 1 << bits;
+  for (int d = threadIdx.x; d < radix; d += kThreads) s_hist[d] = 0;
+  __syncthreads();
+  const int64_t n = active_count(n_max, n_dev);
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kChunk;
+  const uint32_t mask = static_cast<uint32_t>(radix - 1);
+  if (base < n) {
+#pragma unroll 4
+    for (int r = 0; r < kItems; ++r) {
+      int64_t i = base + r * kThreads + threadIdx.x;
+      if (i < n) {
+        uint32_t d = static_cast<uint32_t>(keys[i] >> shift) & mask;
+        atomicAdd(&s_hist[d], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < radix; d += kThreads) hist[static_cast<int64_t>(d) * n_blocks + blockIdx.x] = s_hist[d];
+}
+
+template <class K>
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                            K* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                            const uint32_t* __restrict__ offsets, int64_t n_max,
+                                                            const uint32_t* n_dev, int shift, int bits,
+                                                            int64_t n_blocks) {
+  __shared__ uint32_t s_run[256];
+  __shared__ uint32_t s_wave_cnt[kWaves][256];
+  const int64_t n = active_count(n_max, n_dev);
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kChunk;
+  if (base >= n) return;  // uniform per block
+  const int radix = 1 << bits;
+  const uint32_t mask = static_cast<uint32_t>(radix - 1);
+  const int w = threadIdx.x >> 6;
+  for (int d = threadIdx.x; d < radix; d += kThreads) s_run[d] = offsets[static_cast<int64_t>(d) * n_blocks + blockIdx.x];
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t i = base + r * kThreads + threadIdx.x;
+    const bool valid = i < n;
+    K key = valid ? kin[i] : K(0);
+    uint32_t val = valid ? vin[i] : 0u;
+    const uint32_t d = static_cast<uint32_t>(key >> shift) & mask;
+    for (int x = threadIdx.x; x < kWaves * radix; x += kThreads) (&s_wave_cnt[0][0])[(x / radix) * 256 + (x % radix)] = 0;
+    __syncthreads();
+    uint64_t m = __ballot(valid);
+    for (int b = 0; b < bits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(valid && bit);
+      m &= bit ? bb : ~bb;
+    }
+    const uint32_t rank = popc_below(m);
+    if (valid && rank == 0) s_wave_cnt[w][d] = static_cast<uint32_t>(__popcll(m));
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = s_run[d] + rank;
+      for (int ww = 0; ww < w; ++ww) pos += s_wave_cnt[ww][d];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    for (int dd = threadIdx.x; dd < radix; dd += kThreads) {
+      uint32_t add = 0;
+#pragma unroll
+      for (int ww = 0; ww < kWaves; ++ww) add += s_wave_cnt[ww][dd];
+      s_run[dd] += add;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+size_t scan_scratch_bytes(int64_t n_max) {
+  int64_t nb = ceil_div(n_max > 0 ? n_max : 1, kChunk);
+  return align_up(static_cast<size_t>(nb) * 8, 256) + 256;
+}
+
+template <class T>
+static vbm_status scan_impl(const T* in, T* out, int64_t n_max, const uint32_t* n_dev, T* total_dev, void* scratch,
+                            hipStream_t s) {
+  if (n_max <= 0) return VBM_OK;
+  const int64_t nb = ceil_div(n_max, kChunk);
+  T* sums = static_cast<T*>(scratch);
+  hipLaunchKernelGGL(k_scan_reduce<T>, dim3(nb), dim3(kThreads), 0, s, in, sums, n_max, n_dev);
+  VBM_LAUNCH_CHECK("scan_reduce");
+  hipLaunchKernelGGL(k_scan_top<T>, dim3(1), dim3(kThreads), 0, s, sums, nb, total_dev);
+  VBM_LAUNCH_CHECK("scan_top");
+  hipLaunchKernelGGL(k_scan_down<T>, dim3(nb), dim3(kThreads), 0, s, in, out, sums, n_max, n_dev);
+  VBM_LAUNCH_CHECK("scan_down");
+  return VBM_OK;
+}
+
+vbm_status scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n_max, const uint32_t* n_dev,
+                              uint32_t* total_dev, void* scratch, hipStream_t s) {
+  return scan_impl<uint32_t>(in, out, n_max, n_dev, total_dev, scratch, s);
+}
+
+vbm_status scan_exclusive_u64(const uint64_t* in, uint64_t* out, int64_t n_max, const uint32_t* n_dev,
+                              uint64_t* total_dev, void* scratch, hipStream_t s) {
+  return scan_impl<uint64_t>(in, out, n_max, n_dev, total_dev, scratch, s);
+}
+
+vbm_status fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s) {
+  if (n <= 0) return VBM_OK;
+  int64_t blocks = ceil_div(n, 256);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, p, value, n);
+  VBM_LAUNCH_CHECK("fill_u32");
+  return VBM_OK;
+}
+
+size_t radix_scratch_bytes(int64_t n_max, int digit_bits) {
+  const int64_t nb = ceil_div(n_max > 0 ? n_max : 1, kChunk);
+  const int64_t hist = static_cast<int64_t>(1 << digit_bits) * nb;
+  return align_up(static_cast<size_t>(hist) * 4, 256) + scan_scratch_bytes(hist);
+}
+
+template <class K>
+vbm_status radix_sort_pairs(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t n_max, const uint32_t* n_dev,
+                            int end_bit, int digit_bits, void* scratch, hipStream_t s, bool* result_in_k1) {
+  *result_in_k1 = false;
+  if (n_max <= 0 || end_bit <= 0) return VBM_OK;
+  if (digit_bits < 1 || digit_bits > 8) {
+    set_error("radix digit width %d outside 1..8", digit_bits);
+    return VBM_ERR_INVALID;
+  }
+  const int64_t nb = ceil_div(n_max, kChunk);
+  const int64_t hist_n = static_cast<int64_t>(1 << digit_bits) * nb;
+  uint32_t* hist = static_cast<uint32_t*>(scratch);
+  void* scan_scratch = static_cast<char*>(scratch) + align_up(static_cast<size_t>(hist_n) * 4, 256);
+  K* kin = k0;
+  uint32_t* vin = v0;
+  K* kout = k1;
+  uint32_t* vout = v1;
+  for (int shift = 0; shift < end_bit; shift += digit_bits) {
+    const int bits = (end_bit - shift) < digit_bits ? (end_bit - shift) : digit_bits;
+    hipLaunchKernelGGL(k_radix_hist<K>, dim3(nb), dim3(kThreads), 0, s, kin, hist, n_max, n_dev, shift, bits, nb);
+    VBM_LAUNCH_CHECK("radix_hist");
+    const int64_t hn = static_cast<int64_t>(1 << bits) * nb;
+    VBM_TRY(scan_exclusive_u32(hist, hist, hn, nullptr, nullptr, scan_scratch, s));
+    hipLaunchKernelGGL(k_radix_scatter<K>, dim3(nb), dim3(kThreads), 0, s, kin, vin, kout, vout, hist, n_max, n_dev,
+                       shift, bits, nb);
+    VBM_LAUNCH_CHECK("radix_scatter");
+    K* tk = kin;
+    kin = kout;
+    kout = tk;
+    uint32_t* tv = vin;
+    vin = vout;
+    vout = tv;
+    *result_in_k1 = !*result_in_k1;
+  }
+  return VBM_OK;
+}
+
+template vbm_status radix_sort_pairs<uint32_t>(uint32_t*, uint32_t*, uint32_t*, uint32_t*, int64_t, const uint32_t*,
+                                               int, int, void*, hipStream_t, bool*);
+template vbm_status radix_sort_pairs<uint64_t>(uint64_t*, uint32_t*, uint64_t*, uint32_t*, int64_t, const uint32_t*,
+                                               int, int, void*, hipStream_t, bool*);
+
+}  // namespace vbm

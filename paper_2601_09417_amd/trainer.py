@@ -1,0 +1,144 @@
+"""Fine-tuning step runners (Sec. 4.4: render, image loss, backward, Adam) on top of libvbm.
+
+* ``VBMRender``  -- torch.autograd.Function around vbm_render_fwd / vbm_render_bwd (the backward
+  recomputes each pixel's transmittance instead of storing per-Gaussian state).
+* ``FineTuner``  -- one fine-tuning iteration in three schedules:
+    plain    one view per launch: per view a forward (which synchronises once to size the sort
+             exactly), one loss over all views, per view a backward; then Adam
+    batched  every view (and scene) in one launch per phase, counts kept on the device
+    graph    the batched step captured once in a HIP graph and replayed
+  All three produce identical pair lists and images; gradients agree up to float atomics order.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import api
+
+
+class VBMRender(torch.autograd.Function):
+    """image = render(P) for a planned batch; P is the [14, N] activated parameter tensor."""
+
+    @staticmethod
+    def forward(ctx, P: torch.Tensor, rp: api.RenderPlan):
+        fwd = api.render_fwd(rp, P.detach().contiguous())
+        ctx.rp = rp
+        ctx.fwd = fwd
+        ctx.save_for_backward(P)
+        return fwd.image
+
+    @staticmethod
+    def backward(ctx, grad_image):
+        (P,) = ctx.saved_tensors
+        g = api.render_bwd(ctx.rp, P.detach().contiguous(), grad_image.contiguous(), ctx.fwd)
+        return g, None
+
+
+class FineTuner:
+    def __init__(self, P: torch.Tensor, cams, targets: torch.Tensor, scene_offsets=None, view_scene=None,
+                 tile: int = 16, sort_bits: int = 8, loss: str = "l1", lam: float = 0.2, lr=api.LR_DEFAULT,
+                 schedule: str = "batched", pair_capacity: int | None = None, capacity_margin: float = 1.25):
+        assert schedule in ("plain", "batched", "graph")
+        self.dev = P.device
+        self.cams = list(cams)
+        self.N = P.shape[1]
+        self.scene_offsets = np.asarray(scene_offsets if scene_offsets is not None else [0, self.N], np.int64)
+        self.view_scene = list(view_scene) if view_scene is not None else [0] * len(self.cams)
+        self.tile, self.sort_bits = tile, sort_bits
+        self.schedule = schedule
+        self.lr = lr
+        self.margin = capacity_margin
+        self.act = P.contiguous().clone()
+        self.raw = api.raw_from_activated(self.act)
+        self.m = torch.zeros_like(self.raw)
+        self.v = torch.zeros_like(self.raw)
+        self.grads = torch.zeros_like(self.raw)
+        self.step_dev = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        self.targets = targets
+        npx = sum(c.width * c.height for c in self.cams)
+        self.image = torch.zeros(3 * npx, dtype=torch.float32, device=self.dev)
+        self.final_T = torch.zeros(npx, dtype=torch.float32, device=self.dev)
+        self.n_contrib = torch.zeros(npx, dtype=torch.int32, device=self.dev)
+        self.dL = torch.zeros(3 * npx, dtype=torch.float32, device=self.dev)
+        self.loss_fn = api.ImageLoss([[c.width, c.height] for c in self.cams], loss, lam, self.dev)
+        self.pix_off = np.concatenate([[0], np.cumsum([c.width * c.height for c in self.cams])]).astype(np.int64)
+        self.graph = None
+        self.overflows = 0
+        self._plan(pair_capacity)
+
+    # -- planning ------------------------------------------------------------------------------
+    def _measure_pairs(self) -> list:
+        """Exact pair count per view from one exact-mode forward (planning only)."""
+        counts = []
+        for v, cam in enumerate(self.cams):
+            rp = api.plan_batch([cam], self.scene_offsets, [self.view_scene[v]], self.tile, self.sort_bits, 1, "exact",
+                                self.dev)
+            out = api.render_fwd(rp, self.act)
+            torch.cuda.synchronize(self.dev)
+            counts.append(int(out.status[1].item()))
+        return counts
+
+    def _plan(self, capacity):
+        if capacity is None:
+            counts = self._measure_pairs()
+        else:
+            counts = [capacity] * len(self.cams)
+        self.view_caps = [max(1, int(c * self.margin) + 1024) for c in counts]
+        if self.schedule == "plain":
+            self.plans = [api.plan_batch([cam], self.scene_offsets, [self.view_scene[v]], self.tile, self.sort_bits,
+                                         self.view_caps[v], "exact", self.dev) for v, cam in enumerate(self.cams)]
+            self.outs = []
+            for v in range(len(self.cams)):
+                a, b = int(self.pix_off[v]), int(self.pix_off[v + 1])
+                self.outs.append(api.FwdOut(self.image[3 * a:3 * b], self.final_T[a:b], self.n_contrib[a:b],
+                                            torch.zeros(4, dtype=torch.int32, device=self.dev)))
+        else:
+            total = sum(self.view_caps) if capacity is None else capacity
+            self.plans = [api.plan_batch(self.cams, self.scene_offsets, self.view_scene, self.tile, self.sort_bits,
+                                         total, "batched", self.dev)]
+            self.outs = [api.FwdOut(self.image, self.final_T, self.n_contrib,
+                                    torch.zeros(4, dtype=torch.int32, device=self.dev))]
+        self.graph = None
+
+    # -- one iteration ---------------------------------------------------------------------------
+    def _step_body(self):
+        if self.schedule == "plain":
+            for rp, out in zip(self.plans, self.outs):
+                api.render_fwd(rp, self.act, out)
+            self.loss_fn(self.image, self.targets, self.dL)
+            for v, (rp, out) in enumerate(zip(self.plans, self.outs)):
+                a, b = int(self.pix_off[v]), int(self.pix_off[v + 1])
+                api.render_bwd(rp, self.act, self.dL[3 * a:3 * b], out, self.grads, accumulate=v > 0)
+        else:
+            rp, out = self.plans[0], self.outs[0]
+            api.render_fwd(rp, self.act, out)
+            self.loss_fn(self.image, self.targets, self.dL)
+            api.render_bwd(rp, self.act, self.dL, out, self.grads, accumulate=False)
+        api.adam_step(self.raw, self.m, self.v, self.grads, self.act, self.lr, step_dev=self.step_dev)
+
+    def step(self):
+        if self.schedule == "graph":
+            if self.graph is None:
+                self._capture()
+            self.graph.replay()
+        else:
+            self._step_body()
+
+    def _capture(self):
+        # Every buffer of the step is preallocated and the library allocates nothing, so the step
+        # is captured directly; the capture executes nothing, the first replay is the first step.
+        torch.cuda.synchronize(self.dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._step_body()
+
+    def overflowed(self) -> bool:
+        """True if any forward since the last check dropped pairs (reads the device flag)."""
+        return any(int(o.status[0].item()) != 0 for o in self.outs)
+
+    def pair_count(self) -> int:
+        return sum(int(o.status[1].item()) for o in self.outs)
+
+    def loss(self) -> float:
+        return float(self.loss_fn.loss.item())

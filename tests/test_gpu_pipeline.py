@@ -1,0 +1,215 @@
+"""GPU parity of the upstream stages (TF + DWT, selection, construction), the loss, Adam, the DVR
+supervision renderer, and of the step schedules (plain, batched, graph replay)."""
+import numpy as np
+import pytest
+import torch
+
+import vbm_inputs as vi
+from oracle import adam as oadam
+from oracle import bank as obank
+from oracle import construct as oconstruct
+from oracle import dvr as odvr
+from oracle import dwt as odwt
+from oracle import loss as oloss
+from oracle import select as oselect
+from oracle import tf as otf
+from tests.gpu_common import IMG_TOL, dev, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2601_09417_amd import api
+    return api
+
+
+def _dwt_case(G, J, wav, seed):
+    vol = vi.blob_volume(G, 6, seed).astype(np.float32)
+    vol = vi.minmax(vol).astype(np.float32)
+    tf = vi.transfer_function(seed)
+    return vol, tf
+
+
+@pytest.mark.parametrize("G,J,wav", [(32, 1, "haar"), (32, 3, "haar"), (32, 2, "bior4.4"), (48, 3, "bior4.4"),
+                                     (16, 3, "bior4.4")])
+def test_dwt_matches_oracle(G, J, wav):
+    api = _api()
+    say(f"dwt G={G} J={J} {wav}")
+    vol, tf = _dwt_case(G, J, wav, G + J)
+    coeffs = api.dwt3d(torch.from_numpy(vol).to(dev()), J, wav, (tf.xs, tf.rgba)).cpu().numpy()
+    rgba = otf.apply(vol, tf.xs, tf.rgba)
+    ref = odwt.dwt3d_rgba(rgba, J, wav)
+    tol = 1e-6 if wav == "haar" else 1e-5
+    for (j, o), (off, n) in odwt.block_offsets(G, J).items():
+        blk = slice(off, off + n ** 3)
+        scale = max(np.abs(ref[:, blk]).max(), 1e-6)
+        err = np.abs(coeffs[:, blk] - ref[:, blk]).max() / scale
+        assert err <= tol, ((j, o), err)
+
+
+def test_dwt_rgba_input_path():
+    api = _api()
+    G, J = 16, 2
+    rgba = np.random.default_rng(1).uniform(size=(4, G ** 3)).astype(np.float32)
+    coeffs = api.dwt3d(torch.from_numpy(rgba).to(dev()), J, "bior4.4", None).cpu().numpy()
+    ref = odwt.dwt3d_rgba(rgba.reshape(4, G, G, G), J, "bior4.4")
+    assert np.abs(coeffs - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("G,J,wav,K,s_mode", [(32, 1, "haar", 2048, "paper"), (32, 3, "bior4.4", 5000, "none"),
+                                              (16, 2, "haar", 16 ** 3, "paper")])
+def test_select_bit_exact_and_construction(G, J, wav, K, s_mode):
+    api = _api()
+    say(f"select/build G={G} J={J} {wav} K={K}")
+    vol, tf = _dwt_case(G, J, wav, 7)
+    coeffs_d = api.dwt3d(torch.from_numpy(vol).to(dev()), J, wav, (tf.xs, tf.rgba))
+    entries, packed = api.bank_build(wav, J)
+    P, kept = api.build_gaussians(coeffs_d, G, J, packed, K, s_mode=s_mode)
+    coeffs = coeffs_d.cpu().numpy()
+    ref_kept = oselect.topk(coeffs, K)            # stage-isolated: same float32 coefficients
+    assert np.array_equal(kept.cpu().numpy(), ref_kept)
+    ob = obank.build_bank(wav, J)
+    ref = oconstruct.construct(coeffs, ref_kept, G, J, ob, s_mode=s_mode)
+    Pn = P.cpu().numpy()
+    for name, rows in (("means", slice(0, 3)), ("scales", slice(3, 6)), ("quats", slice(6, 10)),
+                       ("opacity", slice(10, 11)), ("rgb", slice(11, 14))):
+        r = ref[name].reshape(rows.stop - rows.start, -1)
+        err = np.abs(Pn[rows] - r).max() / max(np.abs(r).max(), 1e-6)
+        assert err <= 1e-6, (name, err)
+
+
+def test_select_ties_go_to_lower_index():
+    api = _api()
+    G, J = 16, 1
+    c = np.zeros((4, G ** 3), np.float32)
+    c[3, ::7] = 1.0          # many exact ties
+    c[0, 5] = 2.0
+    coeffs = torch.from_numpy(c).to(dev())
+    _, packed = api.bank_build("haar", J)
+    K = 100
+    _, kept = api.build_gaussians(coeffs, G, J, packed, K)
+    assert np.array_equal(kept.cpu().numpy(), oselect.topk(c, K))
+
+
+@pytest.mark.parametrize("kind", ["l1", "l1_dssim"])
+def test_loss_matches_oracle(kind):
+    api = _api()
+    rng = np.random.default_rng(4)
+    dims = [(37, 29), (64, 48)]
+    imgs = [rng.uniform(size=(3, h, w)).astype(np.float32) for w, h in dims]
+    tgts = [np.clip(i + 0.1 * rng.normal(size=i.shape), 0, 1).astype(np.float32) for i in imgs]
+    x = torch.from_numpy(np.concatenate([i.reshape(-1) for i in imgs])).to(dev())
+    y = torch.from_numpy(np.concatenate([t.reshape(-1) for t in tgts])).to(dev())
+    lf = api.ImageLoss(dims, kind, 0.2)
+    g = torch.empty_like(x)
+    loss = float(lf(x, y, g).item())
+    ref_loss, ref_g = oloss.loss_and_grad(imgs, tgts, kind)
+    assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss)
+    rg = np.concatenate([a.reshape(-1) for a in ref_g])
+    assert np.abs(g.cpu().numpy() - rg).max() <= 1e-4 * np.abs(rg).max()
+
+
+def test_adam_matches_oracle():
+    api = _api()
+    rng = np.random.default_rng(9)
+    N = 1000
+    gs = vi.random_gaussians(N, 2)
+    P = api.pack_params(gs.means, gs.scales, gs.quats, gs.opacity, gs.rgb, dev())
+    raw = api.raw_from_activated(P)
+    m = torch.zeros_like(raw)
+    v = torch.zeros_like(raw)
+    act = P.clone()
+    ls, lo = oadam.raw_from_activated(gs.scales, gs.opacity)
+    oraw = dict(means=gs.means.astype(np.float64), log_scales=ls, quats=gs.quats.astype(np.float64),
+                logit_opacity=lo, rgb=gs.rgb.astype(np.float64))
+    # oracle starts from the same float32 raw values
+    R = raw.cpu().numpy().astype(np.float64)
+    oraw = dict(means=R[0:3], log_scales=R[3:6], quats=R[6:10], logit_opacity=R[10], rgb=R[11:14])
+    om = {k: np.zeros_like(a) for k, a in oraw.items()}
+    ov = {k: np.zeros_like(a) for k, a in oraw.items()}
+    step_dev = torch.zeros(1, dtype=torch.int32, device=dev())
+    for t in range(1, 4):
+        G = rng.normal(size=(14, N)).astype(np.float32)
+        grads = torch.from_numpy(G).to(dev())
+        api.adam_step(raw, m, v, grads, act, step_dev=step_dev)
+        act_g = dict(means=G[0:3], scales=G[3:6], quats=G[6:10], opacity=G[10], rgb=G[11:14])
+        og = oadam.chain_grads(act_g, oraw)
+        oraw, om, ov = oadam.step(oraw, og, om, ov, t)
+    Rn = raw.cpu().numpy()
+    for k, rows in (("means", slice(0, 3)), ("log_scales", slice(3, 6)), ("quats", slice(6, 10)),
+                    ("logit_opacity", slice(10, 11)), ("rgb", slice(11, 14))):
+        ref = np.asarray(oraw[k]).reshape(rows.stop - rows.start, -1)
+        init = R[rows]
+        # parity relative to the learning rate: 3 steps move each value by at most 3 lr
+        lr = oadam.DEFAULT_LR[k]
+        assert np.abs((Rn[rows] - init) - (ref - init)).max() <= 1e-3 * lr, k
+    assert int(step_dev.item()) == 3
+    A = act.cpu().numpy()
+    assert np.allclose(A[3:6], np.exp(Rn[3:6]), rtol=1e-6)
+    assert np.allclose(A[10], 1 / (1 + np.exp(-Rn[10])), rtol=1e-6)
+
+
+def test_dvr_matches_oracle():
+    api = _api()
+    G = 32
+    vol = vi.volume_for_config(0)
+    tf = vi.transfer_function(0)
+    cams = vi.orbit_cameras(2, 40, 30)
+    say("dvr 32^3, 2 views 40x30")
+    img = api.dvr_render(torch.from_numpy(vol).to(dev()), (tf.xs, tf.rgba), cams).cpu().numpy()
+    off = 0
+    for c in cams:
+        ref, _ = odvr.render(vol, tf.xs, tf.rgba, c)
+        got = img[off:off + 3 * c.width * c.height].reshape(3, c.height, c.width)
+        off += 3 * c.width * c.height
+        assert np.abs(got - ref).max() <= 1e-4 * max(np.abs(ref).max(), 1e-6)
+
+
+def _tuner_inputs(seed=3):
+    gs = vi.random_gaussians(2000, seed, log_scale_mean=-3.2)
+    cams = vi.orbit_cameras(3, 80, 64)
+    tgt = torch.rand(sum(3 * c.width * c.height for c in cams), device=dev())
+    return gs, cams, tgt
+
+
+@pytest.mark.parametrize("loss", ["l1", "l1_dssim"])
+def test_schedules_agree(loss):
+    from paper_2601_09417_amd import trainer
+    gs, cams, tgt = _tuner_inputs()
+    api = _api()
+    P = api.pack_params(gs.means, gs.scales, gs.quats, gs.opacity, gs.rgb, dev())
+    say(f"schedules plain/batched/graph, loss={loss}")
+    runs = {}
+    for sched in ("plain", "batched", "graph"):
+        ft = trainer.FineTuner(P, cams, tgt, loss=loss, schedule=sched)
+        imgs = []
+        for _ in range(3):
+            ft.step()
+            torch.cuda.synchronize()
+            imgs.append(ft.image.clone())
+            assert not ft.overflowed()
+        runs[sched] = (imgs, ft.act.clone())
+    # first iteration's forward is identical bit for bit (same parameters, same pair lists)
+    assert torch.equal(runs["plain"][0][0], runs["batched"][0][0])
+    assert torch.equal(runs["batched"][0][0], runs["graph"][0][0])
+    # later iterations differ only through float atomics order in the backward
+    for s in ("plain", "graph"):
+        d = (runs[s][1] - runs["batched"][1]).abs().max().item()
+        assert d <= 1e-4, (s, d)
+
+
+def test_graph_replay_matches_eager_repeatedly():
+    from paper_2601_09417_amd import trainer
+    gs, cams, tgt = _tuner_inputs(5)
+    api = _api()
+    P = api.pack_params(gs.means, gs.scales, gs.quats, gs.opacity, gs.rgb, dev())
+    eager = trainer.FineTuner(P, cams, tgt, schedule="batched")
+    graph = trainer.FineTuner(P, cams, tgt, schedule="graph")
+    for it in range(4):
+        eager.step()
+        graph.step()
+        torch.cuda.synchronize()
+        d = (eager.image - graph.image).abs().max().item()
+        assert d <= 1e-4, (it, d)
+        _ = eager.loss()   # host work between replays
+    assert int(graph.step_dev.item()) == 4 and int(eager.step_dev.item()) == 4

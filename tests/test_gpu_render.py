@@ -1,0 +1,170 @@
+"""GPU parity of the renderer against the oracle: float32 binning decisions and pair lists bit-exact,
+images within 1e-5 and gradients within 1e-4 (relative to the group maximum)."""
+import numpy as np
+import pytest
+import torch
+
+import vbm_inputs as vi
+from oracle import binning, render
+from tests.gpu_common import (GRAD_TOL, IMG_TOL, ROWS, dev, flat, group_error, image_error, masked_dL, say,
+                              to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2601_09417_amd import api
+    return api
+
+
+def _scene(n, seed, views, W, H, log_scale=-3.0, opacity=(0.05, 0.95)):
+    gs = vi.random_gaussians(n, seed, log_scale_mean=log_scale, opacity_range=opacity)
+    cams = vi.orbit_cameras(views, W, H, azimuth0=0.3 * seed)
+    return gs, cams
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_projection_and_pair_lists_bit_exact(tile):
+    api = _api()
+    gs, cams = _scene(3000, 11, 3, 131, 77)
+    say(f"pair lists tile={tile} n={gs.n} views=3 131x77")
+    P = to_dev(gs)
+    rp = api.plan_batch(cams, [0, gs.n], tile=tile, pair_capacity=1 << 20)
+    out = api.render_fwd(rp, P)
+    torch.cuda.synchronize()
+    ref = binning.pair_lists(gs, cams, tile)
+    assert int(out.status[0]) == 0
+    P_ref = ref["tile"].size
+    assert int(out.status[1]) == P_ref
+    depth = rp.region("item_depth", torch.float32).cpu().numpy()
+    rect = rp.region("item_rect", torch.int32).cpu().numpy().view(np.uint32)
+    ntl = rp.region("item_ntiles", torch.int32).cpu().numpy()
+    I = int(rp.plan.n_items)
+    for v in range(3):
+        pr = ref["proj"][v]
+        sl = slice(v * gs.n, (v + 1) * gs.n)
+        vis = pr["n_tiles"] > 0
+        assert np.array_equal(ntl[sl], pr["n_tiles"])
+        assert np.array_equal(depth[sl][vis].view(np.uint32), pr["depth"][vis].view(np.uint32))
+        assert np.array_equal(rect[sl][vis] & 0xFFFF, pr["x0"][vis])
+        assert np.array_equal(rect[sl][vis] >> 16, pr["x1"][vis])
+        assert np.array_equal(rect[I:][sl][vis] & 0xFFFF, pr["y0"][vis])
+        assert np.array_equal(rect[I:][sl][vis] >> 16, pr["y1"][vis])
+    ptile = rp.region("pair_tile", torch.int32).cpu().numpy()[:P_ref]
+    pitem = rp.region("pair_item", torch.int32).cpu().numpy()[:P_ref]
+    assert np.array_equal(ptile, ref["tile"])
+    assert np.array_equal(pitem, ref["item"])
+    ranges = rp.region("ranges", torch.int32).cpu().numpy().reshape(-1, 2)
+    assert np.array_equal(ranges, ref["ranges"])
+
+
+@pytest.mark.parametrize("tile,W,H", [(16, 64, 64), (16, 101, 67), (8, 50, 37), (32, 96, 80)])
+def test_forward_backward_parity(tile, W, H):
+    api = _api()
+    gs, cams = _scene(600, 3, 2, W, H)
+    say(f"fwd/bwd parity tile={tile} {W}x{H} n={gs.n}")
+    P = to_dev(gs)
+    rp = api.plan_batch(cams, [0, gs.n], tile=tile, pair_capacity=1 << 18)
+    out = api.render_fwd(rp, P)
+    batch = render.Batch(gs, cams, tile)
+    ref = render.render_forward(batch)
+    imgs = [t.cpu().numpy() for t in api.split_views(out.image, cams)]
+    fts = [t.cpu().numpy() for t in api.split_views(out.final_T, cams, 1)]
+    ncs = [t.cpu().numpy() for t in api.split_views(out.n_contrib, cams, 1)]
+    for v in range(len(cams)):
+        err = image_error(imgs[v], ref[v]["image"], ref[v]["flagged"])
+        say(f"  view {v}: image err {err:.2e}, flagged {int(ref[v]['flagged'].sum())}")
+        assert err <= IMG_TOL
+        ok = ~ref[v]["flagged"]
+        assert np.abs(fts[v] - ref[v]["final_T"])[ok].max() <= 1e-5
+        assert np.array_equal(ncs[v][ok], ref[v]["n_contrib"][ok])
+    dL = masked_dL(cams, [r["flagged"] for r in ref], seed=tile)
+    grads = api.render_bwd(rp, P, flat(dL), out)
+    g_ref, g2_ref = render.render_backward(batch, dL)
+    G = grads.cpu().numpy()
+    for name, rows in ROWS.items():
+        e = group_error(G[rows], g_ref[name].reshape(rows.stop - rows.start, -1))
+        say(f"  grad {name}: {e:.2e}")
+        assert e <= GRAD_TOL, name
+    g2 = rp.region("grad2d", torch.float32).cpu().numpy().reshape(9, -1)
+    for name, rows, ref2 in (("mean2d", slice(0, 2), g2_ref["mean2d"].T), ("conic", slice(2, 5), g2_ref["conic"].T),
+                             ("opacity", slice(5, 6), g2_ref["opacity"][None]), ("rgb", slice(6, 9), g2_ref["rgb"].T)):
+        e = group_error(g2[rows], ref2)
+        assert e <= GRAD_TOL, name
+
+
+def test_empty_and_fully_culled_views():
+    api = _api()
+    gs, cams = _scene(50, 5, 1, 40, 30)
+    gs.means[2] += 10.0   # everything behind the camera or far off-screen
+    cams2 = [vi.Camera(width=40, height=30, fx=30.0, fy=30.0, cx=20.0, cy=15.0, near=0.2,
+                       viewmat=vi.look_at(np.array([0.0, 0.0, -50.0]), target=np.array([0.0, 0.0, -60.0]),
+                                          up=np.array([0.0, 1.0, 0.0])).astype(np.float32))]
+    P = to_dev(gs)
+    rp = api.plan_batch(cams2, [0, gs.n], tile=16, pair_capacity=1024)
+    out = api.render_fwd(rp, P)
+    torch.cuda.synchronize()
+    assert int(out.status[1]) == 0 and int(out.status[2]) == 0
+    assert torch.all(out.final_T == 1.0) and torch.all(out.image == 0.0) and torch.all(out.n_contrib == 0)
+    g = api.render_bwd(rp, P, torch.ones_like(out.image), out)
+    assert torch.all(g == 0.0)
+
+
+def test_capacity_overflow_is_flagged():
+    api = _api()
+    gs, cams = _scene(800, 8, 1, 64, 64)
+    P = to_dev(gs)
+    rp = api.plan_batch(cams, [0, gs.n], tile=16, pair_capacity=100)
+    out = api.render_fwd(rp, P)
+    torch.cuda.synchronize()
+    assert int(out.status[0]) == 1 and int(out.status[1]) > 100
+    rp2 = api.plan_batch(cams, [0, gs.n], tile=16, pair_capacity=int(out.status[1]))
+    out2 = api.render_fwd(rp2, P)
+    torch.cuda.synchronize()
+    assert int(out2.status[0]) == 0
+
+
+def test_batched_equals_plain_and_multiscene():
+    api = _api()
+    s1, _ = _scene(300, 21, 1, 60, 40)
+    s2, _ = _scene(900, 22, 1, 60, 40, log_scale=-3.5)
+    gs = vi.GaussianSet.concat([s1, s2])
+    cams = vi.orbit_cameras(2, 72, 56) + vi.orbit_cameras(2, 40, 33, azimuth0=1.0)
+    view_scene = [0, 1, 1, 0]
+    so = [0, s1.n, s1.n + s2.n]
+    say("batched vs plain, 2 scenes, 4 uneven views")
+    P = to_dev(gs)
+    rp = api.plan_batch(cams, so, view_scene, tile=16, pair_capacity=1 << 18)
+    out = api.render_fwd(rp, P)
+    imgs = api.split_views(out.image, cams)
+    for v, cam in enumerate(cams):
+        rpv = api.plan_batch([cam], so, [view_scene[v]], tile=16, pair_capacity=1 << 16, mode="exact")
+        ov = api.render_fwd(rpv, P)
+        torch.cuda.synchronize()
+        assert torch.equal(ov.image.view(3, cam.height, cam.width), imgs[v])
+    # multi-scene oracle parity
+    batch = render.Batch(gs, cams, 16, view_scene, so)
+    ref = render.render_forward(batch)
+    for v in range(len(cams)):
+        assert image_error(imgs[v].cpu().numpy(), ref[v]["image"], ref[v]["flagged"]) <= IMG_TOL
+    dL = masked_dL(cams, [r["flagged"] for r in ref], seed=5)
+    grads = api.render_bwd(rp, P, flat(dL), out)
+    g_ref, _ = render.render_backward(batch, dL)
+    G = grads.cpu().numpy()
+    for name, rows in ROWS.items():
+        assert group_error(G[rows], g_ref[name].reshape(rows.stop - rows.start, -1)) <= GRAD_TOL, name
+
+
+def test_forward_is_deterministic_and_accumulate_adds():
+    api = _api()
+    gs, cams = _scene(1500, 31, 2, 90, 70)
+    P = to_dev(gs)
+    rp = api.plan_batch(cams, [0, gs.n], tile=16, pair_capacity=1 << 18)
+    a = api.render_fwd(rp, P)
+    img_a = a.image.clone()
+    b = api.render_fwd(rp, P)
+    assert torch.equal(img_a, b.image)
+    dL = torch.randn_like(b.image)
+    g1 = api.render_bwd(rp, P, dL, b)
+    g2 = api.render_bwd(rp, P, dL, b, grads=g1.clone(), accumulate=True)
+    assert torch.allclose(g2, 2 * g1, rtol=1e-5, atol=1e-7 * float(g1.abs().max()))
