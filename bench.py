@@ -1,0 +1,367 @@
+#!/usr/bin/env python
+"""Fine-tuning throughput of the VBM fine-tuning loop on one MI355X.
+
+One step = one image-space fine-tuning iteration (Sec. 4.4): EWA projection of every Gaussian in
+every view, binning with the depth-keyed radix sort, front-to-back compositing, the image loss
+(0.8 L1 + 0.2 D-SSIM) and its gradient, the reverse-order backward through compositing and
+projection, and one Adam step -- all in libvbm's HIP kernels.  The Gaussians come from the method's
+own initialisation (TF -> 3D DWT -> top-K by joint norm -> transition-bank construction), run once
+on the GPU before timing, and the targets from the GPU ray marcher, also before timing.
+
+Workload (default "H"): 512^3 synthetic turbulence volume (random phases, E(k) ~ k^-5/3 for
+1 <= k <= 64, min-max normalised), bior4.4 J=5, the top 1,000,000 coefficients, 8 orbit views at
+1920x1080, 16x16 tiles.  Reported value: iterations/sec of the batched schedule (every view in one
+launch per phase, captured in a HIP graph), with the plain one-view-per-launch schedule timed
+alongside, the compositing kernels' roofline and the CPU oracle timed on a bounded sample.
+
+Prints exactly one JSON line on stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+# Algorithmic cost per (pixel, Gaussian) evaluation of the compositing kernels.
+FLOPS_FWD_EVAL, FLOPS_FWD_USED = 17, 8
+FLOPS_BWD_EVAL, FLOPS_BWD_USED = 17, 40
+BYTES_PER_PAIR_FWD, BYTES_PER_PIXEL_FWD = 40, 20
+BYTES_PER_PAIR_BWD, BYTES_PER_PIXEL_BWD = 76, 20
+
+WORKLOADS = {
+    "H": dict(config=3, G=512, J=5, wavelet="bior4.4", K=1_000_000, views=8, W=1920, H=1080, tile=16,
+              loss="l1_dssim", desc="512^3 turbulence (E(k)~k^-5/3, kmax 64), bior4.4 J=5, top-1M Gaussians, "
+                                    "8 orbit views 1920x1080, tile 16, loss 0.8 L1 + 0.2 D-SSIM, Adam"),
+    "c1": dict(config=1, G=128, J=3, wavelet="haar", K=100_000, views=16, W=800, H=800, tile=16, loss="l1",
+               desc="128^3 blobs + k^-2 noise, Haar J=3, top-100k Gaussians, 16 orbit views 800x800, tile 16, L1, Adam"),
+}
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ----------------------------------------------------------------------------- CPU oracle baseline
+
+def cpu_baseline_worker(queue, workload: str, n_tiles: int, threads: int) -> None:
+    """Times the CPU oracle's per-iteration work on a bounded sample of the same workload."""
+    try:
+        import torch
+        torch.set_num_threads(threads)
+        import vbm_inputs as vi
+        from oracle import adam as oadam
+        from oracle import bank as obank
+        from oracle import binning, construct, dvr, dwt, loss, render, select
+        from oracle import tf as otf
+
+        wl = WORKLOADS[workload]
+        t_init = time.perf_counter()
+        vol = vi.volume_for_config(wl["config"])
+        tfn = vi.transfer_function(wl["config"])
+        rgba = otf.apply(vol, tfn.xs, tfn.rgba)
+        coeffs = dwt.dwt3d_rgba(rgba, wl["J"], wl["wavelet"])
+        del rgba
+        kept = select.topk(coeffs.astype(np.float32), wl["K"])
+        bank = obank.build_bank(wl["wavelet"], wl["J"])
+        g = construct.construct(coeffs, kept, wl["G"], wl["J"], bank, s_mode="none")
+        del coeffs
+        gs = vi.GaussianSet(*(g[k].astype(np.float32) for k in ("means", "scales", "quats", "opacity", "rgb")))
+        cams = vi.orbit_cameras(wl["views"], wl["W"], wl["H"])
+        init_s = time.perf_counter() - t_init
+
+        # (1) projection + binning of view 0, every Gaussian (scaled by the view count)
+        t0 = time.perf_counter()
+        batch = render.Batch(gs, [cams[0]], wl["tile"])
+        t_bin = time.perf_counter() - t0
+        # (2) FP64 projection forward + backward of view 0 (scaled by the view count)
+        t0 = time.perf_counter()
+        P = batch.leaf_params()
+        m2d, con, op, rgb = batch.project_items(P)
+        torch.autograd.backward([m2d, con, op, rgb], [torch.ones_like(m2d), torch.ones_like(con),
+                                                      torch.ones_like(op), torch.ones_like(rgb)])
+        t_proj = time.perf_counter() - t0
+        # (3) compositing forward + backward of sampled tiles (scaled by tiles per step)
+        cam = cams[0]
+        TX, TY = -(-cam.width // wl["tile"]), -(-cam.height // wl["tile"])
+        rng = np.random.default_rng(12345)
+        sample = rng.choice(TX * TY, size=min(n_tiles, TX * TY), replace=False)
+        m2d_d, con_d, op_d, rgb_d = (t.detach() for t in (m2d, con, op, rgb))
+        ranges, items = batch.pairs["ranges"], batch.pairs["item"]
+        t_comp = 0.0
+        pairs_sampled = 0
+        for gt in sample:
+            ty, tx = divmod(int(gt), TX)
+            xs, ys = render._tile_pixels(cam, wl["tile"], tx, ty)
+            tgt, _ = dvr.render(vol, tfn.xs, tfn.rgba, cam, pixels=(xs, ys))      # supervision: not timed
+            s, e = ranges[gt]
+            it = torch.as_tensor(items[s:e])
+            pairs_sampled += int(e - s)
+            t0 = time.perf_counter()
+            leaves = [t[it].clone().requires_grad_(True) for t in (m2d_d, con_d, op_d, rgb_d)]
+            pix = torch.stack([torch.as_tensor(xs + 0.5, dtype=torch.float64),
+                               torch.as_tensor(ys + 0.5, dtype=torch.float64)], 1)
+            col, _, _, _, _ = render.composite_tile(pix, *leaves, torch.zeros(3, dtype=torch.float64))
+            l1 = (col - torch.as_tensor(tgt.T)).abs().sum()
+            if l1.requires_grad:          # empty tiles have nothing to differentiate
+                l1.backward()
+            t_comp += time.perf_counter() - t0
+        # (4) loss with SSIM on one 256x256 crop (scaled by pixels per step)
+        crop = np.random.default_rng(1).uniform(size=(3, 256, 256))
+        t0 = time.perf_counter()
+        loss.loss_and_grad([crop], [np.clip(crop + 0.05, 0, 1)], wl["loss"])
+        t_loss = time.perf_counter() - t0
+        # (5) Adam over all Gaussians
+        raw = dict(means=gs.means.astype(np.float64), log_scales=np.log(gs.scales.astype(np.float64)),
+                   quats=gs.quats.astype(np.float64), logit_opacity=np.zeros(gs.n), rgb=gs.rgb.astype(np.float64))
+        zeros = {k: np.zeros_like(v) for k, v in raw.items()}
+        t0 = time.perf_counter()
+        oadam.step(raw, raw, zeros, {k: v.copy() for k, v in zeros.items()}, 1)
+        t_adam = time.perf_counter() - t0
+        n_views = wl["views"]
+        tiles_total = n_views * TX * TY
+        px_total = n_views * cam.width * cam.height
+        sec = (n_views * (t_bin + t_proj) + t_comp * tiles_total / len(sample)
+               + t_loss * px_total / (256 * 256) + t_adam)
+        queue.put(dict(ok=True, sec_per_iter=sec, init_s=init_s, t_bin=t_bin, t_proj=t_proj, t_comp=t_comp,
+                       tiles=len(sample), pairs_sampled=pairs_sampled, t_loss=t_loss, t_adam=t_adam,
+                       threads=torch.get_num_threads()))
+    except Exception as exc:  # pragma: no cover - reported in the JSON line
+        import traceback
+        queue.put(dict(ok=False, error=f"{exc!r}", tb=traceback.format_exc()[-2000:]))
+
+
+# ----------------------------------------------------------------------------- GPU side
+
+def traffic_from_profiles(kernel_src: str):
+    """HBM bytes per launch of the backward compositing kernel from committed rocprofv3 counter runs,
+    or None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "composite_bwd_H_counters.md")
+    if not os.path.exists(path):
+        return None
+    digest = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+    for line in open(path):
+        if line.startswith("traffic_json:"):
+            d = json.loads(line.split(":", 1)[1])
+            if d.get("kernel_sha") == digest:
+                return d.get("bytes_per_launch")
+    return None
+
+
+def run_gpu(args, wl):
+    import torch
+
+    import vbm_inputs as vi
+    from paper_2601_09417_amd import _lib as L
+    from paper_2601_09417_amd import api, trainer
+
+    dev = torch.device("cuda:0")
+    lib = L.load()
+    out = {}
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    t0 = time.perf_counter()
+    vol = vi.volume_for_config(wl["config"])
+    tfn = vi.transfer_function(wl["config"])
+    out["volume_gen_s"] = time.perf_counter() - t0
+    vol_d = torch.from_numpy(vol).to(dev)
+    del vol
+    cams = vi.orbit_cameras(wl["views"], wl["W"], wl["H"])
+
+    # initialisation (once per scene; not part of the iteration)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    coeffs = api.dwt3d(vol_d, wl["J"], wl["wavelet"], (tfn.xs, tfn.rgba))
+    _, packed = api.bank_build(wl["wavelet"], wl["J"])
+    P, _ = api.build_gaussians(coeffs, wl["G"], wl["J"], packed, wl["K"], s_mode="none")
+    torch.cuda.synchronize()
+    out["init_ms"] = (time.perf_counter() - t0) * 1e3
+    del coeffs
+    targets = api.dvr_render(vol_d, (tfn.xs, tfn.rgba), cams)
+    torch.cuda.synchronize()
+    log(f"init {out['init_ms']:.1f} ms; targets ready")
+
+    def timed(ft, steps, warmup):
+        for _ in range(warmup):
+            ft.step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            ft.step()
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        return wall, e0.elapsed_time(e1) / 1e3
+
+    # batched schedule, captured as a graph: the reported value
+    ft = trainer.FineTuner(P, cams, targets, loss=wl["loss"], lam=0.2, tile=wl["tile"], schedule="graph")
+    wall, ev = timed(ft, args.steps, args.warmup)
+    if ft.overflowed():
+        raise RuntimeError("pair capacity overflow during the timed region")
+    out["batched_wall_s"], out["batched_event_s"] = wall, ev
+    out["pairs_per_step"] = ft.pair_count()
+    out["loss"] = ft.loss()
+    log(f"batched(graph): {args.steps / wall:.2f} it/s, pairs {out['pairs_per_step']}")
+    del ft
+
+    # kernel-level timing of the compositing kernels on the eager batched schedule
+    fb = trainer.FineTuner(P, cams, targets, loss=wl["loss"], lam=0.2, tile=wl["tile"], schedule="batched")
+    for _ in range(args.warmup):
+        fb.step()
+    counters = torch.zeros(4, dtype=torch.int64, device=dev)
+    evs = []
+    torch.cuda.synchronize()
+    for i in range(args.steps):
+        quad = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        for e in quad:
+            e.record()  # creates the underlying event
+        lib.vbm_profile_events(*[e.cuda_event for e in quad])
+        lib.vbm_profile_counters(counters.data_ptr() if i == 0 else None)
+        fb.step()
+        evs.append(quad)
+    lib.vbm_profile_events(None, None, None, None)
+    lib.vbm_profile_counters(None)
+    torch.cuda.synchronize()
+    fwd_ms = float(np.mean([q[0].elapsed_time(q[1]) for q in evs]))
+    bwd_ms = float(np.mean([q[2].elapsed_time(q[3]) for q in evs]))
+    c = counters.cpu().numpy().astype(np.float64)
+    npx = sum(cc.width * cc.height for cc in cams)
+    P_pairs = out["pairs_per_step"]
+    out["kernels"] = {
+        "composite_fwd": dict(ms=fwd_ms, evals=c[0], contrib=c[1],
+                              tflops=(FLOPS_FWD_EVAL * c[0] + FLOPS_FWD_USED * c[1]) / (fwd_ms * 1e-3) / 1e12,
+                              gbs=(BYTES_PER_PAIR_FWD * P_pairs + BYTES_PER_PIXEL_FWD * npx) / (fwd_ms * 1e-3) / 1e9),
+        "composite_bwd": dict(ms=bwd_ms, evals=c[2], contrib=c[3],
+                              tflops=(FLOPS_BWD_EVAL * c[2] + FLOPS_BWD_USED * c[3]) / (bwd_ms * 1e-3) / 1e12,
+                              gbs=(BYTES_PER_PAIR_BWD * P_pairs + BYTES_PER_PIXEL_BWD * npx) / (bwd_ms * 1e-3) / 1e9),
+    }
+    log(f"composite fwd {fwd_ms:.2f} ms, bwd {bwd_ms:.2f} ms per launch")
+    del fb
+
+    # plain schedule: one view per launch, one host sync per view forward
+    if not args.skip_plain:
+        fp = trainer.FineTuner(P, cams, targets, loss=wl["loss"], lam=0.2, tile=wl["tile"], schedule="plain")
+        wall_p, _ = timed(fp, args.steps, args.warmup)
+        out["plain_wall_s"] = wall_p
+        log(f"plain: {args.steps / wall_p:.2f} it/s")
+        del fp
+    return out
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="H", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-plain", action="store_true")
+    ap.add_argument("--cpu-tiles", type=int, default=256, help="tiles in the CPU oracle sample")
+    ap.add_argument("--cpu-threads", type=int, default=8)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device-to-device copy of this size first (scales HBM counters)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs the fine-tuning path on one GPU only; multi-GPU sharding is a design note, "
+              "not a measured configuration (use --gpus 1).", file=sys.stderr)
+        return 2
+    wl = WORKLOADS[args.workload]
+    rank0 = int(os.environ.get("RANK", "0")) == 0
+
+    # start the CPU oracle before anything touches the GPU in this process
+    proc = queue = None
+    if rank0 and not args.no_cpu_baseline:
+        ctx = mp.get_context("spawn")
+        queue = ctx.Queue()
+        proc = ctx.Process(target=cpu_baseline_worker, args=(queue, args.workload, args.cpu_tiles, args.cpu_threads),
+                           daemon=True)
+        proc.start()
+        log(f"CPU oracle baseline started (pid {proc.pid})")
+
+    gpu = run_gpu(args, wl)
+
+    cpu = None
+    if proc is not None:
+        log("waiting for the CPU oracle baseline")
+        try:
+            cpu = queue.get(timeout=900)
+        except Exception as exc:
+            cpu = dict(ok=False, error=f"no result: {exc!r}")
+        proc.join(timeout=30)
+
+    value = args.steps / gpu["batched_wall_s"]
+    plain = args.steps / gpu["plain_wall_s"] if "plain_wall_s" in gpu else None
+    k = gpu["kernels"]["composite_bwd"]
+    traffic = traffic_from_profiles(os.path.join(ROOT, "paper_2601_09417_amd", "csrc", "raster.hip"))
+    result = {
+        "metric": "fine-tune iters/sec (fwd+bwd, 1M Gaussians, 1080p, 8 views) batched vs plain",
+        "value": round(value, 4),
+        "unit": "iters/sec",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 / value, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {wl['desc']}", "gaussians": wl["K"], "views": wl["views"],
+                   "width": wl["W"], "height": wl["H"], "tile": wl["tile"], "schedule": "batched, HIP graph"},
+        "plain_value": None if plain is None else round(plain, 4),
+        "batched_over_plain": None if plain is None else round(value / plain, 3),
+        "pairs_per_step": gpu["pairs_per_step"],
+        "init_ms": round(gpu["init_ms"], 2),
+        "kernels_ms": {n: round(d["ms"], 3) for n, d in gpu["kernels"].items()},
+        "roofline": {
+            "bound": "alu",
+            "kernel": "composite_bwd",
+            "achieved": round(k["tflops"], 3),
+            "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(k["tflops"] / FP32_PEAK_TFLOPS, 4),
+            "traffic": traffic,
+            "algorithmic_hbm_gbs": round(k["gbs"], 1),
+            "hbm_frac": round(k["gbs"] / HBM_PEAK_GBS, 4),
+        },
+    }
+    if cpu is not None and cpu.get("ok"):
+        result["cpu_baseline"] = {
+            "value": round(1.0 / cpu["sec_per_iter"], 6), "unit": "iters/sec", "cores": cpu["threads"],
+            "kind": "oracle",
+            "sample": (f"FP64 oracle on the same workload: projection+binning and FP64 projection fwd/bwd of all "
+                       f"{wl['K']} Gaussians for view 0 (x{wl['views']} views), compositing fwd+bwd of "
+                       f"{cpu['tiles']} random tiles of view 0 ({cpu['pairs_sampled']} pairs; scaled to all tiles), "
+                       f"loss on a 256x256 crop (scaled to all pixels), Adam on all Gaussians; "
+                       f"oracle-built Gaussians, init {cpu['init_s']:.0f}s untimed"),
+            "sec_per_iter": round(cpu["sec_per_iter"], 2),
+        }
+    elif cpu is not None:
+        result["cpu_baseline"] = {"value": None, "error": cpu.get("error")}
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -286,6 +286,21 @@ vbm_status vbm_adam_step(int64_t n, int64_t stride, float* raw, float* m, float*
 vbm_status vbm_dvr_render(const float* vol, int32_t G, const vbm_tf* tf_host, const vbm_view* views_host,
                           int32_t n_views, float step_vox, float* image, void* stream);
 
+/* ------------------------------------------------------------------------------------------
+ * vbm_profile_events -- measurement aid: hipEvent_t handles (passed as void*) that later
+ * vbm_render_fwd / vbm_render_bwd calls record on their stream immediately before and after the
+ * compositing kernel launch, so a caller can time that kernel alone with hipEventElapsedTime.
+ * Process-wide setting; NULL handles disable the recording.  Not for use inside graph capture.
+ * ------------------------------------------------------------------------------------------ */
+vbm_status vbm_profile_events(void* composite_fwd_begin, void* composite_fwd_end, void* composite_bwd_begin,
+                              void* composite_bwd_end);
+
+/* vbm_profile_counters -- measurement aid: when dev_counters (device uint64 [4], zeroed by the caller)
+ * is non-NULL, later compositing launches add the number of (pixel, Gaussian) evaluations and of
+ * contributing evaluations: [0] forward evaluated, [1] forward contributing, [2] backward evaluated,
+ * [3] backward contributing.  Process-wide; NULL disables it (the default). */
+vbm_status vbm_profile_counters(void* dev_counters);
+
 #ifdef __cplusplus
 }
 #endif

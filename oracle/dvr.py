@@ -48,12 +48,16 @@ def trilinear(vol: np.ndarray, p: np.ndarray) -> np.ndarray:
     return out
 
 
-def render(vol: np.ndarray, xs, rgba, cam, step_vox: float = 0.5, t_min: float = 1e-4):
+def render(vol: np.ndarray, xs, rgba, cam, step_vox: float = 0.5, t_min: float = 1e-4, pixels=None):
+    """Image [3][H][W] and transmittance [H][W]; with ``pixels`` = (px, py) index arrays only those
+    rays are marched and the results are [3][n] and [n]."""
     vol = np.asarray(vol, dtype=np.float64)
     G = vol.shape[0]
     h = 2.0 / G
     dt = step_vox * h
     eye, d = ray_dirs(cam)
+    if pixels is not None:
+        d = d[np.asarray(pixels[1]), np.asarray(pixels[0])][None]      # [1][n][3]
     with np.errstate(divide="ignore", invalid="ignore"):
         inv = 1.0 / d
         t1 = (-1.0 - eye) * inv
@@ -62,7 +66,7 @@ def render(vol: np.ndarray, xs, rgba, cam, step_vox: float = 0.5, t_min: float =
     tf = np.min(np.maximum(t1, t2), -1)
     tn = np.maximum(tn, 0.0)
     hit = tf > tn
-    H, W = cam.height, cam.width
+    H, W = d.shape[0], d.shape[1]
     C = np.zeros((H, W, 3))
     T = np.ones((H, W))
     nsteps = np.where(hit, np.floor((tf - tn) / dt).astype(np.int64) + 1, 0)
@@ -78,4 +82,6 @@ def render(vol: np.ndarray, xs, rgba, cam, step_vox: float = 0.5, t_min: float =
         Ta = T[act]
         C[act] += (Ta * a)[:, None] * c[:3].T
         T[act] = Ta * (1.0 - a)
+    if pixels is not None:
+        return C[0].T, T[0]
     return C.transpose(2, 0, 1), T

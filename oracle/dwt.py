@@ -15,23 +15,43 @@ o = 1..7 of level j; each block is [n_j^3] in [z][y][x] order with n_j = G / 2^j
 from __future__ import annotations
 
 import numpy as np
+import torch
 
 from . import wavelets
 
 
-def analysis_1d(x: np.ndarray, bank: wavelets.FilterBank, axis: int):
-    """One periodised analysis step along ``axis``: returns (low, high), each half as long."""
-    N = x.shape[axis]
+def analysis_1d(x, bank: wavelets.FilterBank, axis: int):
+    """One periodised analysis step along ``axis``: returns (low, high), each half as long.
+
+    The signal is extended periodically by the filter reach on both sides so that every tap
+    x[(2k + m) mod N] is a plain strided slice of the extended array.  Accepts a numpy array or a
+    float64 CPU torch tensor (the multi-level transform keeps torch tensors between levels so that
+    the elementwise sums run multi-threaded) and returns the same kind.
+    """
+    is_np = isinstance(x, np.ndarray)
+    xt = torch.from_numpy(np.asarray(x, dtype=np.float64)) if is_np else x
+    N = xt.shape[axis]
     assert N % 2 == 0
-    k = np.arange(N // 2)
+    xm = xt.movedim(axis, 0)
+    firsts = [bank.lo_a[1], bank.hi_a[1]]
+    lasts = [bank.lo_a[1] + len(bank.lo_a[0]) - 1, bank.hi_a[1] + len(bank.hi_a[0]) - 1]
+    lo_pad, hi_pad = max(0, -min(firsts)), max(0, max(lasts) - 1) + 1
+    if lo_pad <= N and hi_pad <= N:
+        ext = torch.cat([xm[N - lo_pad:], xm, xm[:hi_pad]], 0)
+        base = lo_pad
+    else:                                                       # filter longer than the signal
+        reps = -(-max(lo_pad, hi_pad) // N) + 1
+        ext = torch.cat([xm] * (2 * reps + 1), 0)
+        base = reps * N
     out = []
     for taps, first in (bank.lo_a, bank.hi_a):
         acc = None
         for i, c in enumerate(taps):
             m = first + i
-            term = c * np.take(x, (2 * k + m) % N, axis=axis)
-            acc = term if acc is None else acc + term
-        out.append(acc)
+            term = float(c) * ext[base + m: base + m + N: 2]
+            acc = term if acc is None else acc.add_(term)
+        acc = acc.movedim(0, axis).contiguous()
+        out.append(acc.numpy() if is_np else acc)
     return out[0], out[1]
 
 
@@ -84,13 +104,13 @@ def dwt3d(x: np.ndarray, J: int, wavelet: str) -> dict:
     G = x.shape[0]
     assert x.shape == (G, G, G) and G % (1 << J) == 0
     out = {}
-    cur = np.asarray(x, dtype=np.float64)
+    cur = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64))
     for j in range(1, J + 1):
         oct_ = analysis_level(cur, bank)
         for o in range(1, 8):
-            out[(j, o)] = oct_[o]
+            out[(j, o)] = oct_[o].numpy()
         cur = oct_[0]
-    out[(J, 0)] = cur
+    out[(J, 0)] = cur.numpy()
     return out
 
 

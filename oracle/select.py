@@ -20,9 +20,24 @@ def joint_norm_f32(coeffs: np.ndarray) -> np.ndarray:
 
 
 def topk(coeffs: np.ndarray, K: int) -> np.ndarray:
-    """Indices of the K largest joint norms (ties -> lower index), returned in ascending index order."""
+    """Indices of the K largest joint norms (ties -> lower index), returned in ascending index order.
+
+    With t the K-th largest value, that set is every index with v > t plus the lowest-index entries
+    with v == t until K are taken.
+    """
     v = joint_norm_f32(coeffs)
     M = v.shape[0]
     K = min(int(K), M)
-    order = np.lexsort((np.arange(M), -v))
+    if K == 0:
+        return np.zeros(0, dtype=np.int64)
+    t = np.partition(v, M - K)[M - K]
+    above = np.nonzero(v > t)[0]
+    ties = np.nonzero(v == t)[0][:K - above.size]
+    return np.sort(np.concatenate([above, ties])).astype(np.int64)
+
+
+def topk_bruteforce(coeffs: np.ndarray, K: int) -> np.ndarray:
+    """Same set by a full lexicographic sort on (-v, index); for small inputs."""
+    v = joint_norm_f32(coeffs)
+    order = np.lexsort((np.arange(v.shape[0]), -v))
     return np.sort(order[:K]).astype(np.int64)

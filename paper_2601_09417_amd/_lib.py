@@ -92,6 +92,8 @@ _SIGS = {
                                   vbm_gaussians, C.POINTER(vbm_adam_opts), C.c_void_p, C.c_void_p]),
     "vbm_dvr_render": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(vbm_tf), C.POINTER(vbm_view), C.c_int32,
                                    C.c_float, C.c_void_p, C.c_void_p]),
+    "vbm_profile_events": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vbm_profile_counters": (C.c_int32, [C.c_void_p]),
 }
 
 EXPORTS = tuple(_SIGS)

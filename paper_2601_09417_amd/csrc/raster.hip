@@ -28,6 +28,19 @@ __device__ __forceinline__ int find_view(const DevView* __restrict__ views, int 
   return lo;
 }
 
+// Measurement aid: adds the block's evaluated / contributing (pixel, Gaussian) counts to stats[0..1].
+__device__ __forceinline__ void add_stats(unsigned long long* stats, uint32_t n_eval, uint32_t n_used) {
+  unsigned long long e = n_eval, u = n_used;
+  for (int d = 32; d >= 1; d >>= 1) {
+    e += __shfl_xor(e, d, 64);
+    u += __shfl_xor(u, d, 64);
+  }
+  if (lane_id() == 0) {
+    atomicAdd(&stats[0], e);
+    atomicAdd(&stats[1], u);
+  }
+}
+
 template <int TILE>
 __global__ __launch_bounds__(TILE* TILE) void k_composite_fwd(const DevView* __restrict__ views, int n_views,
                                                                const uint2* __restrict__ ranges,
@@ -35,11 +48,13 @@ __global__ __launch_bounds__(TILE* TILE) void k_composite_fwd(const DevView* __r
                                                                const float4* __restrict__ rec,
                                                                const float* __restrict__ blue,
                                                                float* __restrict__ image, float* __restrict__ final_T,
-                                                               int32_t* __restrict__ n_contrib) {
+                                                               int32_t* __restrict__ n_contrib,
+                                                               unsigned long long* __restrict__ stats) {
   constexpr int NT = TILE * TILE;
   __shared__ float4 sA[NT];
   __shared__ float4 sB[NT];
   __shared__ float sBlue[NT];
+  uint32_t n_eval = 0, n_used = 0;
   const int tile = blockIdx.x;
   const DevView& v = views[find_view(views, n_views, tile)];
   const int local = tile - v.tile_offset;
@@ -69,6 +84,7 @@ __global__ __launch_bounds__(TILE* TILE) void k_composite_fwd(const DevView* __r
       const float4 b = sB[j];
       const float dx = a.x - fx, dy = a.y - fy;
       const float power = -0.5f * (a.z * dx * dx + b.x * dy * dy) - a.w * dx * dy;
+      ++n_eval;
       if (power > 0.0f) continue;
       const float alpha = fminf(kAlphaMax, b.y * __expf(power));
       if (alpha < kAlphaMin) continue;
@@ -83,8 +99,10 @@ __global__ __launch_bounds__(TILE* TILE) void k_composite_fwd(const DevView* __r
       cb += sBlue[j] * w;
       T = Tn;
       last = base + j - start + 1;
+      ++n_used;
     }
   }
+  if (stats) add_stats(stats, n_eval, n_used);
   if (inside) {
     const int64_t HW = static_cast<int64_t>(v.width) * v.height;
     const int64_t pix = static_cast<int64_t>(py) * v.width + px;
@@ -112,7 +130,9 @@ __global__ __launch_bounds__(TILE* TILE) void k_composite_bwd(const DevView* __r
                                                                const float* __restrict__ final_T,
                                                                const int32_t* __restrict__ n_contrib,
                                                                const float* __restrict__ dL_dimg,
-                                                               float* __restrict__ grad2d, int64_t n_items) {
+                                                               float* __restrict__ grad2d, int64_t n_items,
+                                                               unsigned long long* __restrict__ stats) {
+  uint32_t n_eval = 0, n_used = 0;
   constexpr int NT = TILE * TILE;
   __shared__ float4 sA[NT];
   __shared__ float4 sB[NT];
@@ -170,6 +190,7 @@ __global__ __launch_bounds__(TILE* TILE) void k_composite_bwd(const DevView* __r
       for (int k = 0; k < 9; ++k) g[k] = 0.0f;
       bool contrib = false;
       if (pos < nc) {
+        ++n_eval;
         const float4 a = sA[j];
         const float4 b = sB[j];
         const float dx = a.x - fx, dy = a.y - fy;
@@ -180,6 +201,7 @@ __global__ __launch_bounds__(TILE* TILE) void k_composite_bwd(const DevView* __r
           const float alpha = fminf(kAlphaMax, og);
           if (alpha >= kAlphaMin) {
             contrib = true;
+            ++n_used;
             T = T / (1.0f - alpha);
             accr = last_a * last_r + (1.0f - last_a) * accr;
             accg = last_a * last_g + (1.0f - last_a) * accg;
@@ -226,14 +248,15 @@ __global__ __launch_bounds__(TILE* TILE) void k_composite_bwd(const DevView* __r
       }
     }
   }
+  if (stats) add_stats(stats, n_eval, n_used);
 }
 
 template <int TILE>
 static vbm_status launch_fwd_t(const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
                                const uint32_t* pair_item, const float4* rec, const float* blue, float* image,
-                               float* final_T, int32_t* n_contrib, hipStream_t s) {
+                               float* final_T, int32_t* n_contrib, unsigned long long* stats, hipStream_t s) {
   hipLaunchKernelGGL(k_composite_fwd<TILE>, dim3(n_tiles), dim3(TILE * TILE), 0, s, views, n_views, ranges, pair_item,
-                     rec, blue, image, final_T, n_contrib);
+                     rec, blue, image, final_T, n_contrib, stats);
   VBM_LAUNCH_CHECK("composite_fwd");
   return VBM_OK;
 }
@@ -242,20 +265,20 @@ template <int TILE>
 static vbm_status launch_bwd_t(const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
                                const uint32_t* pair_item, const float4* rec, const float* blue, const float* final_T,
                                const int32_t* n_contrib, const float* dL_dimg, float* grad2d, int64_t n_items,
-                               hipStream_t s) {
+                               unsigned long long* stats, hipStream_t s) {
   hipLaunchKernelGGL(k_composite_bwd<TILE>, dim3(n_tiles), dim3(TILE * TILE), 0, s, views, n_views, ranges, pair_item,
-                     rec, blue, final_T, n_contrib, dL_dimg, grad2d, n_items);
+                     rec, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats);
   VBM_LAUNCH_CHECK("composite_bwd");
   return VBM_OK;
 }
 
 vbm_status launch_composite_fwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
                                 const uint32_t* pair_item, const float4* rec, const float* blue, float* image,
-                                float* final_T, int32_t* n_contrib, hipStream_t s) {
+                                float* final_T, int32_t* n_contrib, unsigned long long* stats, hipStream_t s) {
   switch (tile) {
-    case 8: return launch_fwd_t<8>(views, n_views, n_tiles, ranges, pair_item, rec, blue, image, final_T, n_contrib, s);
-    case 16: return launch_fwd_t<16>(views, n_views, n_tiles, ranges, pair_item, rec, blue, image, final_T, n_contrib, s);
-    case 32: return launch_fwd_t<32>(views, n_views, n_tiles, ranges, pair_item, rec, blue, image, final_T, n_contrib, s);
+    case 8: return launch_fwd_t<8>(views, n_views, n_tiles, ranges, pair_item, rec, blue, image, final_T, n_contrib, stats, s);
+    case 16: return launch_fwd_t<16>(views, n_views, n_tiles, ranges, pair_item, rec, blue, image, final_T, n_contrib, stats, s);
+    case 32: return launch_fwd_t<32>(views, n_views, n_tiles, ranges, pair_item, rec, blue, image, final_T, n_contrib, stats, s);
   }
   set_error("unsupported tile size %d", tile);
   return VBM_ERR_UNSUPPORTED;
@@ -264,11 +287,11 @@ vbm_status launch_composite_fwd(int tile, const DevView* views, int n_views, int
 vbm_status launch_composite_bwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
                                 const uint32_t* pair_item, const float4* rec, const float* blue, const float* final_T,
                                 const int32_t* n_contrib, const float* dL_dimg, float* grad2d, int64_t n_items,
-                                hipStream_t s) {
+                                unsigned long long* stats, hipStream_t s) {
   switch (tile) {
-    case 8: return launch_bwd_t<8>(views, n_views, n_tiles, ranges, pair_item, rec, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, s);
-    case 16: return launch_bwd_t<16>(views, n_views, n_tiles, ranges, pair_item, rec, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, s);
-    case 32: return launch_bwd_t<32>(views, n_views, n_tiles, ranges, pair_item, rec, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, s);
+    case 8: return launch_bwd_t<8>(views, n_views, n_tiles, ranges, pair_item, rec, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s);
+    case 16: return launch_bwd_t<16>(views, n_views, n_tiles, ranges, pair_item, rec, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s);
+    case 32: return launch_bwd_t<32>(views, n_views, n_tiles, ranges, pair_item, rec, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s);
   }
   set_error("unsupported tile size %d", tile);
   return VBM_ERR_UNSUPPORTED;

@@ -31,11 +31,11 @@ __global__ void k_project_bwd(const DevView*, int, const DevScene*, int, vbm_gau
                               const uint32_t*, vbm_gaussians, int, int64_t);
 vbm_status launch_composite_fwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
                                 const uint32_t* pair_item, const float4* rec, const float* blue, float* image,
-                                float* final_T, int32_t* n_contrib, hipStream_t s);
+                                float* final_T, int32_t* n_contrib, unsigned long long* stats, hipStream_t s);
 vbm_status launch_composite_bwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
                                 const uint32_t* pair_item, const float4* rec, const float* blue, const float* final_T,
                                 const int32_t* n_contrib, const float* dL_dimg, float* grad2d, int64_t n_items,
-                                hipStream_t s);
+                                unsigned long long* stats, hipStream_t s);
 
 namespace {
 
@@ -148,6 +148,15 @@ vbm_status check_plan(const vbm_plan* p, const void* views, void* ws, size_t ws_
 int grid_cap(int64_t n, int64_t cap) {
   int64_t b = ceil_div(n > 0 ? n : 1, 256);
   return static_cast<int>(b < cap ? b : cap);
+}
+
+// Events recorded around the compositing launches when set (see vbm_profile_events).
+hipEvent_t g_prof[4] = {nullptr, nullptr, nullptr, nullptr};
+unsigned long long* g_stats = nullptr;  // device [4]: fwd evaluated, fwd contributing, bwd evaluated, bwd contributing
+
+vbm_status record(int which, hipStream_t s) {
+  if (!g_prof[which]) return VBM_OK;
+  return hip_check(hipEventRecord(g_prof[which], s), "profile event record");
 }
 
 }  // namespace
@@ -343,8 +352,10 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
     hipLaunchKernelGGL(k_ranges, dim3(grid_cap(pair_n, 16384)), dim3(256), 0, s, pt[0], counters, cap, ranges);
     VBM_LAUNCH_CHECK("ranges");
   }
+  VBM_TRY(record(0, s));
   VBM_TRY(launch_composite_fwd(p->tile, views, p->n_views, p->n_tiles, ranges, pi[0], rec, blue, image, final_T,
-                               n_contrib, s));
+                               n_contrib, g_stats, s));
+  VBM_TRY(record(1, s));
   hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, s, counters, status);
   VBM_LAUNCH_CHECK("status");
   return VBM_OK;
@@ -372,14 +383,30 @@ extern "C" vbm_status vbm_render_bwd(const vbm_plan* p, const void* view_table, 
   const int64_t I = p->n_items;
   float* grad2d = region<float>(p, ws, R_GRAD2D);
   VBM_TRY(fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, 9 * I, s));
+  VBM_TRY(record(2, s));
   VBM_TRY(launch_composite_bwd(p->tile, views, p->n_views, p->n_tiles, region<uint2>(p, ws, R_RANGES),
                                region<uint32_t>(p, ws, R_PITEM), region<float4>(p, ws, R_REC),
-                               region<float>(p, ws, R_BLUE), final_T, n_contrib, dL_dimg, grad2d, I, s));
+                               region<float>(p, ws, R_BLUE), final_T, n_contrib, dL_dimg, grad2d, I,
+                               g_stats ? g_stats + 2 : nullptr, s));
+  VBM_TRY(record(3, s));
   if (p->n_gaussians > 0) {
     hipLaunchKernelGGL(k_project_bwd, dim3(ceil_div(p->n_gaussians, 256)), dim3(256), 0, s, views, p->n_views, scenes,
                        p->n_scenes, g, grad2d, I, region<uint32_t>(p, ws, R_NTILES), grads, accumulate,
                        p->n_gaussians);
     VBM_LAUNCH_CHECK("project_bwd");
   }
+  return VBM_OK;
+}
+
+extern "C" vbm_status vbm_profile_events(void* fwd_begin, void* fwd_end, void* bwd_begin, void* bwd_end) {
+  vbm::g_prof[0] = static_cast<hipEvent_t>(fwd_begin);
+  vbm::g_prof[1] = static_cast<hipEvent_t>(fwd_end);
+  vbm::g_prof[2] = static_cast<hipEvent_t>(bwd_begin);
+  vbm::g_prof[3] = static_cast<hipEvent_t>(bwd_end);
+  return VBM_OK;
+}
+
+extern "C" vbm_status vbm_profile_counters(void* dev_counters) {
+  vbm::g_stats = static_cast<unsigned long long*>(dev_counters);
   return VBM_OK;
 }

@@ -103,6 +103,9 @@ def test_select_topk_bruteforce_with_ties():
     thr = float(v[ranked[K - 1]])
     tied = [i for i in range(500) if float(v[i]) == thr]
     assert all((i in kept) == (i in ranked[:K]) for i in tied)
+    assert np.array_equal(kept, select.topk_bruteforce(c, K))
+    for K2 in (1, 99, 100, 101, 499, 500):
+        assert np.array_equal(select.topk(c, K2), select.topk_bruteforce(c, K2))
 
 
 def test_joint_norm_is_float32_fixed_order():
