@@ -334,6 +334,7 @@ def main() -> int:
         "pairs_per_step": gpu["pairs_per_step"],
         "init_ms": round(gpu["init_ms"], 2),
         "kernels_ms": {n: round(d["ms"], 3) for n, d in gpu["kernels"].items()},
+        "composite_evals": {n: [int(d["evals"]), int(d["contrib"])] for n, d in gpu["kernels"].items()},
         "roofline": {
             "bound": "alu",
             "kernel": "composite_bwd",
