@@ -14,6 +14,13 @@ identically bit for bit.  The reading of the cited rasteriser used throughout:
   radius           r = ceil(3 sqrt(lambda_max)), lambda_max = mid + sqrt(max(0.1, mid^2 - det))
   pixel centre     mean2d = (fx X/Z + cx, fy Y/Z + cy); pixel (i, j) samples (i + 0.5, j + 0.5)
   tile rectangle   x0 = clamp(floor((px - r)/T), 0, TX), x1 = clamp(floor((px + r)/T) + 1, 0, TX)
+  footprint        a pixel gets alpha = o exp(-q/2) >= 1/255 only where q = d^T Sigma2^-1 d <= 2 ln(255 o);
+                   a Gaussian with o < 1/255 is dropped, and a tile of the rectangle is kept only when the
+                   minimum of q over the rectangle of its pixel centres is <= tau, an upper bound of
+                   2 ln(255 o) computed without transcendental functions:
+                   tau = 2 * 32 (x^(1/32) - 1) * 1.01 + 0.01, x = 255 o (ln x <= n (x^(1/n) - 1)).
+                   Dropped pairs are exactly those whose alpha stays below 1/255 at every pixel of the
+                   tile, so the rendered image does not change.
   pair order       ascending (global tile, depth bits as u32, item index)
 """
 from __future__ import annotations
@@ -22,6 +29,38 @@ import numpy as np
 
 f32 = np.float32
 ONE, TWO, HALF, DIL, LIMK, THREE, EIGMIN = f32(1), f32(2), f32(0.5), f32(0.3), f32(1.3), f32(3), f32(0.1)
+ALPHA_MIN32 = f32(1) / f32(255)
+
+
+def footprint_tau(o):
+    """float32 upper bound of 2 ln(255 o) (five square roots, no transcendental function)."""
+    y = f32(255) * np.asarray(o, dtype=f32)
+    for _ in range(5):
+        y = np.sqrt(y)
+    u = f32(32) * (y - ONE)
+    return (TWO * u) * f32(1.01) + f32(0.01)
+
+
+def tile_reached(mx, my, A, B, C, tau, tx, ty, T, W, H):
+    """Vectorised float32 test: does {q <= tau} reach a pixel centre of tile (tx, ty)?"""
+    X0 = (tx * T).astype(f32) + HALF
+    X1 = np.minimum((tx + 1) * T, W).astype(f32) - HALF
+    Y0 = (ty * T).astype(f32) + HALF
+    Y1 = np.minimum((ty + 1) * T, H).astype(f32) - HALF
+    dx0, dx1, dy0, dy1 = X0 - mx, X1 - mx, Y0 - my, Y1 - my
+    inside = (dx0 <= 0) & (dx1 >= 0) & (dy0 <= 0) & (dy1 >= 0)
+    B2 = TWO * B
+
+    def q(dx, dy):
+        return ((A * dx) * dx + (B2 * dx) * dy) + (C * dy) * dy
+
+    with np.errstate(all="ignore"):
+        ya = np.minimum(np.maximum(-((B * dx0) / C), dy0), dy1)
+        yb = np.minimum(np.maximum(-((B * dx1) / C), dy0), dy1)
+        xa = np.minimum(np.maximum(-((B * dy0) / A), dx0), dx1)
+        xb = np.minimum(np.maximum(-((B * dy1) / A), dx0), dx1)
+        qm = np.minimum(np.minimum(q(dx0, ya), q(dx1, yb)), np.minimum(q(xa, dy0), q(xb, dy1)))
+    return inside | (qm <= tau)
 
 
 def _rot_f32(qw, qx, qy, qz):
@@ -36,7 +75,7 @@ def _rot_f32(qw, qx, qy, qz):
             [TWO * (xz - wy), TWO * (yz + wx), ONE - TWO * (xx + yy)]]
 
 
-def project_fp32(means, scales, quats, cam, tile: int) -> dict:
+def project_fp32(means, scales, quats, cam, tile: int, opacity=None) -> dict:
     """Per-Gaussian float32 projection decisions for one camera.
 
     means/scales [3][N], quats [4][N] float32.  Returns depth (float32), rect x0, y0, x1, y1 (int64),
@@ -88,13 +127,33 @@ def project_fp32(means, scales, quats, cam, tile: int) -> dict:
         y0 = np.minimum(np.maximum(np.floor((py - r) / Tf), f32(0)), f32(TY))
         y1 = np.minimum(np.maximum(np.floor((py + r) / Tf) + ONE, f32(0)), f32(TY))
         vis &= np.isfinite(px) & np.isfinite(py) & np.isfinite(r)
+        ca, cb, cc = c / det, -(b / det), a / det
+        if opacity is not None:
+            op = np.asarray(opacity, dtype=f32)
+            vis &= op >= ALPHA_MIN32
     x0 = np.where(vis, x0, 0).astype(np.int64)
     x1 = np.where(vis, x1, 0).astype(np.int64)
     y0 = np.where(vis, y0, 0).astype(np.int64)
     y1 = np.where(vis, y1, 0).astype(np.int64)
-    n_tiles = np.where(vis, (x1 - x0) * (y1 - y0), 0)
+    rect_tiles = np.where(vis, (x1 - x0) * (y1 - y0), 0)
+    reached = None
+    if opacity is not None:
+        # expand every rectangle tile, keep those the opacity-aware footprint reaches
+        gidx = np.nonzero(rect_tiles > 0)[0]
+        cnt = rect_tiles[gidx]
+        rep = np.repeat(gidx, cnt)
+        start = np.concatenate([[0], np.cumsum(cnt)[:-1]]) if cnt.size else np.zeros(0, np.int64)
+        local = np.arange(rep.size) - np.repeat(start, cnt)
+        w = (x1 - x0)[rep]
+        tx = x0[rep] + local % np.maximum(w, 1)
+        ty = y0[rep] + local // np.maximum(w, 1)
+        keep = tile_reached(px[rep], py[rep], ca[rep], cb[rep], cc[rep], footprint_tau(op)[rep], tx, ty, T, W, H)
+        reached = (rep[keep], tx[keep], ty[keep])
+        n_tiles = np.bincount(rep[keep], minlength=x0.shape[0]).astype(np.int64)
+    else:
+        n_tiles = rect_tiles
     return dict(depth=Zc.astype(f32), x0=x0, y0=y0, x1=x1, y1=y1, n_tiles=n_tiles, radius=r, px=px, py=py,
-                a=a, b=b, c=c, visible=vis & (n_tiles > 0), TX=TX, TY=TY)
+                a=a, b=b, c=c, conic=(ca, cb, cc), visible=vis & (n_tiles > 0), TX=TX, TY=TY, reached=reached)
 
 
 def tile_grid(cams, tile: int):
@@ -115,8 +174,8 @@ def pair_lists(gs, cams, tile: int, view_scene=None, scene_offsets=None) -> dict
     gs: dict/obj with float32 means, scales, quats ([3|4][N]); views reference scenes through
     ``view_scene`` (default: every view sees scene 0 = all Gaussians).
     """
-    means, scales, quats = (np.asarray(getattr(gs, k) if hasattr(gs, k) else gs[k], dtype=f32)
-                            for k in ("means", "scales", "quats"))
+    means, scales, quats, opacity = (np.asarray(getattr(gs, k) if hasattr(gs, k) else gs[k], dtype=f32)
+                                     for k in ("means", "scales", "quats", "opacity"))
     N = means.shape[1]
     if view_scene is None:
         view_scene = [0] * len(cams)
@@ -126,19 +185,11 @@ def pair_lists(gs, cams, tile: int, view_scene=None, scene_offsets=None) -> dict
     keys_t, keys_d, items, projs = [], [], [], []
     for v, cam in enumerate(cams):
         s0, s1 = scene_offsets[view_scene[v]], scene_offsets[view_scene[v] + 1]
-        pr = project_fp32(means[:, s0:s1], scales[:, s0:s1], quats[:, s0:s1], cam, tile)
+        pr = project_fp32(means[:, s0:s1], scales[:, s0:s1], quats[:, s0:s1], cam, tile, opacity[s0:s1])
         projs.append(pr)
-        nt = pr["n_tiles"]
-        gidx = np.nonzero(nt > 0)[0]
-        if gidx.size == 0:
+        rep, tx, ty = pr["reached"]
+        if rep.size == 0:
             continue
-        cnt = nt[gidx]
-        rep = np.repeat(gidx, cnt)
-        start = np.concatenate([[0], np.cumsum(cnt)[:-1]])
-        local = np.arange(rep.size) - np.repeat(start, cnt)
-        w = (pr["x1"] - pr["x0"])[rep]
-        tx = pr["x0"][rep] + local % w
-        ty = pr["y0"][rep] + local // w
         keys_t.append(toff[v] + ty * pr["TX"] + tx)
         keys_d.append(pr["depth"][rep].view(np.uint32).astype(np.int64))
         items.append(ioff[v] + rep)

@@ -43,8 +43,50 @@ __device__ __forceinline__ void rot_from_quat(float qw, float qx, float qy, floa
   Rq[2][2] = 1.0f - 2.0f * (xx + yy);
 }
 
+// Opacity-aware footprint.  A pixel receives alpha = o exp(-q/2) >= 1/255 only where
+// q = d^T Sigma2^-1 d <= 2 ln(255 o).  tau bounds that from above without transcendental functions,
+// ln x <= 32 (x^(1/32) - 1) (five correctly rounded square roots), widened by 1% and 0.01 to absorb
+// the float32 evaluation error of the compositing kernels; a Gaussian with o < 1/255 reaches nothing.
+__device__ __forceinline__ float footprint_tau(float o) {
+  float y = 255.0f * o;
+  y = __fsqrt_rn(y);
+  y = __fsqrt_rn(y);
+  y = __fsqrt_rn(y);
+  y = __fsqrt_rn(y);
+  y = __fsqrt_rn(y);
+  const float u = 32.0f * (y - 1.0f);
+  return (2.0f * u) * 1.01f + 0.01f;
+}
+
+__device__ __forceinline__ float quad_form(float A, float B2, float C, float dx, float dy) {
+  return ((A * dx) * dx + (B2 * dx) * dy) + (C * dy) * dy;
+}
+
+// True when the footprint {q <= tau} can reach a pixel centre of the tile (tx, ty): the minimum of
+// q over the rectangle spanned by the tile's pixel centres (clipped to the image) is <= tau.  The
+// minimum is 0 with the centre inside; otherwise it lies on one of the four edges, where q is a
+// 1D quadratic minimised at a clamped stationary point.
+__device__ __forceinline__ bool tile_reached(float mx, float my, float A, float B, float C, float tau, int tx,
+                                             int ty, int tile, int W, int H) {
+  const float X0 = static_cast<float>(tx * tile) + 0.5f;
+  const float X1 = static_cast<float>(min((tx + 1) * tile, W)) - 0.5f;
+  const float Y0 = static_cast<float>(ty * tile) + 0.5f;
+  const float Y1 = static_cast<float>(min((ty + 1) * tile, H)) - 0.5f;
+  const float dx0 = X0 - mx, dx1 = X1 - mx, dy0 = Y0 - my, dy1 = Y1 - my;
+  if (dx0 <= 0.0f && dx1 >= 0.0f && dy0 <= 0.0f && dy1 >= 0.0f) return true;
+  const float B2 = 2.0f * B;
+  const float ya = fminf(fmaxf(-__fdiv_rn(B * dx0, C), dy0), dy1);
+  const float yb = fminf(fmaxf(-__fdiv_rn(B * dx1, C), dy0), dy1);
+  const float xa = fminf(fmaxf(-__fdiv_rn(B * dy0, A), dx0), dx1);
+  const float xb = fminf(fmaxf(-__fdiv_rn(B * dy1, A), dx0), dx1);
+  const float q = fminf(fminf(quad_form(A, B2, C, dx0, ya), quad_form(A, B2, C, dx1, yb)),
+                        fminf(quad_form(A, B2, C, xa, dy0), quad_form(A, B2, C, xb, dy1)));
+  return q <= tau;
+}
+
 __device__ __forceinline__ ProjResult project_one(const DevView& v, int tile, float mx, float my, float mz, float sx,
-                                                  float sy, float sz, float qw, float qx, float qy, float qz) {
+                                                  float sy, float sz, float qw, float qx, float qy, float qz,
+                                                  float opacity) {
   ProjResult o;
   const float* R = v.R;
   const float Xc = ((R[0] * mx + R[1] * my) + R[2] * mz) + v.t[0];
@@ -98,7 +140,7 @@ __device__ __forceinline__ ProjResult project_one(const DevView& v, int tile, fl
   const float fx1 = fminf(fmaxf(floorf(__fdiv_rn(px + r, Tf)) + 1.0f, 0.0f), static_cast<float>(v.tiles_x));
   const float fy0 = fminf(fmaxf(floorf(__fdiv_rn(py - r, Tf)), 0.0f), static_cast<float>(v.tiles_y));
   const float fy1 = fminf(fmaxf(floorf(__fdiv_rn(py + r, Tf)) + 1.0f, 0.0f), static_cast<float>(v.tiles_y));
-  vis = vis && isfinite(px) && isfinite(py) && isfinite(r);
+  vis = vis && isfinite(px) && isfinite(py) && isfinite(r) && opacity >= 1.0f / 255.0f;
   o.x0 = vis ? static_cast<uint32_t>(fx0) : 0u;
   o.x1 = vis ? static_cast<uint32_t>(fx1) : 0u;
   o.y0 = vis ? static_cast<uint32_t>(fy0) : 0u;
@@ -126,17 +168,27 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
   const int64_t gi = v.gauss_offset + i;
   const int64_t item = v.item_offset + i;
   const int64_t S = g.stride;
+  const float op = g.opacity[gi];
   const ProjResult p = project_one(v, tile, g.means[gi], g.means[S + gi], g.means[2 * S + gi], g.scales[gi],
                                    g.scales[S + gi], g.scales[2 * S + gi], g.quats[gi], g.quats[S + gi],
-                                   g.quats[2 * S + gi], g.quats[3 * S + gi]);
-  const uint32_t nt = p.visible ? (p.x1 - p.x0) * (p.y1 - p.y0) : 0u;
+                                   g.quats[2 * S + gi], g.quats[3 * S + gi], op);
+  uint32_t nt = 0;
+  if (p.visible) {
+    const float tau = footprint_tau(op);
+    for (uint32_t ty = p.y0; ty < p.y1; ++ty)
+      for (uint32_t tx = p.x0; tx < p.x1; ++tx)
+        nt += tile_reached(p.px, p.py, p.ca, p.cb, p.cc, tau, static_cast<int>(tx), static_cast<int>(ty), tile,
+                           v.width, v.height)
+                  ? 1u
+                  : 0u;
+  }
   depth[item] = p.visible ? p.depth : 0.0f;
   rect[item] = p.x0 | (p.x1 << 16);
   rect[n_items + item] = p.y0 | (p.y1 << 16);
   ntiles[item] = nt;
   vis_flag[item] = nt ? 1u : 0u;
   rec[2 * item] = make_float4(p.px, p.py, p.ca, p.cb);
-  rec[2 * item + 1] = make_float4(p.cc, g.opacity[gi], g.rgb[gi], g.rgb[S + gi]);
+  rec[2 * item + 1] = make_float4(p.cc, op, g.rgb[gi], g.rgb[S + gi]);
   blue[item] = g.rgb[2 * S + gi];
 }
 
@@ -170,9 +222,10 @@ __global__ __launch_bounds__(256) void k_gather_ntiles(const uint32_t* __restric
 // dropped and flagged.
 __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views, const uint64_t* __restrict__ keys,
                                               const uint32_t* __restrict__ vals, const uint32_t* __restrict__ offs,
-                                              const uint32_t* __restrict__ rect, int64_t n_items,
-                                              uint32_t* __restrict__ counters, int64_t n_max, int64_t capacity,
-                                              uint32_t* __restrict__ pair_tile, uint32_t* __restrict__ pair_item) {
+                                              const uint32_t* __restrict__ rect, const float4* __restrict__ rec,
+                                              int tile, int64_t n_items, uint32_t* __restrict__ counters,
+                                              int64_t n_max, int64_t capacity, uint32_t* __restrict__ pair_tile,
+                                              uint32_t* __restrict__ pair_item) {
   const int64_t n = min(static_cast<int64_t>(counters[0]), n_max);
   for (int64_t p = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; p < n;
        p += static_cast<int64_t>(gridDim.x) * 256) {
@@ -180,10 +233,16 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
     const DevView& v = views[keys[p] >> 32];
     const uint32_t rx = rect[item], ry = rect[n_items + item];
     const uint32_t x0 = rx & 0xFFFFu, x1 = rx >> 16, y0 = ry & 0xFFFFu, y1 = ry >> 16;
+    const float4 ra = rec[2 * static_cast<int64_t>(item)];
+    const float4 rb = rec[2 * static_cast<int64_t>(item) + 1];
+    const float tau = footprint_tau(rb.y);
     int64_t o = offs[p];
     bool over = false;
     for (uint32_t ty = y0; ty < y1; ++ty)
       for (uint32_t tx = x0; tx < x1; ++tx) {
+        if (!tile_reached(ra.x, ra.y, ra.z, ra.w, rb.x, tau, static_cast<int>(tx), static_cast<int>(ty), tile, v.width,
+                          v.height))
+          continue;
         if (o < capacity) {
           pair_tile[o] = static_cast<uint32_t>(v.tile_offset) + ty * static_cast<uint32_t>(v.tiles_x) + tx;
           pair_item[o] = item;

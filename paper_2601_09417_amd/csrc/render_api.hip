@@ -23,8 +23,8 @@ __global__ void k_project(const DevView*, int, vbm_gaussians_c, float*, uint32_t
 __global__ void k_compact_visible(const DevView*, const uint32_t*, const float*, const uint32_t*, uint64_t*,
                                   uint32_t*);
 __global__ void k_gather_ntiles(const uint32_t*, const uint32_t*, const uint32_t*, int64_t, uint32_t*);
-__global__ void k_emit(const DevView*, const uint64_t*, const uint32_t*, const uint32_t*, const uint32_t*, int64_t,
-                       uint32_t*, int64_t, int64_t, uint32_t*, uint32_t*);
+__global__ void k_emit(const DevView*, const uint64_t*, const uint32_t*, const uint32_t*, const uint32_t*,
+                       const float4*, int, int64_t, uint32_t*, int64_t, int64_t, uint32_t*, uint32_t*);
 __global__ void k_ranges(const uint32_t*, const uint32_t*, int64_t, uint2*);
 __global__ void k_status(const uint32_t*, int32_t*);
 __global__ void k_project_bwd(const DevView*, int, const DevScene*, int, vbm_gaussians_c, const float*, int64_t,
@@ -339,7 +339,7 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
   const int pfirst = tile_passes % 2;
   if (I > 0 && emit_grid_n > 0) {
     hipLaunchKernelGGL(k_emit, dim3(grid_cap(emit_grid_n, 16384)), dim3(256), 0, s, views, vk[0], vv[0], poffs, rect,
-                       I, counters, I, cap, pt[pfirst], pi[pfirst]);
+                       rec, p->tile, I, counters, I, cap, pt[pfirst], pi[pfirst]);
     VBM_LAUNCH_CHECK("emit");
   }
   if (pair_n > 0) {

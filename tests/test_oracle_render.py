@@ -80,14 +80,38 @@ def test_tiled_equals_bruteforce_per_pixel():
         for _ in range(60):
             x, y = int(rng.integers(cam.width)), int(rng.integers(cam.height))
             tx, ty = x // 16, y // 16
-            cand = [g for g in range(gs.n) if pr["n_tiles"][g] > 0 and pr["x0"][g] <= tx < pr["x1"][g]
-                    and pr["y0"][g] <= ty < pr["y1"][g]]
+            rep, rtx, rty = pr["reached"]
+            cand = [int(g) for g in rep[(rtx == tx) & (rty == ty)]]
             cand.sort(key=lambda g: (int(pr["depth"][g:g + 1].view(np.uint32)[0]), g))
             items = [ioff + g for g in cand]
             col, T, nc = render.composite_pixel_bruteforce(x + 0.5, y + 0.5, items, m2d, con, op, rgb, cam.bg)
             assert np.abs(np.array(col) - out[v]["image"][:, y, x]).max() <= 1e-12
             assert abs(T - out[v]["final_T"][y, x]) <= 1e-12
             assert nc == out[v]["n_contrib"][y, x]
+
+
+def test_footprint_culling_drops_only_non_contributing_pairs():
+    """Compositing over the full 3-sigma rectangles (no footprint test) gives the same image: every
+    dropped (tile, Gaussian) pair has alpha < 1/255 at all pixels of its tile."""
+    gs, cams = _scene(n=300, seed=12)
+    gs.opacity[:] = np.linspace(0.001, 0.9, gs.n).astype(np.float32)
+    b = render.Batch(gs, cams[:1], 16)
+    out = render.render_forward(b)[0]
+    P = b.leaf_params()
+    m2d, con, op, rgb = (t.detach().numpy() for t in b.project_items(P))
+    pr = binning.project_fp32(gs.means, gs.scales, gs.quats, cams[0], 16)      # no opacity: full rectangles
+    dropped = int(pr["n_tiles"].sum()) - int(b.pairs["tile"].size)
+    assert dropped > 0
+    cam = cams[0]
+    for y in range(0, cam.height, 3):
+        for x in range(0, cam.width, 3):
+            tx, ty = x // 16, y // 16
+            cand = [g for g in range(gs.n) if pr["n_tiles"][g] > 0 and pr["x0"][g] <= tx < pr["x1"][g]
+                    and pr["y0"][g] <= ty < pr["y1"][g]]
+            cand.sort(key=lambda g: (int(pr["depth"][g:g + 1].view(np.uint32)[0]), g))
+            col, T, _ = render.composite_pixel_bruteforce(x + 0.5, y + 0.5, cand, m2d, con, op, rgb, cam.bg)
+            assert np.abs(np.array(col) - out["image"][:, y, x]).max() <= 1e-12
+            assert abs(T - out["final_T"][y, x]) <= 1e-12
 
 
 def test_pair_list_invariants():
@@ -201,3 +225,12 @@ def test_gradient_matches_central_differences():
             assert abs(fd - grads[key][idx]) <= 1e-6 * scale, (key, idx, fd, grads[key][idx])
             checked += 1
     assert checked >= 25
+
+
+def test_footprint_threshold_bounds_the_log():
+    """tau(o) >= 2 ln(255 o) with margin for every representable opacity in [1/255, 1]."""
+    o = np.linspace(1 / 255, 1.0, 200001).astype(np.float32)
+    o = o[o >= binning.ALPHA_MIN32]
+    tau = binning.footprint_tau(o).astype(np.float64)
+    exact = 2 * np.log(255 * o.astype(np.float64))
+    assert np.all(tau >= exact * 1.005 + 0.005)
