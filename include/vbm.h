@@ -185,7 +185,7 @@ typedef struct {
 typedef struct {
   int32_t tile;          /* tile edge in pixels: 8, 16 or 32 */
   int32_t sort_bits;     /* radix digit width for the tile sort: 4..8 */
-  int64_t pair_capacity; /* pair slots reserved in the workspace (> 0) */
+  int64_t pair_capacity; /* pair slots reserved in the workspace, in [1, 2^30) */
   int32_t mode;          /* VBM_MODE_BATCHED or VBM_MODE_EXACT */
   int32_t pad;
 } vbm_schedule;
@@ -211,11 +211,17 @@ typedef struct {
 #define VBM_REGION_PAIR_TILE 6   /* uint32 [pair_capacity]: sorted global tile of each pair */
 #define VBM_REGION_PAIR_ITEM 7   /* uint32 [pair_capacity]: sorted item of each pair */
 #define VBM_REGION_RANGES 8      /* uint32 [n_tiles][2]: [start, end) of each tile's list */
-#define VBM_REGION_GRAD2D 9      /* float32 [9][n_items]: dmean2d.xy, dconic.abc, dopacity, drgb */
+#define VBM_REGION_GRAD2D 9      /* float32 [9][n_items]: dmean2d.xy, dconic.abc, dopacity, drgb
+                                  * (after vbm_render_bwd; rows of items never binned stay 0) */
+#define VBM_REGION_ITEM_COEF 19  /* float32 [n_items][8]: compositing record mean2d.xy, -A/2 log2e,
+                                  * -B log2e, -C/2 log2e, log2(opacity), r, g (conic A, B, C) */
 
 /* Plans a batch (host only).  scene_offsets_host is int64 [n_scenes + 1].  If view_table_host
  * is not NULL it receives plan->view_table_bytes bytes that the caller copies to the device and
- * passes as view_table_dev.  Item i of view v is Gaussian scene_offsets[scene_v] + (i - item_offset_v). */
+ * passes as view_table_dev.  Item i of view v is Gaussian scene_offsets[scene_v] + (i - item_offset_v).
+ * Limits (VBM_ERR_INVALID beyond them): 1..4096 views and scenes, images up to 16384 x 16384, fewer
+ * than 2^27 items (sum over views of the scene's Gaussian count) and 2^31 tiles, Gaussians and image
+ * values in the batch. */
 vbm_status vbm_plan_make(const vbm_view* views_host, int32_t n_views, const int64_t* scene_offsets_host,
                          int32_t n_scenes, const vbm_schedule* sched_host, vbm_plan* plan_out,
                          void* view_table_host);

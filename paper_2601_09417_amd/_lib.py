@@ -13,7 +13,7 @@ VBM_WS_REGIONS = 24
 MODE_BATCHED, MODE_EXACT = 0, 1
 WAVELETS = {"haar": 0, "bior4.4": 1}
 REGION = dict(counters=0, item_depth=1, item_rect=2, item_ntiles=3, item_rec=4, item_blue=5, pair_tile=6,
-              pair_item=7, ranges=8, grad2d=9)
+              pair_item=7, ranges=8, grad2d=9, item_coef=19)
 STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "workspace too small", -4: "HIP error",
           -5: "capacity exceeded"}
 

@@ -160,8 +160,8 @@ __device__ __forceinline__ ProjResult project_one(const DevView& v, int tile, fl
 __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ views, int tile, vbm_gaussians_c g,
                                                  float* __restrict__ depth, uint32_t* __restrict__ rect,
                                                  uint32_t* __restrict__ ntiles, float4* __restrict__ rec,
-                                                 float* __restrict__ blue, uint32_t* __restrict__ vis_flag,
-                                                 int64_t n_items) {
+                                                 float4* __restrict__ coef, float* __restrict__ blue,
+                                                 uint32_t* __restrict__ vis_flag, int64_t n_items) {
   const DevView& v = views[blockIdx.y];
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= v.n_gauss) return;
@@ -189,6 +189,11 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
   vis_flag[item] = nt ? 1u : 0u;
   rec[2 * item] = make_float4(p.px, p.py, p.ca, p.cb);
   rec[2 * item + 1] = make_float4(p.cc, op, g.rgb[gi], g.rgb[S + gi]);
+  // Compositing record: the exponent in base 2 with log2(opacity) folded in,
+  // e2 = hA dx^2 + hB dx dy + hC dy^2 + log2(o) = log2(o) - (A dx^2 + 2 B dx dy + C dy^2) log2(e) / 2.
+  constexpr float kLog2e = 1.44269504088896341f;
+  coef[2 * item] = make_float4(p.px, p.py, (-0.5f * kLog2e) * p.ca, -kLog2e * p.cb);
+  coef[2 * item + 1] = make_float4((-0.5f * kLog2e) * p.cc, p.visible ? __log2f(op) : 0.0f, g.rgb[gi], g.rgb[S + gi]);
   blue[item] = g.rgb[2 * S + gi];
 }
 
@@ -378,11 +383,30 @@ __device__ __forceinline__ void project_bwd_one(const DevView& v, const float m[
   for (int i = 0; i < 4; ++i) dq[i] = (dqn[i] - qn[i] * dot) / nq;
 }
 
+// The compositing backward leaves per item the moments of dL/dpower over the pixels it reached
+// (sum dx dp, sum dp dy, sum dx^2 dp, sum dx dp dy, sum dp dy^2, sum dp; d = mean2d - pixel) and
+// the colour gradient.  power = -(A dx^2 + 2 B dx dy + C dy^2) / 2 and alpha = o exp(power) make
+// the 2D gradients linear in them:
+//   dmean.x = -(A m0 + B m1), dmean.y = -(B m0 + C m1), dA = -m2 / 2, dB = -m3, dC = -m4 / 2,
+//   dopacity = m5 / o.
+// They are written back in place, so the region holds the 2D gradients afterwards.
+__device__ __forceinline__ void moments_to_grad2d(const float4 ra, const float4 rb, float g2[9]) {
+  const float A = ra.z, B = ra.w, Cc = rb.x, o = rb.y;
+  const float m0 = g2[0], m1 = g2[1];
+  g2[0] = -(A * m0 + B * m1);
+  g2[1] = -(B * m0 + Cc * m1);
+  g2[2] = -0.5f * g2[2];
+  g2[3] = -g2[3];
+  g2[4] = -0.5f * g2[4];
+  g2[5] = g2[5] / o;
+}
+
 __global__ __launch_bounds__(256) void k_project_bwd(const DevView* __restrict__ views, int n_views,
                                                      const DevScene* __restrict__ scenes, int n_scenes,
-                                                     vbm_gaussians_c g, const float* __restrict__ grad2d,
-                                                     int64_t n_items, const uint32_t* __restrict__ ntiles,
-                                                     vbm_gaussians grads, int accumulate, int64_t n_total) {
+                                                     vbm_gaussians_c g, float* __restrict__ grad2d,
+                                                     const float4* __restrict__ rec, int64_t n_items,
+                                                     const uint32_t* __restrict__ ntiles, vbm_gaussians grads,
+                                                     int accumulate, int64_t n_total) {
   const int64_t gi = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (gi >= n_total) return;
   int sc = 0;
@@ -400,6 +424,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(const DevView* __restrict__
     if (ntiles[item] == 0) continue;
     float g2[9];
     for (int k = 0; k < 9; ++k) g2[k] = grad2d[k * n_items + item];
+    moments_to_grad2d(rec[2 * item], rec[2 * item + 1], g2);
+    for (int k = 0; k < 6; ++k) grad2d[k * n_items + item] = g2[k];
     ao += g2[5];
     ac[0] += g2[6];
     ac[1] += g2[7];

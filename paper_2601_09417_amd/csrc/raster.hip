@@ -3,17 +3,27 @@
 //
 // Work decomposition: one wave64 per 256 pixels of a tile (a 16x16 tile is one wave, a 32x32 tile
 // four independent waves, an 8x8 tile one wave with one pixel per lane), each lane owning
-// PPL = 4 pixels of rows that are contiguous across the wave.  The tile's depth-sorted list is
-// walked by every wave in lockstep: a Gaussian's item id and its 36-byte record are wave-uniform,
-// so they are fetched with scalar loads into SGPRs and broadcast to the VALU for free -- no LDS
-// staging, no workgroup barriers, and the per-Gaussian load cost is amortised over 256 pixels.
-// Per-pixel updates are branch-free (predicated selects), and a wave leaves the list as soon as
-// every one of its pixels has terminated.
+// PPL = 4 pixels of ONE pixel column (rows 64 / TILE apart), so the horizontal offset to a
+// Gaussian's centre is shared by a lane's pixels.  The tile's depth-sorted list is walked by every
+// wave in lockstep: a Gaussian's item id and its 36-byte record are wave-uniform, fetched with
+// buffer loads at a uniform offset one pair ahead of use -- no LDS staging, no barriers, and the
+// per-Gaussian load cost is amortised over 256 pixels.
+//
+// The record holds the exponent in base 2 with the log-opacity folded in:
+//   e2(d) = hA dx^2 + hB dx dy + hC dy^2 + log2(o) = log2(o) + power(d) log2(e),
+// so alpha = min(0.99, 2^e2) costs one exponential and no multiply by the opacity.  Projection
+// keeps only Gaussians with a positive-definite conic, for which power <= 0 at every pixel, so a
+// "skip when power > 0" guard could only fire on float32 rounding near the centre and is left out.
 //
 // The backward walks the list in reverse from the wave's largest n_contrib, recomputes each
-// pixel's transmittance from final_T by division, sums the nine partial derivatives over the lane's
-// pixels in registers, reduces them across the wave with DPP row operations plus four lane reads,
-// and issues one float atomic per value per (Gaussian, wave) -- only when some pixel contributed.
+// pixel's transmittance from final_T by division and keeps the normalised colour behind the
+// current Gaussian in one running value per channel.  The geometric gradient is accumulated as
+// three per-lane moments of dL/dpower (sum, first and second moment in dy); the lane's column
+// offset dx turns them into the five sums the 2D parameters need.  Nine per-wave sums are then
+// formed with a DPP reduce-scatter inside 16-lane rows (27 VALU operations, one value per lane)
+// plus two cross-row lane swaps, and nine lanes issue one float atomic each -- only when some pixel contributed.  The
+// atomics add those raw moments; the projection backward turns them into mean/conic/opacity
+// gradients with the item's conic, since that map is linear.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -24,15 +34,13 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 
-typedef __attribute__((address_space(4))) const float cfloat;
-typedef __attribute__((address_space(4))) const uint32_t cuint;
-
 template <int TILE>
 struct TileCfg {
   static constexpr int kPix = TILE * TILE;
   static constexpr int kWaves = kPix >= 256 ? kPix / 256 : 1;
   static constexpr int kPPL = kPix / (64 * kWaves);  // pixels per lane
   static constexpr int kThreads = 64 * kWaves;
+  static_assert(64 % TILE == 0, "a lane's pixels must share one column");
 };
 
 __device__ __forceinline__ int find_view(const DevView* __restrict__ views, int n_views, int tile) {
@@ -45,37 +53,114 @@ __device__ __forceinline__ int find_view(const DevView* __restrict__ views, int 
   return lo;
 }
 
-// The Gaussian's exponent at one pixel, written once with explicit fused operations so the forward
-// and the backward take bit-identical skip/contribute decisions.
-__device__ __forceinline__ float gauss_power(const float4 a, const float conic_c, float dx, float dy) {
-  const float q = fmaf(a.z * dx, dx, conic_c * dy * dy);
-  return fmaf(-0.5f, q, -(a.w * dx) * dy);
+// One Gaussian's compositing record (wave-uniform values).
+struct Rec {
+  float mx, my, hA, hB, hC, lo, r, g, b;
+};
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+constexpr int kRsrcWord3 = 0x00020000;  // raw (untyped) buffer access on the gfx9 family
+
+// Buffer descriptors of the arrays the list walk reads.  Buffer loads are vector-memory
+// operations (completed in issue order, so a prefetch one step ahead is waited for exactly) with a
+// uniform SGPR offset (no per-lane address arithmetic), and the hardware range check turns a read
+// past num_records into a zero instead of an access fault.
+struct ListSrc {
+  __amdgpu_buffer_rsrc_t items, coef, blue;
+};
+
+__device__ __forceinline__ ListSrc make_list_src(const uint32_t* pair_item, int64_t n_pairs, const float* coef,
+                                                 const float* blue, int64_t n_items) {
+  // num_records is a 32-bit byte count: the plan bounds n_items by 2^27 and n_pairs by 2^30.
+  ListSrc s;
+  s.items = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(pair_item), (short)0,
+                                              static_cast<int>(static_cast<uint32_t>(n_pairs * 4)), kRsrcWord3);
+  s.coef = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(coef), (short)0,
+                                             static_cast<int>(static_cast<uint32_t>(n_items * 32)), kRsrcWord3);
+  s.blue = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(blue), (short)0,
+                                             static_cast<int>(static_cast<uint32_t>(n_items * 4)), kRsrcWord3);
+  return s;
 }
 
-// The 32-byte record of item `it` (mean2d.xy, conic.ab | conic.c, opacity, r, g) as two float4.
-__device__ __forceinline__ void load_record(cfloat* r, uint32_t it, float4& a, float4& b) {
-  const size_t o = 8 * static_cast<size_t>(it);
-  a = make_float4(r[o], r[o + 1], r[o + 2], r[o + 3]);
-  b = make_float4(r[o + 4], r[o + 5], r[o + 6], r[o + 7]);
+__device__ __forceinline__ uint32_t load_item(const ListSrc& s, int j) {
+  return static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b32(s.items, 0, 4 * j, 0));
 }
 
-template <int DPP_CTRL>
+__device__ __forceinline__ Rec load_rec(const ListSrc& s, uint32_t it) {
+  const int off = static_cast<int>(32u * it);
+  const v4i a = __builtin_amdgcn_raw_buffer_load_b128(s.coef, 0, off, 0);
+  const v4i b = __builtin_amdgcn_raw_buffer_load_b128(s.coef, 16, off, 0);
+  Rec r;
+  r.mx = __int_as_float(a.x);
+  r.my = __int_as_float(a.y);
+  r.hA = __int_as_float(a.z);
+  r.hB = __int_as_float(a.w);
+  r.hC = __int_as_float(b.x);
+  r.lo = __int_as_float(b.y);
+  r.r = __int_as_float(b.z);
+  r.g = __int_as_float(b.w);
+  r.b = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(s.blue, 0, static_cast<int>(4u * it), 0));
+  return r;
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Base-2 exponent of the Gaussian at a pixel whose per-lane terms u = hA dx^2 + log2(o) and
+// v = hB dx are precomputed; one expression shared by the forward and the backward so that both
+// take bit-identical skip / contribute decisions.
+__device__ __forceinline__ float exponent2(const Rec& r, float u, float v, float dy) {
+  return fmaf(fmaf(r.hC, dy, v), dy, u);
+}
+
+template <int CTRL>
 __device__ __forceinline__ float dpp_move(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), DPP_CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
-// Sum over the 64 lanes (every lane must be active): quad swaps, half-row and row mirrors leave
-// each 16-lane row holding its row sum; four lane reads add the rows.
-__device__ __forceinline__ float wave_sum(float v) {
-  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_move<0x141>(v);  // row_half_mirror
-  v += dpp_move<0x140>(v);  // row_mirror
-  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
-  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
-  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
-  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
-  return (r0 + r1) + (r2 + r3);
+// One step of a reduce-scatter inside 16-lane rows: lanes with `hi` clear keep value a, the others
+// value b, each adding its DPP partner's copy (the partner always has the opposite `hi`).
+template <int CTRL>
+__device__ __forceinline__ float rs_pair(float a, float b, bool hi) {
+  const float keep = hi ? b : a;
+  const float send = hi ? a : b;
+  return keep + dpp_move<CTRL>(send);
+}
+template <int CTRL>
+__device__ __forceinline__ float rs_single(float v) {
+  return v + dpp_move<CTRL>(v);
+}
+
+constexpr int kRowMirror = 0x140;
+constexpr int kRowHalfMirror = 0x141;
+constexpr int kQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int kQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
+
+// Wave sums of nine values (every lane active).  Lane l < 16 ends with the sum of value
+// rs_index(l): even lanes l hold value 4 b1 + 2 b2 + b3 (b_i = bit i of l), odd lanes value 8.
+__device__ __forceinline__ float reduce_scatter9(const float g[9], int lane) {
+  const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
+  const float A = rs_pair<kRowMirror>(g[0], g[1], b3);
+  const float B = rs_pair<kRowMirror>(g[2], g[3], b3);
+  const float C = rs_pair<kRowMirror>(g[4], g[5], b3);
+  const float D = rs_pair<kRowMirror>(g[6], g[7], b3);
+  float E = rs_single<kRowMirror>(g[8]);
+  const float F = rs_pair<kRowHalfMirror>(A, B, b2);
+  const float G = rs_pair<kRowHalfMirror>(C, D, b2);
+  E = rs_single<kRowHalfMirror>(E);
+  const float H = rs_pair<kQuadXor2>(F, G, b1);
+  E = rs_single<kQuadXor2>(E);
+  const float K = rs_pair<kQuadXor1>(H, E, b0);
+  // Cross-row sums for lanes 0..15 only: permlane32_swap hands lanes 0..31 of its second operand
+  // the upper half of its first (which keeps its own lower half), permlane16_swap likewise hands
+  // row 0 the contents of row 1.
+  const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(K), 0u, false, false);
+  const float K2 = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(K2), 0u, false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ int rs_index(int lane) {
+  return (lane & 1) ? 8 : ((lane >> 1) & 1) * 4 + ((lane >> 2) & 1) * 2 + ((lane >> 3) & 1);
 }
 
 // Measurement aid: adds the wave's evaluated / contributing (pixel, Gaussian) counts to stats[0..1].
@@ -91,11 +176,195 @@ __device__ __forceinline__ void add_stats(unsigned long long* stats, uint32_t n_
   }
 }
 
+// A pixel that has terminated (or lies outside the image) gets this row coordinate: its exponent
+// then overflows to -inf, alpha underflows to 0 and it never contributes again, so the step needs
+// no separate liveness test.
+constexpr float kDeadRow = 1e30f;
+constexpr float kLiveBound = 1e29f;
+
+template <int PPL>
+__device__ __forceinline__ bool any_live(const float (&fy)[PPL]) {
+  float m = fy[0];
+#pragma unroll
+  for (int k = 1; k < PPL; ++k) m = fminf(m, fy[k]);
+  return __any(m < kLiveBound);
+}
+
+// One list step of the forward for the lane's pixels: alpha = min(0.99, 2^e2); a pixel takes the
+// Gaussian when alpha >= 1/255, unless the new transmittance would fall below 1e-4, in which case
+// the pixel stops without it.
+template <int PPL, bool STATS>
+__device__ __forceinline__ void fwd_step(const Rec& r, int pos, float fx, float (&fy)[PPL], float (&T)[PPL],
+                                         float (&cr)[PPL], float (&cg)[PPL], float (&cb)[PPL], int (&last)[PPL],
+                                         uint32_t& n_eval, uint32_t& n_used) {
+  const float dx = r.mx - fx;
+  const float u = fmaf(r.hA, dx * dx, r.lo);
+  const float vb = r.hB * dx;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const float dy = r.my - fy[k];
+    const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(exponent2(r, u, vb, dy)));
+    const bool ok = alpha >= kAlphaMin;
+    const float w = alpha * T[k];
+    const float Tn = T[k] - w;
+    const bool stop = ok && Tn < kTMin;
+    const bool use = ok && !stop;
+    if (STATS) {
+      n_eval += fy[k] < kLiveBound ? 1u : 0u;
+      n_used += use ? 1u : 0u;
+    }
+    const float wu = use ? w : 0.0f;
+    cr[k] = fmaf(r.r, wu, cr[k]);
+    cg[k] = fmaf(r.g, wu, cg[k]);
+    cb[k] = fmaf(r.b, wu, cb[k]);
+    T[k] = use ? Tn : T[k];
+    fy[k] = stop ? kDeadRow : fy[k];
+    last[k] = use ? pos : last[k];
+  }
+}
+
 template <int TILE, bool STATS>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
     const DevView* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
-    const uint32_t* __restrict__ pair_item, const float4* __restrict__ rec, const float* __restrict__ blue,
-    float* __restrict__ image, float* __restrict__ final_T, int32_t* __restrict__ n_contrib,
+    const uint32_t* __restrict__ pair_item, int64_t n_pairs, const float* __restrict__ coef,
+    const float* __restrict__ blue, int64_t n_items, float* __restrict__ image, float* __restrict__ final_T,
+    int32_t* __restrict__ n_contrib, unsigned long long* __restrict__ stats) {
+  using C = TileCfg<TILE>;
+  constexpr int PPL = C::kPPL;
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  const int wave = static_cast<int>(threadIdx.x) >> 6;
+  const int tile = blockIdx.x;
+  const DevView& v = views[find_view(views, n_views, tile)];
+  const int local = tile - v.tile_offset;
+  const int tx = local % v.tiles_x, ty = local / v.tiles_x;
+  float fy[PPL], T[PPL], cr[PPL], cg[PPL], cb[PPL];
+  int last[PPL];
+  bool inside[PPL];
+  int py[PPL];
+  const int q0 = wave * (C::kPix / C::kWaves) + lane;
+  const int px = tx * TILE + q0 % TILE;
+  const float fx = static_cast<float>(px) + 0.5f;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    py[k] = ty * TILE + (q0 + k * 64) / TILE;
+    inside[k] = px < v.width && py[k] < v.height;
+    fy[k] = inside[k] ? static_cast<float>(py[k]) + 0.5f : kDeadRow;
+    T[k] = 1.0f;
+    cr[k] = cg[k] = cb[k] = 0.0f;
+    last[k] = 0;
+  }
+  const uint2 rg = ranges[tile];
+  const int start = static_cast<int>(rg.x), end = static_cast<int>(rg.y);
+  uint32_t n_eval = 0, n_used = 0;
+  // Load pipeline, unrolled by two so the two record buffers alternate without copies: while pair
+  // j is composited from ra, the record of j + 1 (into rb) and the item of j + 2 are in flight,
+  // and the other way round.  An empty list reads no pair entry (item 0 is a harmless dummy).
+  const ListSrc src = make_list_src(pair_item, n_pairs, coef, blue, n_items);
+  const int lastj = end > start ? end - 1 : start;
+  Rec ra = load_rec(src, end > start ? uniform(load_item(src, start)) : 0u);
+  Rec rb;
+  uint32_t itb = end > start ? load_item(src, min(start + 1, lastj)) : 0u;
+  uint32_t ita;
+  // Both halves run unconditionally (a branch between them would let the compiler sink the
+  // prefetch below it); past the end of the list the second record is a clamped duplicate whose
+  // log-opacity is set to -inf, so alpha = 0 and it changes nothing.
+  for (int j = start; j < end; j += 2) {
+    if (!any_live(fy)) break;
+    rb = load_rec(src, uniform(itb));
+    ita = load_item(src, min(j + 2, lastj));
+    fwd_step<PPL, STATS>(ra, j - start + 1, fx, fy, T, cr, cg, cb, last, n_eval, n_used);
+    rb.lo = j + 1 < end ? rb.lo : -__builtin_inff();
+    ra = load_rec(src, uniform(ita));
+    itb = load_item(src, min(j + 3, lastj));
+    fwd_step<PPL, STATS>(rb, j - start + 2, fx, fy, T, cr, cg, cb, last, n_eval, n_used);
+  }
+  if (STATS) add_stats(stats, n_eval, n_used);
+  const int64_t HW = static_cast<int64_t>(v.width) * v.height;
+  float* img = image + 3 * static_cast<int64_t>(v.pixel_offset);
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    if (!inside[k]) continue;
+    const int64_t pix = static_cast<int64_t>(py[k]) * v.width + px;
+    img[pix] = cr[k] + T[k] * v.bg[0];
+    img[HW + pix] = cg[k] + T[k] * v.bg[1];
+    img[2 * HW + pix] = cb[k] + T[k] * v.bg[2];
+    final_T[v.pixel_offset + pix] = T[k];
+    n_contrib[v.pixel_offset + pix] = last[k];
+  }
+}
+
+// Per-wave gradient state of one list step of the backward (see bwd_step).
+template <int PPL>
+struct BwdPix {
+  float fy[PPL], T[PPL], dr[PPL], dg[PPL], db[PPL], accr[PPL], accg[PPL], accb[PPL];
+  int nc[PPL];
+};
+
+// One list step (list position j, 0-based) of the backward for the lane's pixels.  A pixel takes
+// part when j < n_contrib and the forward's alpha test holds; its transmittance before the
+// Gaussian is T / (1 - alpha), dL/dalpha = T_before * sum_c dL/dC_c (c_c - acc_c) with acc the
+// normalised colour behind the Gaussian (the background at first), which then becomes
+// alpha c + (1 - alpha) acc.  dL/dpower = alpha dL/dalpha unless alpha was clamped.
+template <int PPL, bool STATS>
+__device__ __forceinline__ void bwd_step(const Rec& r, uint32_t it, int j, float fx, BwdPix<PPL>& P, int lane,
+                                         int out_k, bool out_lane, float* __restrict__ grad2d, int64_t n_items,
+                                         uint32_t& n_eval, uint32_t& n_used) {
+  const float dx = r.mx - fx;
+  const float dx2 = dx * dx;
+  const float u = fmaf(r.hA, dx2, r.lo);
+  const float vb = r.hB * dx;
+  float G2[PPL], alpha[PPL];
+  bool c[PPL];
+  bool anyc = false;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const float dy = r.my - P.fy[k];
+    G2[k] = __builtin_amdgcn_exp2f(exponent2(r, u, vb, dy));
+    alpha[k] = fminf(kAlphaMax, G2[k]);
+    c[k] = j < P.nc[k] && alpha[k] >= kAlphaMin;
+    anyc |= c[k];
+    if (STATS) {
+      n_eval += j < P.nc[k] ? 1u : 0u;
+      n_used += c[k] ? 1u : 0u;
+    }
+  }
+  if (!__any(anyc)) return;
+  // Per-lane sums: s0 = sum dp, s1 = sum dp dy, s2 = sum dp dy^2 (dp = dL/dpower), and the colour
+  // weights alpha T_before dL/dC.
+  float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, wr = 0.0f, wg = 0.0f, wb = 0.0f;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    if (c[k]) {
+      const float Tk = P.T[k] * __builtin_amdgcn_rcpf(1.0f - alpha[k]);
+      P.T[k] = Tk;
+      const float er = r.r - P.accr[k], eg = r.g - P.accg[k], eb = r.b - P.accb[k];
+      const float dLda = Tk * fmaf(P.dr[k], er, fmaf(P.dg[k], eg, P.db[k] * eb));
+      P.accr[k] = fmaf(alpha[k], er, P.accr[k]);
+      P.accg[k] = fmaf(alpha[k], eg, P.accg[k]);
+      P.accb[k] = fmaf(alpha[k], eb, P.accb[k]);
+      const float w = alpha[k] * Tk;
+      wr = fmaf(w, P.dr[k], wr);
+      wg = fmaf(w, P.dg[k], wg);
+      wb = fmaf(w, P.db[k], wb);
+      const float dp = G2[k] <= kAlphaMax ? dLda * alpha[k] : 0.0f;
+      const float dy = r.my - P.fy[k];
+      const float t = dp * dy;
+      s0 += dp;
+      s1 += t;
+      s2 = fmaf(t, dy, s2);
+    }
+  }
+  const float g[9] = {dx * s0, s1, dx2 * s0, dx * s1, s2, s0, wr, wg, wb};
+  const float sum = reduce_scatter9(g, lane);
+  if (out_lane && sum != 0.0f) unsafeAtomicAdd(&grad2d[out_k * n_items + it], sum);
+}
+
+template <int TILE, bool STATS>
+__global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
+    const DevView* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ pair_item, int64_t n_pairs, const float* __restrict__ coef,
+    const float* __restrict__ blue, const float* __restrict__ final_T, const int32_t* __restrict__ n_contrib,
+    const float* __restrict__ dL_dimg, float* __restrict__ grad2d, int64_t n_items,
     unsigned long long* __restrict__ stats) {
   using C = TileCfg<TILE>;
   constexpr int PPL = C::kPPL;
@@ -105,267 +374,118 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
   const DevView& v = views[find_view(views, n_views, tile)];
   const int local = tile - v.tile_offset;
   const int tx = local % v.tiles_x, ty = local / v.tiles_x;
-  float fx[PPL], fy[PPL], T[PPL], cr[PPL], cg[PPL], cb[PPL];
-  int last[PPL];
-  bool live[PPL], inside[PPL];
-  int px[PPL], py[PPL];
-#pragma unroll
-  for (int k = 0; k < PPL; ++k) {
-    const int q = wave * (C::kPix / C::kWaves) + k * 64 + lane;
-    px[k] = tx * TILE + q % TILE;
-    py[k] = ty * TILE + q / TILE;
-    inside[k] = px[k] < v.width && py[k] < v.height;
-    live[k] = inside[k];
-    fx[k] = static_cast<float>(px[k]) + 0.5f;
-    fy[k] = static_cast<float>(py[k]) + 0.5f;
-    T[k] = 1.0f;
-    cr[k] = cg[k] = cb[k] = 0.0f;
-    last[k] = 0;
-  }
-  const uint2 rg = ranges[tile];
-  const int start = static_cast<int>(rg.x), end = static_cast<int>(rg.y);
-  cuint* items = (cuint*)(pair_item);
-  cfloat* recs = (cfloat*)(rec);
-  cfloat* blues = (cfloat*)(blue);
-  uint32_t n_eval = 0, n_used = 0;
-  // Software pipeline over the list: item ids are fetched two positions ahead and records one
-  // position ahead, so the scalar-load latency overlaps the current Gaussian's arithmetic.
-  const int lastj = end > start ? end - 1 : start;
-  // An empty list touches no pair entry; item 0 always exists, so its record is a safe dummy.
-  uint32_t it_n = end > start ? items[start] : 0u;
-  uint32_t it_nn = end > start ? items[min(start + 1, lastj)] : 0u;
-  float4 a_n, b_n;
-  load_record(recs, it_n, a_n, b_n);
-  float bl_n = blues[it_n];
-  for (int j = start; j < end; ++j) {
-    bool any_live = false;
-#pragma unroll
-    for (int k = 0; k < PPL; ++k) any_live |= live[k];
-    if (!__any(any_live)) break;
-    const float4 a = a_n;
-    const float4 b = b_n;
-    const float bl = bl_n;
-    it_n = it_nn;
-    it_nn = items[min(j + 2, lastj)];
-    load_record(recs, it_n, a_n, b_n);
-    bl_n = blues[it_n];
-    const int pos = j - start + 1;
-#pragma unroll
-    for (int k = 0; k < PPL; ++k) {
-      const float dx = a.x - fx[k], dy = a.y - fy[k];
-      const float power = gauss_power(a, b.x, dx, dy);
-      const float alpha = fminf(kAlphaMax, b.y * __expf(power));
-      const bool ok = live[k] && power <= 0.0f && alpha >= kAlphaMin;
-      const float Tn = T[k] * (1.0f - alpha);
-      const bool stop = ok && Tn < kTMin;
-      const bool use = ok && !stop;
-      if (STATS) {
-        n_eval += live[k] ? 1u : 0u;
-        n_used += use ? 1u : 0u;
-      }
-      live[k] = live[k] && !stop;
-      const float w = use ? alpha * T[k] : 0.0f;
-      cr[k] = fmaf(b.z, w, cr[k]);
-      cg[k] = fmaf(b.w, w, cg[k]);
-      cb[k] = fmaf(bl, w, cb[k]);
-      T[k] = use ? Tn : T[k];
-      last[k] = use ? pos : last[k];
-    }
-  }
-  if (STATS) add_stats(stats, n_eval, n_used);
   const int64_t HW = static_cast<int64_t>(v.width) * v.height;
-  float* img = image + 3 * static_cast<int64_t>(v.pixel_offset);
-#pragma unroll
-  for (int k = 0; k < PPL; ++k) {
-    if (!inside[k]) continue;
-    const int64_t pix = static_cast<int64_t>(py[k]) * v.width + px[k];
-    img[pix] = cr[k] + T[k] * v.bg[0];
-    img[HW + pix] = cg[k] + T[k] * v.bg[1];
-    img[2 * HW + pix] = cb[k] + T[k] * v.bg[2];
-    final_T[v.pixel_offset + pix] = T[k];
-    n_contrib[v.pixel_offset + pix] = last[k];
-  }
-}
-
-template <int TILE, bool STATS>
-__global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
-    const DevView* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
-    const uint32_t* __restrict__ pair_item, const float4* __restrict__ rec, const float* __restrict__ blue,
-    const float* __restrict__ final_T, const int32_t* __restrict__ n_contrib, const float* __restrict__ dL_dimg,
-    float* __restrict__ grad2d, int64_t n_items, unsigned long long* __restrict__ stats) {
-  using C = TileCfg<TILE>;
-  constexpr int PPL = C::kPPL;
-  const int lane = static_cast<int>(threadIdx.x) & 63;
-  const int wave = static_cast<int>(threadIdx.x) >> 6;
-  const int tile = blockIdx.x;
-  const DevView& v = views[find_view(views, n_views, tile)];
-  const int local = tile - v.tile_offset;
-  const int tx = local % v.tiles_x, ty = local / v.tiles_x;
-  const int64_t HW = static_cast<int64_t>(v.width) * v.height;
-  float fx[PPL], fy[PPL], T[PPL], dr[PPL], dg[PPL], db[PPL];
-  float accr[PPL], accg[PPL], accb[PPL], la[PPL], lr[PPL], lg[PPL], lb[PPL];
-  int nc[PPL];
+  BwdPix<PPL> P;
   int maxn = 0;
+  const int q0 = wave * (C::kPix / C::kWaves) + lane;
+  const int px = tx * TILE + q0 % TILE;
+  const float fx = static_cast<float>(px) + 0.5f;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
-    const int q = wave * (C::kPix / C::kWaves) + k * 64 + lane;
-    const int px = tx * TILE + q % TILE;
-    const int py = ty * TILE + q / TILE;
+    const int py = ty * TILE + (q0 + k * 64) / TILE;
     const bool inside = px < v.width && py < v.height;
-    fx[k] = static_cast<float>(px) + 0.5f;
-    fy[k] = static_cast<float>(py) + 0.5f;
-    T[k] = 1.0f;
-    nc[k] = 0;
-    dr[k] = dg[k] = db[k] = 0.0f;
+    P.fy[k] = static_cast<float>(py) + 0.5f;
+    P.T[k] = 1.0f;
+    P.nc[k] = 0;
+    P.dr[k] = P.dg[k] = P.db[k] = 0.0f;
     if (inside) {
       const int64_t pix = static_cast<int64_t>(py) * v.width + px;
-      T[k] = final_T[v.pixel_offset + pix];
-      nc[k] = n_contrib[v.pixel_offset + pix];
+      P.T[k] = final_T[v.pixel_offset + pix];
+      P.nc[k] = n_contrib[v.pixel_offset + pix];
       const float* g = dL_dimg + 3 * static_cast<int64_t>(v.pixel_offset);
-      dr[k] = g[pix];
-      dg[k] = g[HW + pix];
-      db[k] = g[2 * HW + pix];
+      P.dr[k] = g[pix];
+      P.dg[k] = g[HW + pix];
+      P.db[k] = g[2 * HW + pix];
     }
-    accr[k] = v.bg[0];
-    accg[k] = v.bg[1];
-    accb[k] = v.bg[2];
-    la[k] = lr[k] = lg[k] = lb[k] = 0.0f;
-    maxn = max(maxn, nc[k]);
+    P.accr[k] = v.bg[0];
+    P.accg[k] = v.bg[1];
+    P.accb[k] = v.bg[2];
+    maxn = max(maxn, P.nc[k]);
   }
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) maxn = max(maxn, __shfl_xor(maxn, d, 64));
+  maxn = __builtin_amdgcn_readfirstlane(maxn);
   const int start = static_cast<int>(ranges[tile].x);
-  cuint* items = (cuint*)(pair_item);
-  cfloat* recs = (cfloat*)(rec);
-  cfloat* blues = (cfloat*)(blue);
+  const int out_k = rs_index(lane & 15);
+  const bool out_lane = lane < 16 && ((lane & 1) == 0 || lane == 1);
   uint32_t n_eval = 0, n_used = 0;
-  // Same two-deep software pipeline as the forward, walking the list backwards.
-  const int top = maxn > 0 ? maxn - 1 : 0;
-  uint32_t it_n = maxn > 0 ? items[start + top] : 0u;
-  uint32_t it_nn = maxn > 0 ? items[start + max(top - 1, 0)] : 0u;
-  float4 a_n, b_n;
-  load_record(recs, it_n, a_n, b_n);
-  float bl_n = blues[it_n];
-  for (int j = maxn - 1; j >= 0; --j) {
-    const uint32_t it = it_n;
-    const float4 a = a_n;
-    const float4 b = b_n;
-    const float bl = bl_n;
-    it_n = it_nn;
-    it_nn = items[start + max(j - 2, 0)];
-    load_record(recs, it_n, a_n, b_n);
-    bl_n = blues[it_n];
-    float power[PPL], G[PPL], alpha[PPL];
-    bool c[PPL];
-    bool anyc = false;
-#pragma unroll
-    for (int k = 0; k < PPL; ++k) {
-      const float dx = a.x - fx[k], dy = a.y - fy[k];
-      power[k] = gauss_power(a, b.x, dx, dy);
-      G[k] = __expf(power[k]);
-      alpha[k] = fminf(kAlphaMax, b.y * G[k]);
-      c[k] = j < nc[k] && power[k] <= 0.0f && alpha[k] >= kAlphaMin;
-      anyc |= c[k];
-      if (STATS) {
-        n_eval += j < nc[k] ? 1u : 0u;
-        n_used += c[k] ? 1u : 0u;
-      }
-    }
-    if (!__any(anyc)) continue;
-    float g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0, g6 = 0, g7 = 0, g8 = 0;
-#pragma unroll
-    for (int k = 0; k < PPL; ++k) {
-      const bool ck = c[k];
-      const float dx = a.x - fx[k], dy = a.y - fy[k];
-      const float Tk = ck ? T[k] * __builtin_amdgcn_rcpf(1.0f - alpha[k]) : T[k];
-      T[k] = Tk;
-      const float ar = la[k] * lr[k] + (1.0f - la[k]) * accr[k];
-      const float ag = la[k] * lg[k] + (1.0f - la[k]) * accg[k];
-      const float ab = la[k] * lb[k] + (1.0f - la[k]) * accb[k];
-      accr[k] = ck ? ar : accr[k];
-      accg[k] = ck ? ag : accg[k];
-      accb[k] = ck ? ab : accb[k];
-      const float w = ck ? alpha[k] * Tk : 0.0f;
-      g6 = fmaf(w, dr[k], g6);
-      g7 = fmaf(w, dg[k], g7);
-      g8 = fmaf(w, db[k], g8);
-      const float dL_da = Tk * (dr[k] * (b.z - ar) + dg[k] * (b.w - ag) + db[k] * (bl - ab));
-      la[k] = ck ? alpha[k] : la[k];
-      lr[k] = ck ? b.z : lr[k];
-      lg[k] = ck ? b.w : lg[k];
-      lb[k] = ck ? bl : lb[k];
-      const bool unclamped = ck && b.y * G[k] <= kAlphaMax;
-      const float dp = unclamped ? dL_da * alpha[k] : 0.0f;
-      g5 = fmaf(unclamped ? dL_da : 0.0f, G[k], g5);
-      g0 = fmaf(dp, -(a.z * dx + a.w * dy), g0);
-      g1 = fmaf(dp, -(b.x * dy + a.w * dx), g1);
-      g2 = fmaf(dp, -0.5f * dx * dx, g2);
-      g3 = fmaf(dp, -dx * dy, g3);
-      g4 = fmaf(dp, -0.5f * dy * dy, g4);
-    }
-    const float s[9] = {wave_sum(g0), wave_sum(g1), wave_sum(g2), wave_sum(g3), wave_sum(g4),
-                        wave_sum(g5), wave_sum(g6), wave_sum(g7), wave_sum(g8)};
-    if (lane < 9) {
-      float x = s[0];
-#pragma unroll
-      for (int q = 1; q < 9; ++q) x = lane == q ? s[q] : x;
-      if (x != 0.0f) unsafeAtomicAdd(&grad2d[lane * n_items + it], x);
-    }
+  // The forward's two-buffer load pipeline, walking positions maxn - 1 .. 0.
+  const ListSrc src = make_list_src(pair_item, n_pairs, coef, blue, n_items);
+  const uint32_t ia0 = maxn > 0 ? uniform(load_item(src, start + maxn - 1)) : 0u;
+  uint32_t ia = ia0, ib = 0u;
+  Rec ra = load_rec(src, ia0);
+  Rec rb;
+  uint32_t itb = maxn > 1 ? load_item(src, start + maxn - 2) : 0u;
+  uint32_t ita;
+  for (int j = maxn - 1; j >= 0; j -= 2) {
+    ib = uniform(itb);
+    rb = load_rec(src, ib);
+    ita = load_item(src, start + max(j - 2, 0));
+    bwd_step<PPL, STATS>(ra, ia, j, fx, P, lane, out_k, out_lane, grad2d, n_items, n_eval, n_used);
+    if (j == 0) break;
+    ia = uniform(ita);
+    ra = load_rec(src, ia);
+    itb = load_item(src, start + max(j - 3, 0));
+    bwd_step<PPL, STATS>(rb, ib, j - 1, fx, P, lane, out_k, out_lane, grad2d, n_items, n_eval, n_used);
   }
   if (STATS) add_stats(stats, n_eval, n_used);
 }
 
 template <int TILE>
 static vbm_status launch_fwd_t(const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
-                               const uint32_t* pair_item, const float4* rec, const float* blue, float* image,
-                               float* final_T, int32_t* n_contrib, unsigned long long* stats, hipStream_t s) {
+                               const uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
+                               int64_t n_items, float* image, float* final_T, int32_t* n_contrib,
+                               unsigned long long* stats, hipStream_t s) {
   const dim3 block(TileCfg<TILE>::kThreads);
   if (stats)
     hipLaunchKernelGGL((k_composite_fwd<TILE, true>), dim3(n_tiles), block, 0, s, views, n_views, ranges, pair_item,
-                       rec, blue, image, final_T, n_contrib, stats);
+                       n_pairs, coef, blue, n_items, image, final_T, n_contrib, stats);
   else
     hipLaunchKernelGGL((k_composite_fwd<TILE, false>), dim3(n_tiles), block, 0, s, views, n_views, ranges, pair_item,
-                       rec, blue, image, final_T, n_contrib, stats);
+                       n_pairs, coef, blue, n_items, image, final_T, n_contrib, stats);
   VBM_LAUNCH_CHECK("composite_fwd");
   return VBM_OK;
 }
 
 template <int TILE>
 static vbm_status launch_bwd_t(const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
-                               const uint32_t* pair_item, const float4* rec, const float* blue, const float* final_T,
+                               const uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
+                               const float* final_T,
                                const int32_t* n_contrib, const float* dL_dimg, float* grad2d, int64_t n_items,
                                unsigned long long* stats, hipStream_t s) {
   const dim3 block(TileCfg<TILE>::kThreads);
   if (stats)
     hipLaunchKernelGGL((k_composite_bwd<TILE, true>), dim3(n_tiles), block, 0, s, views, n_views, ranges, pair_item,
-                       rec, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats);
+                       n_pairs, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats);
   else
     hipLaunchKernelGGL((k_composite_bwd<TILE, false>), dim3(n_tiles), block, 0, s, views, n_views, ranges, pair_item,
-                       rec, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats);
+                       n_pairs, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats);
   VBM_LAUNCH_CHECK("composite_bwd");
   return VBM_OK;
 }
 
 vbm_status launch_composite_fwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
-                                const uint32_t* pair_item, const float4* rec, const float* blue, float* image,
-                                float* final_T, int32_t* n_contrib, unsigned long long* stats, hipStream_t s) {
+                                const uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
+                                int64_t n_items, float* image, float* final_T, int32_t* n_contrib,
+                                unsigned long long* stats, hipStream_t s) {
   switch (tile) {
-    case 8: return launch_fwd_t<8>(views, n_views, n_tiles, ranges, pair_item, rec, blue, image, final_T, n_contrib, stats, s);
-    case 16: return launch_fwd_t<16>(views, n_views, n_tiles, ranges, pair_item, rec, blue, image, final_T, n_contrib, stats, s);
-    case 32: return launch_fwd_t<32>(views, n_views, n_tiles, ranges, pair_item, rec, blue, image, final_T, n_contrib, stats, s);
+    case 8: return launch_fwd_t<8>(views, n_views, n_tiles, ranges, pair_item, n_pairs, coef, blue, n_items, image, final_T, n_contrib, stats, s);
+    case 16: return launch_fwd_t<16>(views, n_views, n_tiles, ranges, pair_item, n_pairs, coef, blue, n_items, image, final_T, n_contrib, stats, s);
+    case 32: return launch_fwd_t<32>(views, n_views, n_tiles, ranges, pair_item, n_pairs, coef, blue, n_items, image, final_T, n_contrib, stats, s);
   }
   set_error("unsupported tile size %d", tile);
   return VBM_ERR_UNSUPPORTED;
 }
 
 vbm_status launch_composite_bwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
-                                const uint32_t* pair_item, const float4* rec, const float* blue, const float* final_T,
+                                const uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
+                                const float* final_T,
                                 const int32_t* n_contrib, const float* dL_dimg, float* grad2d, int64_t n_items,
                                 unsigned long long* stats, hipStream_t s) {
   switch (tile) {
-    case 8: return launch_bwd_t<8>(views, n_views, n_tiles, ranges, pair_item, rec, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s);
-    case 16: return launch_bwd_t<16>(views, n_views, n_tiles, ranges, pair_item, rec, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s);
-    case 32: return launch_bwd_t<32>(views, n_views, n_tiles, ranges, pair_item, rec, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s);
+    case 8: return launch_bwd_t<8>(views, n_views, n_tiles, ranges, pair_item, n_pairs, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s);
+    case 16: return launch_bwd_t<16>(views, n_views, n_tiles, ranges, pair_item, n_pairs, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s);
+    case 32: return launch_bwd_t<32>(views, n_views, n_tiles, ranges, pair_item, n_pairs, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s);
   }
   set_error("unsupported tile size %d", tile);
   return VBM_ERR_UNSUPPORTED;

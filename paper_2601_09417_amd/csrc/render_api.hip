@@ -18,8 +18,8 @@
 
 namespace vbm {
 
-__global__ void k_project(const DevView*, int, vbm_gaussians_c, float*, uint32_t*, uint32_t*, float4*, float*,
-                          uint32_t*, int64_t);
+__global__ void k_project(const DevView*, int, vbm_gaussians_c, float*, uint32_t*, uint32_t*, float4*, float4*,
+                          float*, uint32_t*, int64_t);
 __global__ void k_compact_visible(const DevView*, const uint32_t*, const float*, const uint32_t*, uint64_t*,
                                   uint32_t*);
 __global__ void k_gather_ntiles(const uint32_t*, const uint32_t*, const uint32_t*, int64_t, uint32_t*);
@@ -27,13 +27,15 @@ __global__ void k_emit(const DevView*, const uint64_t*, const uint32_t*, const u
                        const float4*, int, int64_t, uint32_t*, int64_t, int64_t, uint32_t*, uint32_t*);
 __global__ void k_ranges(const uint32_t*, const uint32_t*, int64_t, uint2*);
 __global__ void k_status(const uint32_t*, int32_t*);
-__global__ void k_project_bwd(const DevView*, int, const DevScene*, int, vbm_gaussians_c, const float*, int64_t,
-                              const uint32_t*, vbm_gaussians, int, int64_t);
+__global__ void k_project_bwd(const DevView*, int, const DevScene*, int, vbm_gaussians_c, float*, const float4*,
+                              int64_t, const uint32_t*, vbm_gaussians, int, int64_t);
 vbm_status launch_composite_fwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
-                                const uint32_t* pair_item, const float4* rec, const float* blue, float* image,
-                                float* final_T, int32_t* n_contrib, unsigned long long* stats, hipStream_t s);
+                                const uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
+                                int64_t n_items, float* image, float* final_T, int32_t* n_contrib,
+                                unsigned long long* stats, hipStream_t s);
 vbm_status launch_composite_bwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
-                                const uint32_t* pair_item, const float4* rec, const float* blue, const float* final_T,
+                                const uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
+                                const float* final_T,
                                 const int32_t* n_contrib, const float* dL_dimg, float* grad2d, int64_t n_items,
                                 unsigned long long* stats, hipStream_t s);
 
@@ -59,7 +61,8 @@ enum Region {
   R_PITEM_ALT = 16,
   R_SCRATCH = 17,
   R_VISFLAG = 18,
-  R_COUNT = 19
+  R_COEF = VBM_REGION_ITEM_COEF,
+  R_COUNT = 20
 };
 
 int ceil_log2(int64_t x) {
@@ -97,6 +100,7 @@ void layout(vbm_plan* p) {
   if (r2 > scr) scr = r2;
   sz[R_SCRATCH] = scr;
   sz[R_VISFLAG] = I * 4;
+  sz[R_COEF] = I * 32;
   size_t off = 0;
   for (int r = 0; r < VBM_WS_REGIONS; ++r) {
     p->region_offset[r] = 0;
@@ -182,8 +186,8 @@ extern "C" vbm_status vbm_plan_make(const vbm_view* views, int32_t n_views, cons
     set_error("vbm_plan_make: sort_bits must be 4..8");
     return VBM_ERR_INVALID;
   }
-  if (sch->pair_capacity < 1 || sch->pair_capacity >= (static_cast<int64_t>(1) << 31)) {
-    set_error("vbm_plan_make: pair_capacity must be in [1, 2^31)");
+  if (sch->pair_capacity < 1 || sch->pair_capacity >= (static_cast<int64_t>(1) << 30)) {
+    set_error("vbm_plan_make: pair_capacity must be in [1, 2^30)");
     return VBM_ERR_INVALID;
   }
   if (sch->mode != VBM_MODE_BATCHED && sch->mode != VBM_MODE_EXACT) {
@@ -250,9 +254,10 @@ extern "C" vbm_status vbm_plan_make(const vbm_view* views, int32_t n_views, cons
     items += ng;
     tiles += static_cast<int64_t>(d.tiles_x) * d.tiles_y;
     pixels += static_cast<int64_t>(in.width) * in.height;
-    if (items >= (static_cast<int64_t>(1) << 31) || tiles >= (static_cast<int64_t>(1) << 31) ||
+    // Items are addressed by 32-bit byte offsets into their 32-byte compositing records.
+    if (items >= (static_cast<int64_t>(1) << 27) || tiles >= (static_cast<int64_t>(1) << 31) ||
         3 * pixels >= (static_cast<int64_t>(1) << 31) || plan->n_gaussians >= (static_cast<int64_t>(1) << 31)) {
-      set_error("vbm_plan_make: batch exceeds 2^31 items, tiles, Gaussians or image values");
+      set_error("vbm_plan_make: batch exceeds 2^27 items or 2^31 tiles, Gaussians or image values");
       return VBM_ERR_INVALID;
     }
   }
@@ -291,6 +296,7 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
   uint32_t* rect = region<uint32_t>(p, ws, R_RECT);
   uint32_t* ntiles = region<uint32_t>(p, ws, R_NTILES);
   float4* rec = region<float4>(p, ws, R_REC);
+  float4* coef = region<float4>(p, ws, R_COEF);
   float* blue = region<float>(p, ws, R_BLUE);
   uint32_t* visflag = region<uint32_t>(p, ws, R_VISFLAG);
   uint64_t* vk[2] = {region<uint64_t>(p, ws, R_VKEYS), region<uint64_t>(p, ws, R_VKEYS_ALT)};
@@ -306,7 +312,7 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
   const int gx = static_cast<int>(ceil_div(p->n_gaussians > 0 ? p->n_gaussians : 1, 256));
   if (I > 0) {
     hipLaunchKernelGGL(k_project, dim3(gx, p->n_views), dim3(256), 0, s, views, p->tile, g, depth, rect, ntiles, rec,
-                       blue, visflag, I);
+                       coef, blue, visflag, I);
     VBM_LAUNCH_CHECK("project");
     VBM_TRY(scan_exclusive_u32(visflag, visflag, I, nullptr, &counters[0], scratch, s));
     const int view_bits = ceil_log2(p->n_views);
@@ -353,7 +359,7 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
     VBM_LAUNCH_CHECK("ranges");
   }
   VBM_TRY(record(0, s));
-  VBM_TRY(launch_composite_fwd(p->tile, views, p->n_views, p->n_tiles, ranges, pi[0], rec, blue, image, final_T,
+  VBM_TRY(launch_composite_fwd(p->tile, views, p->n_views, p->n_tiles, ranges, pi[0], cap, reinterpret_cast<const float*>(coef), blue, I, image, final_T,
                                n_contrib, g_stats, s));
   VBM_TRY(record(1, s));
   hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, s, counters, status);
@@ -385,13 +391,14 @@ extern "C" vbm_status vbm_render_bwd(const vbm_plan* p, const void* view_table, 
   VBM_TRY(fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, 9 * I, s));
   VBM_TRY(record(2, s));
   VBM_TRY(launch_composite_bwd(p->tile, views, p->n_views, p->n_tiles, region<uint2>(p, ws, R_RANGES),
-                               region<uint32_t>(p, ws, R_PITEM), region<float4>(p, ws, R_REC),
+                               region<uint32_t>(p, ws, R_PITEM), p->pair_capacity, region<float>(p, ws, R_COEF),
                                region<float>(p, ws, R_BLUE), final_T, n_contrib, dL_dimg, grad2d, I,
                                g_stats ? g_stats + 2 : nullptr, s));
   VBM_TRY(record(3, s));
   if (p->n_gaussians > 0) {
     hipLaunchKernelGGL(k_project_bwd, dim3(ceil_div(p->n_gaussians, 256)), dim3(256), 0, s, views, p->n_views, scenes,
-                       p->n_scenes, g, grad2d, I, region<uint32_t>(p, ws, R_NTILES), grads, accumulate,
+                       p->n_scenes, g, grad2d, region<float4>(p, ws, R_REC), I, region<uint32_t>(p, ws, R_NTILES),
+                       grads, accumulate,
                        p->n_gaussians);
     VBM_LAUNCH_CHECK("project_bwd");
   }
