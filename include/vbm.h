@@ -211,8 +211,9 @@ typedef struct {
 #define VBM_REGION_PAIR_TILE 6   /* uint32 [pair_capacity]: sorted global tile of each pair */
 #define VBM_REGION_PAIR_ITEM 7   /* uint32 [pair_capacity]: sorted item of each pair */
 #define VBM_REGION_RANGES 8      /* uint32 [n_tiles][2]: [start, end) of each tile's list */
-#define VBM_REGION_GRAD2D 9      /* float32 [9][n_items]: dmean2d.xy, dconic.abc, dopacity, drgb
-                                  * (after vbm_render_bwd; rows of items never binned stay 0) */
+#define VBM_REGION_GRAD2D 9      /* float32 [n_items][16]: dmean2d.xy, dconic.abc, dopacity, drgb in
+                                  * columns 0..8 after vbm_render_bwd (rows of items never binned
+                                  * stay 0; columns 9..15 are padding) */
 #define VBM_REGION_ITEM_COEF 19  /* float32 [n_items][8]: compositing record mean2d.xy, -A/2 log2e,
                                   * -B log2e, -C/2 log2e, log2(opacity), r, g (conic A, B, C) */
 

@@ -422,10 +422,12 @@ __global__ __launch_bounds__(256) void k_project_bwd(const DevView* __restrict__
     if (v.scene != sc) continue;
     const int64_t item = v.item_offset + (gi - v.gauss_offset);
     if (ntiles[item] == 0) continue;
-    float g2[9];
-    for (int k = 0; k < 9; ++k) g2[k] = grad2d[k * n_items + item];
+    float4* row = reinterpret_cast<float4*>(grad2d + 16 * item);
+    const float4 q0 = row[0], q1 = row[1], q2 = row[2];
+    float g2[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x};
     moments_to_grad2d(rec[2 * item], rec[2 * item + 1], g2);
-    for (int k = 0; k < 6; ++k) grad2d[k * n_items + item] = g2[k];
+    row[0] = make_float4(g2[0], g2[1], g2[2], g2[3]);
+    row[1] = make_float4(g2[4], g2[5], g2[6], g2[7]);
     ao += g2[5];
     ac[0] += g2[6];
     ac[1] += g2[7];

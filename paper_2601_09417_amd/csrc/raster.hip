@@ -6,8 +6,8 @@
 // PPL = 4 pixels of ONE pixel column (rows 64 / TILE apart), so the horizontal offset to a
 // Gaussian's centre is shared by a lane's pixels.  The tile's depth-sorted list is walked by every
 // wave in lockstep: a Gaussian's item id and its 36-byte record are wave-uniform, fetched with
-// buffer loads at a uniform offset one pair ahead of use -- no LDS staging, no barriers, and the
-// per-Gaussian load cost is amortised over 256 pixels.
+// buffer loads at a uniform offset (records two list steps ahead of use, item ids four) -- no LDS
+// staging, no barriers, and the per-Gaussian load cost is amortised over 256 pixels.
 //
 // The record holds the exponent in base 2 with the log-opacity folded in:
 //   e2(d) = hA dx^2 + hB dx dy + hC dy^2 + log2(o) = log2(o) + power(d) log2(e),
@@ -21,9 +21,10 @@
 // three per-lane moments of dL/dpower (sum, first and second moment in dy); the lane's column
 // offset dx turns them into the five sums the 2D parameters need.  Nine per-wave sums are then
 // formed with a DPP reduce-scatter inside 16-lane rows (27 VALU operations, one value per lane)
-// plus two cross-row lane swaps, and nine lanes issue one float atomic each -- only when some pixel contributed.  The
-// atomics add those raw moments; the projection backward turns them into mean/conic/opacity
-// gradients with the item's conic, since that map is linear.
+// plus two cross-row lane swaps, and nine lanes issue one float atomic each into the item's
+// 64-byte accumulator row (one cache segment per pair instead of nine lines) -- only when some
+// pixel contributed.  The atomics add those raw moments; the projection backward turns them into
+// mean/conic/opacity gradients with the item's conic, since that map is linear.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -62,7 +63,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 constexpr int kRsrcWord3 = 0x00020000;  // raw (untyped) buffer access on the gfx9 family
 
 // Buffer descriptors of the arrays the list walk reads.  Buffer loads are vector-memory
-// operations (completed in issue order, so a prefetch one step ahead is waited for exactly) with a
+// operations (completed in issue order, so a prefetch is waited for exactly) with a
 // uniform SGPR offset (no per-lane address arithmetic), and the hardware range check turns a read
 // past num_records into a zero instead of an access fault.
 struct ListSrc {
@@ -256,27 +257,30 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
   const uint2 rg = ranges[tile];
   const int start = static_cast<int>(rg.x), end = static_cast<int>(rg.y);
   uint32_t n_eval = 0, n_used = 0;
-  // Load pipeline, unrolled by two so the two record buffers alternate without copies: while pair
-  // j is composited from ra, the record of j + 1 (into rb) and the item of j + 2 are in flight,
-  // and the other way round.  An empty list reads no pair entry (item 0 is a harmless dummy).
+  // Load pipeline, unrolled by three so that buffers rotate without copies: the record of list
+  // step s is requested at step s - 2 and the item id that addresses it at step s - 4 (three
+  // record buffers R, three item slots L).  All three steps of an iteration run (a branch between
+  // them would let the compiler sink the prefetch below it); past the end of the list a record is
+  // a clamped duplicate whose log-opacity is set to -inf, so alpha = 0 and it changes nothing.
   const ListSrc src = make_list_src(pair_item, n_pairs, coef, blue, n_items);
   const int lastj = end > start ? end - 1 : start;
-  Rec ra = load_rec(src, end > start ? uniform(load_item(src, start)) : 0u);
-  Rec rb;
-  uint32_t itb = end > start ? load_item(src, min(start + 1, lastj)) : 0u;
-  uint32_t ita;
-  // Both halves run unconditionally (a branch between them would let the compiler sink the
-  // prefetch below it); past the end of the list the second record is a clamped duplicate whose
-  // log-opacity is set to -inf, so alpha = 0 and it changes nothing.
-  for (int j = start; j < end; j += 2) {
+  Rec R0 = load_rec(src, uniform(load_item(src, start)));
+  Rec R1 = load_rec(src, uniform(load_item(src, min(start + 1, lastj))));
+  Rec R2;
+  uint32_t L1, L2 = load_item(src, min(start + 2, lastj)), L0 = load_item(src, min(start + 3, lastj));
+  for (int j = start; j < end; j += 3) {
     if (!any_live(fy)) break;
-    rb = load_rec(src, uniform(itb));
-    ita = load_item(src, min(j + 2, lastj));
-    fwd_step<PPL, STATS>(ra, j - start + 1, fx, fy, T, cr, cg, cb, last, n_eval, n_used);
-    rb.lo = j + 1 < end ? rb.lo : -__builtin_inff();
-    ra = load_rec(src, uniform(ita));
-    itb = load_item(src, min(j + 3, lastj));
-    fwd_step<PPL, STATS>(rb, j - start + 2, fx, fy, T, cr, cg, cb, last, n_eval, n_used);
+    R2 = load_rec(src, uniform(L2));
+    L1 = load_item(src, min(j + 4, lastj));
+    fwd_step<PPL, STATS>(R0, j - start + 1, fx, fy, T, cr, cg, cb, last, n_eval, n_used);
+    R1.lo = j + 1 < end ? R1.lo : -__builtin_inff();
+    R0 = load_rec(src, uniform(L0));
+    L2 = load_item(src, min(j + 5, lastj));
+    fwd_step<PPL, STATS>(R1, j - start + 2, fx, fy, T, cr, cg, cb, last, n_eval, n_used);
+    R2.lo = j + 2 < end ? R2.lo : -__builtin_inff();
+    R1 = load_rec(src, uniform(L1));
+    L0 = load_item(src, min(j + 6, lastj));
+    fwd_step<PPL, STATS>(R2, j - start + 3, fx, fy, T, cr, cg, cb, last, n_eval, n_used);
   }
   if (STATS) add_stats(stats, n_eval, n_used);
   const int64_t HW = static_cast<int64_t>(v.width) * v.height;
@@ -307,8 +311,8 @@ struct BwdPix {
 // alpha c + (1 - alpha) acc.  dL/dpower = alpha dL/dalpha unless alpha was clamped.
 template <int PPL, bool STATS>
 __device__ __forceinline__ void bwd_step(const Rec& r, uint32_t it, int j, float fx, BwdPix<PPL>& P, int lane,
-                                         int out_k, bool out_lane, float* __restrict__ grad2d, int64_t n_items,
-                                         uint32_t& n_eval, uint32_t& n_used) {
+                                         int out_k, bool out_lane, float* __restrict__ grad2d, uint32_t& n_eval,
+                                         uint32_t& n_used) {
   const float dx = r.mx - fx;
   const float dx2 = dx * dx;
   const float u = fmaf(r.hA, dx2, r.lo);
@@ -356,7 +360,7 @@ __device__ __forceinline__ void bwd_step(const Rec& r, uint32_t it, int j, float
   }
   const float g[9] = {dx * s0, s1, dx2 * s0, dx * s1, s2, s0, wr, wg, wb};
   const float sum = reduce_scatter9(g, lane);
-  if (out_lane && sum != 0.0f) unsafeAtomicAdd(&grad2d[out_k * n_items + it], sum);
+  if (out_lane && sum != 0.0f) unsafeAtomicAdd(&grad2d[16 * static_cast<size_t>(it) + out_k], sum);
 }
 
 template <int TILE, bool STATS>
@@ -409,24 +413,35 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
   const int out_k = rs_index(lane & 15);
   const bool out_lane = lane < 16 && ((lane & 1) == 0 || lane == 1);
   uint32_t n_eval = 0, n_used = 0;
-  // The forward's two-buffer load pipeline, walking positions maxn - 1 .. 0.
+  // The forward's load pipeline, walking list positions maxn - 1 .. 0 (a step's record is
+  // requested two steps ahead, its item id four).  The distance also keeps every wait clear of
+  // the atomics issued at the end of the previous step: vector-memory operations complete in issue
+  // order, and the newest operation a step waits for was issued two steps earlier.  Positions
+  // below 0 are clamped to 0 and their loads never used.
   const ListSrc src = make_list_src(pair_item, n_pairs, coef, blue, n_items);
-  const uint32_t ia0 = maxn > 0 ? uniform(load_item(src, start + maxn - 1)) : 0u;
-  uint32_t ia = ia0, ib = 0u;
-  Rec ra = load_rec(src, ia0);
-  Rec rb;
-  uint32_t itb = maxn > 1 ? load_item(src, start + maxn - 2) : 0u;
-  uint32_t ita;
-  for (int j = maxn - 1; j >= 0; j -= 2) {
-    ib = uniform(itb);
-    rb = load_rec(src, ib);
-    ita = load_item(src, start + max(j - 2, 0));
-    bwd_step<PPL, STATS>(ra, ia, j, fx, P, lane, out_k, out_lane, grad2d, n_items, n_eval, n_used);
+  const int top = max(maxn - 1, 0);
+  uint32_t u0 = uniform(load_item(src, start + top));
+  uint32_t u1 = uniform(load_item(src, start + max(top - 1, 0)));
+  uint32_t u2;
+  Rec R0 = load_rec(src, u0);
+  Rec R1 = load_rec(src, u1);
+  Rec R2;
+  uint32_t L1, L2 = load_item(src, start + max(top - 2, 0)), L0 = load_item(src, start + max(top - 3, 0));
+  for (int j = maxn - 1; j >= 0; j -= 3) {
+    u2 = uniform(L2);
+    R2 = load_rec(src, u2);
+    L1 = load_item(src, start + max(j - 4, 0));
+    bwd_step<PPL, STATS>(R0, u0, j, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
     if (j == 0) break;
-    ia = uniform(ita);
-    ra = load_rec(src, ia);
-    itb = load_item(src, start + max(j - 3, 0));
-    bwd_step<PPL, STATS>(rb, ib, j - 1, fx, P, lane, out_k, out_lane, grad2d, n_items, n_eval, n_used);
+    u0 = uniform(L0);
+    R0 = load_rec(src, u0);
+    L2 = load_item(src, start + max(j - 5, 0));
+    bwd_step<PPL, STATS>(R1, u1, j - 1, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
+    if (j == 1) break;
+    u1 = uniform(L1);
+    R1 = load_rec(src, u1);
+    L0 = load_item(src, start + max(j - 6, 0));
+    bwd_step<PPL, STATS>(R2, u2, j - 2, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
   }
   if (STATS) add_stats(stats, n_eval, n_used);
 }

@@ -85,7 +85,7 @@ void layout(vbm_plan* p) {
   sz[R_PTILE] = P * 4;
   sz[R_PITEM] = P * 4;
   sz[R_RANGES] = NT * 8;
-  sz[R_GRAD2D] = 9 * I * 4;
+  sz[R_GRAD2D] = 16 * I * 4;
   sz[R_VKEYS] = I * 8;
   sz[R_VKEYS_ALT] = I * 8;
   sz[R_VVALS] = I * 4;
@@ -388,7 +388,7 @@ extern "C" vbm_status vbm_render_bwd(const vbm_plan* p, const void* view_table, 
       reinterpret_cast<const DevScene*>(static_cast<const char*>(view_table) + sizeof(DevView) * p->n_views);
   const int64_t I = p->n_items;
   float* grad2d = region<float>(p, ws, R_GRAD2D);
-  VBM_TRY(fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, 9 * I, s));
+  VBM_TRY(fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, 16 * I, s));
   VBM_TRY(record(2, s));
   VBM_TRY(launch_composite_bwd(p->tile, views, p->n_views, p->n_tiles, region<uint2>(p, ws, R_RANGES),
                                region<uint32_t>(p, ws, R_PITEM), p->pair_capacity, region<float>(p, ws, R_COEF),
