@@ -12,9 +12,10 @@
 //   ds/dmu_x = s (2 mu_y / A1 - 2 mu_y / A2 - 2 mu_x / B1 + 2 mu_x / B2),  ds/dSxx = -s / B2,
 //   ds/dSxy = 2 s / A2,  A1 = 2 mu_x mu_y + C1, A2 = 2 sigma_xy + C2, B1 = mu_x^2 + mu_y^2 + C1,
 //   B2 = sigma_x^2 + sigma_y^2 + C2.
-// Two LDS-tiled passes per view: (1) the five filtered maps -> s and the three partials, (2) the
-// filtered partials -> dL/dx.  Partial sums go to per-block slots reduced in a fixed order, so the
-// loss value is deterministic.
+// Two LDS-tiled passes per view over 32x32 output tiles (256 threads, each filtering a 4-row strip
+// of one column vertically): (1) the five filtered maps -> s and the three partials, (2) the
+// filtered partials -> dL/dx.  Partial sums go to per-block slots reduced in two fixed-order
+// stages (256 contiguous chunks, then one block), so the loss value is deterministic.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -25,11 +26,16 @@
 namespace vbm {
 namespace {
 
-constexpr int TS = 16;             // output tile edge
+constexpr int TX = 32;             // output tile width (one column per lane of a half wave)
+constexpr int TY = 32;             // output tile height
 constexpr int RAD = 5;             // window radius
-constexpr int EXT = TS + 2 * RAD;  // tile with halo
+constexpr int EX = TX + 2 * RAD;   // tile with halo
+constexpr int EY = TY + 2 * RAD;
+constexpr int RPT = 4;             // output rows per thread in the vertical pass (256 threads)
+constexpr int kRedBlocks = 256;    // first stage of the partial-sum reduction
 constexpr float kC1 = 0.01f * 0.01f;
 constexpr float kC2 = 0.03f * 0.03f;
+static_assert(TX * (TY / RPT) == 256, "vertical pass covers the tile with 256 threads");
 
 struct Window {
   float w[2 * RAD + 1];
@@ -73,63 +79,82 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ x, const f
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// Pass 1 of SSIM for one view: grid (tiles_x, tiles_y, 3 channels), 256 threads.
+// Pass 1 of SSIM for one view: grid (tiles_x, tiles_y, 3 channels), 256 threads, 32x32 outputs
+// per block.  The five horizontally filtered maps of the (TY + 10) x TX halo rows are staged in
+// LDS; each thread then filters a 4-row strip of one column vertically.
 __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, const float* __restrict__ y, int W,
                                                    int H, Window win, float* __restrict__ p1, float* __restrict__ p2,
                                                    float* __restrict__ p3, float* __restrict__ partial_s,
                                                    float* __restrict__ partial_l1) {
-  __shared__ float sx[EXT][EXT], sy[EXT][EXT];
-  __shared__ float hb[5][EXT][TS];
+  __shared__ float sx[EY][EX + 1], sy[EY][EX + 1];
+  __shared__ float hb[5][EY][TX];
   __shared__ float s_red[4];
   const int c = blockIdx.z;
   const int64_t HW = static_cast<int64_t>(W) * H;
   const float* xc = x + c * HW;
   const float* yc = y + c * HW;
-  const int ox = blockIdx.x * TS - RAD, oy = blockIdx.y * TS - RAD;
-  for (int i = threadIdx.x; i < EXT * EXT; i += 256) {
-    const int r = i / EXT, q = i % EXT;
+  const int ox = blockIdx.x * TX - RAD, oy = blockIdx.y * TY - RAD;
+  for (int i = threadIdx.x; i < EX * EY; i += 256) {
+    const int r = i / EX, q = i % EX;
     const int gx = ox + q, gy = oy + r;
     const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
     sx[r][q] = in ? xc[static_cast<int64_t>(gy) * W + gx] : 0.0f;
     sy[r][q] = in ? yc[static_cast<int64_t>(gy) * W + gx] : 0.0f;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < EXT * TS; i += 256) {
-    const int r = i / TS, q = i % TS;
+  const int col = threadIdx.x % TX;
+  for (int r = threadIdx.x / TX; r < EY; r += 256 / TX) {
     float a = 0, b = 0, aa = 0, bb = 0, ab = 0;
+#pragma unroll
     for (int k = 0; k < 2 * RAD + 1; ++k) {
-      const float u = sx[r][q + k], v = sy[r][q + k], wk = win.w[k];
-      a += wk * u;
-      b += wk * v;
-      aa += wk * u * u;
-      bb += wk * v * v;
-      ab += wk * u * v;
+      const float u = sx[r][col + k], v = sy[r][col + k], wk = win.w[k];
+      a = fmaf(wk, u, a);
+      b = fmaf(wk, v, b);
+      aa = fmaf(wk * u, u, aa);
+      bb = fmaf(wk * v, v, bb);
+      ab = fmaf(wk * u, v, ab);
     }
-    hb[0][r][q] = a;
-    hb[1][r][q] = b;
-    hb[2][r][q] = aa;
-    hb[3][r][q] = bb;
-    hb[4][r][q] = ab;
+    hb[0][r][col] = a;
+    hb[1][r][col] = b;
+    hb[2][r][col] = aa;
+    hb[3][r][col] = bb;
+    hb[4][r][col] = ab;
   }
   __syncthreads();
-  const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
-  const int gx = blockIdx.x * TS + tx, gy = blockIdx.y * TS + ty;
-  float m[5] = {0, 0, 0, 0, 0};
-  for (int k = 0; k < 2 * RAD + 1; ++k)
-    for (int f = 0; f < 5; ++f) m[f] += win.w[k] * hb[f][ty + k][tx];
+  const int r0 = (threadIdx.x / TX) * RPT;
+  const int gx = blockIdx.x * TX + col;
+  float m[RPT][5];
+#pragma unroll
+  for (int o = 0; o < RPT; ++o)
+#pragma unroll
+    for (int f = 0; f < 5; ++f) m[o][f] = 0.0f;
+#pragma unroll
+  for (int t = 0; t < RPT + 2 * RAD; ++t) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      const float h = hb[f][r0 + t][col];
+#pragma unroll
+      for (int o = 0; o < RPT; ++o)
+        if (t - o >= 0 && t - o <= 2 * RAD) m[o][f] = fmaf(win.w[t - o], h, m[o][f]);
+    }
+  }
   float sval = 0.0f, l1 = 0.0f;
-  if (gx < W && gy < H) {
-    const float mx = m[0], my = m[1];
-    const float vx = m[2] - mx * mx, vy = m[3] - my * my, cxy = m[4] - mx * my;
-    const float A1 = 2.0f * mx * my + kC1, A2 = 2.0f * cxy + kC2;
-    const float B1 = mx * mx + my * my + kC1, B2 = vx + vy + kC2;
-    const float s = (A1 * A2) / (B1 * B2);
-    const int64_t pix = c * HW + static_cast<int64_t>(gy) * W + gx;
-    p1[pix] = s * (2.0f * my / A1 - 2.0f * my / A2 - 2.0f * mx / B1 + 2.0f * mx / B2);
-    p2[pix] = -s / B2;
-    p3[pix] = 2.0f * s / A2;
-    sval = s;
-    l1 = fabsf(sx[ty + RAD][tx + RAD] - sy[ty + RAD][tx + RAD]);
+#pragma unroll
+  for (int o = 0; o < RPT; ++o) {
+    const int gy = blockIdx.y * TY + r0 + o;
+    if (gx < W && gy < H) {
+      const float mx = m[o][0], my = m[o][1];
+      const float vx = m[o][2] - mx * mx, vy = m[o][3] - my * my, cxy = m[o][4] - mx * my;
+      const float A1 = 2.0f * mx * my + kC1, A2 = 2.0f * cxy + kC2;
+      const float B1 = mx * mx + my * my + kC1, B2 = vx + vy + kC2;
+      const float sv = (A1 * A2) / (B1 * B2);
+      const int64_t pix = c * HW + static_cast<int64_t>(gy) * W + gx;
+      p1[pix] = sv * (2.0f * my / A1 - 2.0f * my / A2 - 2.0f * mx / B1 + 2.0f * mx / B2);
+      p2[pix] = -sv / B2;
+      p3[pix] = 2.0f * sv / A2;
+      sval += sv;
+      l1 += fabsf(sx[r0 + o + RAD][col + RAD] - sy[r0 + o + RAD][col + RAD]);
+    }
   }
   const int64_t bid = (static_cast<int64_t>(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
   const float ts = block_sum(sval, s_red);
@@ -139,55 +164,102 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
   if (threadIdx.x == 0) partial_l1[bid] = tl;
 }
 
-// Pass 2: dL/dx = w_l1 sign(x - y) - w_ssim [w*p1 + 2 x (w*p2) + y (w*p3)].
+// Pass 2: dL/dx = w_l1 sign(x - y) - w_ssim [w*p1 + 2 x (w*p2) + y (w*p3)], same tiling.
 __global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ x, const float* __restrict__ y, int W,
                                                    int H, Window win, const float* __restrict__ p1,
                                                    const float* __restrict__ p2, const float* __restrict__ p3,
                                                    float w_l1, float w_ssim, float* __restrict__ grad) {
-  __shared__ float sp[3][EXT][EXT];
-  __shared__ float hb[3][EXT][TS];
+  __shared__ float sp[3][EY][EX + 1];
+  __shared__ float hb[3][EY][TX];
   const int c = blockIdx.z;
   const int64_t HW = static_cast<int64_t>(W) * H;
-  const int ox = blockIdx.x * TS - RAD, oy = blockIdx.y * TS - RAD;
+  const int ox = blockIdx.x * TX - RAD, oy = blockIdx.y * TY - RAD;
   const float* P[3] = {p1 + c * HW, p2 + c * HW, p3 + c * HW};
-  for (int i = threadIdx.x; i < EXT * EXT; i += 256) {
-    const int r = i / EXT, q = i % EXT;
+  for (int i = threadIdx.x; i < EX * EY; i += 256) {
+    const int r = i / EX, q = i % EX;
     const int gx = ox + q, gy = oy + r;
     const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
-    for (int f = 0; f < 3; ++f) sp[f][r][q] = in ? P[f][static_cast<int64_t>(gy) * W + gx] : 0.0f;
+    const int64_t off = static_cast<int64_t>(gy) * W + gx;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) sp[f][r][q] = in ? P[f][off] : 0.0f;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < EXT * TS; i += 256) {
-    const int r = i / TS, q = i % TS;
+  const int col = threadIdx.x % TX;
+  for (int r = threadIdx.x / TX; r < EY; r += 256 / TX) {
     float a[3] = {0, 0, 0};
+#pragma unroll
     for (int k = 0; k < 2 * RAD + 1; ++k)
-      for (int f = 0; f < 3; ++f) a[f] += win.w[k] * sp[f][r][q + k];
-    for (int f = 0; f < 3; ++f) hb[f][r][q] = a[f];
+#pragma unroll
+      for (int f = 0; f < 3; ++f) a[f] = fmaf(win.w[k], sp[f][r][col + k], a[f]);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) hb[f][r][col] = a[f];
   }
   __syncthreads();
-  const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
-  const int gx = blockIdx.x * TS + tx, gy = blockIdx.y * TS + ty;
-  if (gx >= W || gy >= H) return;
-  float b[3] = {0, 0, 0};
-  for (int k = 0; k < 2 * RAD + 1; ++k)
-    for (int f = 0; f < 3; ++f) b[f] += win.w[k] * hb[f][ty + k][tx];
-  const int64_t pix = c * HW + static_cast<int64_t>(gy) * W + gx;
-  const float xv = x[pix], yv = y[pix];
-  const float d = xv - yv;
-  const float sg = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
-  grad[pix] = w_l1 * sg - w_ssim * (b[0] + 2.0f * xv * b[1] + yv * b[2]);
+  const int r0 = (threadIdx.x / TX) * RPT;
+  const int gx = blockIdx.x * TX + col;
+  float b[RPT][3];
+#pragma unroll
+  for (int o = 0; o < RPT; ++o)
+#pragma unroll
+    for (int f = 0; f < 3; ++f) b[o][f] = 0.0f;
+#pragma unroll
+  for (int t = 0; t < RPT + 2 * RAD; ++t) {
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      const float h = hb[f][r0 + t][col];
+#pragma unroll
+      for (int o = 0; o < RPT; ++o)
+        if (t - o >= 0 && t - o <= 2 * RAD) b[o][f] = fmaf(win.w[t - o], h, b[o][f]);
+    }
+  }
+  if (gx >= W) return;
+#pragma unroll
+  for (int o = 0; o < RPT; ++o) {
+    const int gy = blockIdx.y * TY + r0 + o;
+    if (gy >= H) continue;
+    const int64_t pix = c * HW + static_cast<int64_t>(gy) * W + gx;
+    const float xv = x[pix], yv = y[pix];
+    const float d = xv - yv;
+    const float sg = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
+    grad[pix] = w_l1 * sg - w_ssim * (b[o][0] + 2.0f * xv * b[o][1] + yv * b[o][2]);
+  }
 }
 
-// Sums the per-block partials in a fixed order: loss = a * sum(l1 parts) + b * sum(ssim parts) + c.
-__global__ void k_finalize(const float* __restrict__ l1p, int64_t nl1, const float* __restrict__ sp, int64_t ns,
-                           double a, double b, double c0, float* __restrict__ loss) {
-  __shared__ double s_red[256];
-  double acc_l = 0.0, acc_s = 0.0;
-  for (int64_t i = threadIdx.x; i < nl1; i += 256) acc_l += l1p[i];
-  for (int64_t i = threadIdx.x; i < ns; i += 256) acc_s += sp[i];
-  s_red[threadIdx.x] = a * acc_l + b * acc_s;
+// First stage of the deterministic reduction: block b sums the fixed chunk
+// [b * chunk, min((b + 1) * chunk, n)) of each partial array in double, in a fixed order.
+__global__ __launch_bounds__(256) void k_reduce_stage(const float* __restrict__ l1p, const float* __restrict__ sp,
+                                                      int64_t n, int64_t chunk, double* __restrict__ out) {
+  __shared__ double s_l[256], s_s[256];
+  const int64_t lo = static_cast<int64_t>(blockIdx.x) * chunk;
+  const int64_t hi = min(lo + chunk, n);
+  double al = 0.0, as = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+    al += l1p[i];
+    if (sp) as += sp[i];
+  }
+  s_l[threadIdx.x] = al;
+  s_s[threadIdx.x] = as;
   __syncthreads();
   for (int st = 128; st >= 1; st >>= 1) {
+    if (static_cast<int>(threadIdx.x) < st) {
+      s_l[threadIdx.x] += s_l[threadIdx.x + st];
+      s_s[threadIdx.x] += s_s[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = s_l[0];
+    out[2 * blockIdx.x + 1] = s_s[0];
+  }
+}
+
+// Second stage: loss = a * sum(l1 parts) + b * sum(ssim parts) + c, summed in a fixed order.
+__global__ void k_finalize(const double* __restrict__ parts, double a, double b, double c0,
+                           float* __restrict__ loss) {
+  __shared__ double s_red[kRedBlocks];
+  s_red[threadIdx.x] = a * parts[2 * threadIdx.x] + b * parts[2 * threadIdx.x + 1];
+  __syncthreads();
+  for (int st = kRedBlocks / 2; st >= 1; st >>= 1) {
     if (static_cast<int>(threadIdx.x) < st) s_red[threadIdx.x] += s_red[threadIdx.x + st];
     __syncthreads();
   }
@@ -207,10 +279,11 @@ extern "C" size_t vbm_image_loss_workspace_size(const int32_t* dims, int32_t n_v
   for (int v = 0; v < n_views; ++v) {
     const int64_t W = dims[2 * v], H = dims[2 * v + 1];
     px += W * H;
-    blocks += ceil_div(W, TS) * ceil_div(H, TS) * 3;
+    blocks += ceil_div(W, TX) * ceil_div(H, TY) * 3;
   }
-  if (kind == 0) return align_up(kL1Blocks * 4, 256);
-  return 3 * align_up(3 * px * 4, 256) + 2 * align_up(blocks * 4, 256);
+  const size_t red = align_up(2 * kRedBlocks * sizeof(double), 256);
+  if (kind == 0) return align_up(kL1Blocks * 4, 256) + red;
+  return 3 * align_up(3 * px * 4, 256) + 2 * align_up(blocks * 4, 256) + red;
 }
 
 extern "C" vbm_status vbm_image_loss(const float* image, const float* target, const int32_t* dims, int32_t n_views,
@@ -238,31 +311,36 @@ extern "C" vbm_status vbm_image_loss(const float* image, const float* target, co
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n = 3 * px;
+  const double dn = static_cast<double>(n);
+  Carver c(ws);
   if (kind == 0) {
-    float* partial = static_cast<float*>(ws);
+    float* partial = c.take<float>(kL1Blocks);
+    double* parts = c.take<double>(2 * kRedBlocks);
     hipLaunchKernelGGL(k_l1, dim3(kL1Blocks), dim3(256), 0, s, image, target, n, 1.0f / static_cast<float>(n), grad,
                        partial);
     VBM_LAUNCH_CHECK("loss_l1");
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partial, static_cast<int64_t>(kL1Blocks), partial,
-                       static_cast<int64_t>(0), 1.0 / static_cast<double>(n), 0.0, 0.0, loss);
+    hipLaunchKernelGGL(k_reduce_stage, dim3(kRedBlocks), dim3(256), 0, s, partial, static_cast<const float*>(nullptr),
+                       static_cast<int64_t>(kL1Blocks), ceil_div(kL1Blocks, kRedBlocks), parts);
+    VBM_LAUNCH_CHECK("loss_reduce");
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlocks), 0, s, parts, 1.0 / dn, 0.0, 0.0, loss);
     VBM_LAUNCH_CHECK("loss_finalize");
     return VBM_OK;
   }
-  Carver c(ws);
   float* p1 = c.take<float>(n);
   float* p2 = c.take<float>(n);
   float* p3 = c.take<float>(n);
   int64_t blocks = 0;
-  for (int v = 0; v < n_views; ++v) blocks += ceil_div(dims[2 * v], TS) * ceil_div(dims[2 * v + 1], TS) * 3;
+  for (int v = 0; v < n_views; ++v) blocks += ceil_div(dims[2 * v], TX) * ceil_div(dims[2 * v + 1], TY) * 3;
   float* ps = c.take<float>(blocks);
   float* pl = c.take<float>(blocks);
+  double* parts = c.take<double>(2 * kRedBlocks);
   const Window win = make_window();
   const float w_l1 = (1.0f - lambda) / static_cast<float>(n);
   const float w_ss = lambda / static_cast<float>(n);
   int64_t off = 0, boff = 0;
   for (int v = 0; v < n_views; ++v) {
     const int W = dims[2 * v], H = dims[2 * v + 1];
-    const dim3 grid(static_cast<unsigned>(ceil_div(W, TS)), static_cast<unsigned>(ceil_div(H, TS)), 3);
+    const dim3 grid(static_cast<unsigned>(ceil_div(W, TX)), static_cast<unsigned>(ceil_div(H, TY)), 3);
     hipLaunchKernelGGL(k_ssim_maps, grid, dim3(256), 0, s, image + off, target + off, W, H, win, p1 + off, p2 + off,
                        p3 + off, ps + boff, pl + boff);
     VBM_LAUNCH_CHECK("ssim_maps");
@@ -272,8 +350,10 @@ extern "C" vbm_status vbm_image_loss(const float* image, const float* target, co
     off += 3 * static_cast<int64_t>(W) * H;
     boff += static_cast<int64_t>(grid.x) * grid.y * 3;
   }
-  const double dn = static_cast<double>(n);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, pl, blocks, ps, blocks, (1.0 - lambda) / dn, -lambda / dn,
+  hipLaunchKernelGGL(k_reduce_stage, dim3(kRedBlocks), dim3(256), 0, s, pl, ps, blocks,
+                     ceil_div(blocks, kRedBlocks), parts);
+  VBM_LAUNCH_CHECK("loss_reduce");
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedBlocks), 0, s, parts, (1.0 - lambda) / dn, -lambda / dn,
                      static_cast<double>(lambda), loss);
   VBM_LAUNCH_CHECK("loss_finalize");
   return VBM_OK;
