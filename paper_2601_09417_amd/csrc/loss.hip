@@ -35,6 +35,7 @@ constexpr int RPT = 4;             // output rows per thread in the vertical pas
 constexpr int kRedBlocks = 256;    // first stage of the partial-sum reduction
 constexpr float kC1 = 0.01f * 0.01f;
 constexpr float kC2 = 0.03f * 0.03f;
+constexpr int kLoads = (EX * EY + 255) / 256;  // halo elements per thread
 static_assert(TX * (TY / RPT) == 256, "vertical pass covers the tile with 256 threads");
 
 struct Window {
@@ -94,12 +95,24 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
   const float* xc = x + c * HW;
   const float* yc = y + c * HW;
   const int ox = blockIdx.x * TX - RAD, oy = blockIdx.y * TY - RAD;
-  for (int i = threadIdx.x; i < EX * EY; i += 256) {
+  // All of a thread's halo loads are issued before the first LDS store, so their latencies overlap.
+  float vx[kLoads], vy[kLoads];
+#pragma unroll
+  for (int k = 0; k < kLoads; ++k) {
+    const int i = threadIdx.x + 256 * k;
     const int r = i / EX, q = i % EX;
     const int gx = ox + q, gy = oy + r;
-    const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
-    sx[r][q] = in ? xc[static_cast<int64_t>(gy) * W + gx] : 0.0f;
-    sy[r][q] = in ? yc[static_cast<int64_t>(gy) * W + gx] : 0.0f;
+    const bool in = i < EX * EY && gx >= 0 && gx < W && gy >= 0 && gy < H;
+    vx[k] = in ? xc[static_cast<int64_t>(gy) * W + gx] : 0.0f;
+    vy[k] = in ? yc[static_cast<int64_t>(gy) * W + gx] : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < kLoads; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    if (i < EX * EY) {
+      sx[i / EX][i % EX] = vx[k];
+      sy[i / EX][i % EX] = vy[k];
+    }
   }
   __syncthreads();
   const int col = threadIdx.x % TX;
@@ -175,13 +188,23 @@ __global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ x, 
   const int64_t HW = static_cast<int64_t>(W) * H;
   const int ox = blockIdx.x * TX - RAD, oy = blockIdx.y * TY - RAD;
   const float* P[3] = {p1 + c * HW, p2 + c * HW, p3 + c * HW};
-  for (int i = threadIdx.x; i < EX * EY; i += 256) {
+  float vp[3][kLoads];
+#pragma unroll
+  for (int k = 0; k < kLoads; ++k) {
+    const int i = threadIdx.x + 256 * k;
     const int r = i / EX, q = i % EX;
     const int gx = ox + q, gy = oy + r;
-    const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
+    const bool in = i < EX * EY && gx >= 0 && gx < W && gy >= 0 && gy < H;
     const int64_t off = static_cast<int64_t>(gy) * W + gx;
 #pragma unroll
-    for (int f = 0; f < 3; ++f) sp[f][r][q] = in ? P[f][off] : 0.0f;
+    for (int f = 0; f < 3; ++f) vp[f][k] = in ? P[f][off] : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < kLoads; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    if (i < EX * EY)
+#pragma unroll
+      for (int f = 0; f < 3; ++f) sp[f][i / EX][i % EX] = vp[f][k];
   }
   __syncthreads();
   const int col = threadIdx.x % TX;

@@ -161,7 +161,8 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
                                                  float* __restrict__ depth, uint32_t* __restrict__ rect,
                                                  uint32_t* __restrict__ ntiles, float4* __restrict__ rec,
                                                  float4* __restrict__ coef, float* __restrict__ blue,
-                                                 uint32_t* __restrict__ vis_flag, int64_t n_items) {
+                                                 uint32_t* __restrict__ vis_flag, uint32_t* __restrict__ reach_mask,
+                                                 int64_t n_items) {
   const DevView& v = views[blockIdx.y];
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= v.n_gauss) return;
@@ -172,16 +173,21 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
   const ProjResult p = project_one(v, tile, g.means[gi], g.means[S + gi], g.means[2 * S + gi], g.scales[gi],
                                    g.scales[S + gi], g.scales[2 * S + gi], g.quats[gi], g.quats[S + gi],
                                    g.quats[2 * S + gi], g.quats[3 * S + gi], op);
-  uint32_t nt = 0;
+  // Reached tiles of the rectangle; for rectangles of at most 32 tiles their row-major bit mask is
+  // kept so that emission does not evaluate the footprint test again.
+  uint32_t nt = 0, mask = 0;
   if (p.visible) {
     const float tau = footprint_tau(op);
+    uint32_t bit = 0;
     for (uint32_t ty = p.y0; ty < p.y1; ++ty)
-      for (uint32_t tx = p.x0; tx < p.x1; ++tx)
-        nt += tile_reached(p.px, p.py, p.ca, p.cb, p.cc, tau, static_cast<int>(tx), static_cast<int>(ty), tile,
-                           v.width, v.height)
-                  ? 1u
-                  : 0u;
+      for (uint32_t tx = p.x0; tx < p.x1; ++tx, ++bit) {
+        const bool hit = tile_reached(p.px, p.py, p.ca, p.cb, p.cc, tau, static_cast<int>(tx), static_cast<int>(ty),
+                                      tile, v.width, v.height);
+        nt += hit ? 1u : 0u;
+        mask |= (hit && bit < 32) ? (1u << bit) : 0u;
+      }
   }
+  reach_mask[item] = mask;
   depth[item] = p.visible ? p.depth : 0.0f;
   rect[item] = p.x0 | (p.x1 << 16);
   rect[n_items + item] = p.y0 | (p.y1 << 16);
@@ -230,7 +236,7 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
                                               const uint32_t* __restrict__ rect, const float4* __restrict__ rec,
                                               int tile, int64_t n_items, uint32_t* __restrict__ counters,
                                               int64_t n_max, int64_t capacity, uint32_t* __restrict__ pair_tile,
-                                              uint32_t* __restrict__ pair_item) {
+                                              uint32_t* __restrict__ pair_item, const uint32_t* __restrict__ reach_mask) {
   const int64_t n = min(static_cast<int64_t>(counters[0]), n_max);
   for (int64_t p = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; p < n;
        p += static_cast<int64_t>(gridDim.x) * 256) {
@@ -238,11 +244,28 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
     const DevView& v = views[keys[p] >> 32];
     const uint32_t rx = rect[item], ry = rect[n_items + item];
     const uint32_t x0 = rx & 0xFFFFu, x1 = rx >> 16, y0 = ry & 0xFFFFu, y1 = ry >> 16;
+    int64_t o = offs[p];
+    bool over = false;
+    const uint32_t w = x1 - x0;
+    if (w * (y1 - y0) <= 32) {
+      // Small rectangle: the projection's mask lists the reached tiles in row-major order.
+      for (uint32_t m = reach_mask[item]; m; m &= m - 1) {
+        const uint32_t b = static_cast<uint32_t>(__builtin_ctz(m));
+        const uint32_t tx = x0 + b % w, ty = y0 + b / w;
+        if (o < capacity) {
+          pair_tile[o] = static_cast<uint32_t>(v.tile_offset) + ty * static_cast<uint32_t>(v.tiles_x) + tx;
+          pair_item[o] = item;
+        } else {
+          over = true;
+        }
+        ++o;
+      }
+      if (over) counters[2] = 1u;
+      continue;
+    }
     const float4 ra = rec[2 * static_cast<int64_t>(item)];
     const float4 rb = rec[2 * static_cast<int64_t>(item) + 1];
     const float tau = footprint_tau(rb.y);
-    int64_t o = offs[p];
-    bool over = false;
     for (uint32_t ty = y0; ty < y1; ++ty)
       for (uint32_t tx = x0; tx < x1; ++tx) {
         if (!tile_reached(ra.x, ra.y, ra.z, ra.w, rb.x, tau, static_cast<int>(tx), static_cast<int>(ty), tile, v.width,
