@@ -44,9 +44,9 @@ BYTES_PER_PAIR_BWD, BYTES_PER_PIXEL_BWD = 76, 20
 WORKLOADS = {
     "H": dict(config=3, G=512, J=5, wavelet="bior4.4", K=1_000_000, views=8, W=1920, H=1080, tile=16,
               loss="l1_dssim", desc="512^3 turbulence (E(k)~k^-5/3, kmax 64), bior4.4 J=5, top-1M Gaussians, "
-                                    "8 orbit views 1920x1080, tile 16, loss 0.8 L1 + 0.2 D-SSIM, Adam"),
+                                    "8 orbit views 1920x1080, loss 0.8 L1 + 0.2 D-SSIM, Adam"),
     "c1": dict(config=1, G=128, J=3, wavelet="haar", K=100_000, views=16, W=800, H=800, tile=16, loss="l1",
-               desc="128^3 blobs + k^-2 noise, Haar J=3, top-100k Gaussians, 16 orbit views 800x800, tile 16, L1, Adam"),
+               desc="128^3 blobs + k^-2 noise, Haar J=3, top-100k Gaussians, 16 orbit views 800x800, L1, Adam"),
 }
 
 
@@ -213,8 +213,21 @@ def run_gpu(args, wl):
         wall = time.perf_counter() - t
         return wall, e0.elapsed_time(e1) / 1e3
 
+    # schedule knobs: the autotuner times each (tile, radix digit) candidate on the eager batched
+    # step before anything is captured or timed
+    loss_kind = wl["loss"] if args.loss == "default" else args.loss
+    if args.tile == "auto":
+        tune = trainer.autotune(P, cams, targets, loss=loss_kind, lam=0.2)
+        tile, bits = tune["tile"], tune["sort_bits"]
+        out["autotune"] = [dict(tile=d["tile"], sort_bits=d["sort_bits"], ms=round(d["ms"], 3)) for d in tune["table"]]
+        log("autotune: " + ", ".join(f"tile {d['tile']}/{d['sort_bits']}b {d['ms']:.2f} ms" for d in tune["table"])
+            + f" -> tile {tile}, {bits}-bit digits")
+    else:
+        tile, bits = int(args.tile), 8
+    out["tile"], out["sort_bits"], out["loss_kind"] = tile, bits, loss_kind
+
     # batched schedule, captured as a graph: the reported value
-    ft = trainer.FineTuner(P, cams, targets, loss=wl["loss"], lam=0.2, tile=wl["tile"], schedule="graph")
+    ft = trainer.FineTuner(P, cams, targets, loss=loss_kind, lam=0.2, tile=tile, sort_bits=bits, schedule="graph")
     wall, ev = timed(ft, args.steps, args.warmup)
     if ft.overflowed():
         raise RuntimeError("pair capacity overflow during the timed region")
@@ -225,7 +238,7 @@ def run_gpu(args, wl):
     del ft
 
     # kernel-level timing of the compositing kernels on the eager batched schedule
-    fb = trainer.FineTuner(P, cams, targets, loss=wl["loss"], lam=0.2, tile=wl["tile"], schedule="batched")
+    fb = trainer.FineTuner(P, cams, targets, loss=loss_kind, lam=0.2, tile=tile, sort_bits=bits, schedule="batched")
     for _ in range(args.warmup):
         fb.step()
     counters = torch.zeros(4, dtype=torch.int64, device=dev)
@@ -260,7 +273,7 @@ def run_gpu(args, wl):
 
     # plain schedule: one view per launch, one host sync per view forward
     if not args.skip_plain:
-        fp = trainer.FineTuner(P, cams, targets, loss=wl["loss"], lam=0.2, tile=wl["tile"], schedule="plain")
+        fp = trainer.FineTuner(P, cams, targets, loss=loss_kind, lam=0.2, tile=tile, sort_bits=bits, schedule="plain")
         wall_p, _ = timed(fp, args.steps, args.warmup)
         out["plain_wall_s"] = wall_p
         log(f"plain: {args.steps / wall_p:.2f} it/s")
@@ -274,6 +287,10 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="H", choices=sorted(WORKLOADS))
+    ap.add_argument("--tile", default="auto", choices=["auto", "8", "16", "32"],
+                    help="tile edge; auto = pick (tile, radix digit) by timing each before the timed run")
+    ap.add_argument("--loss", default="default", choices=["default", "l1", "l1_dssim"],
+                    help="image loss; default = the workload's")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--cpu-tiles", type=int, default=256, help="tiles in the CPU oracle sample")
@@ -313,7 +330,9 @@ def main() -> int:
     value = args.steps / gpu["batched_wall_s"]
     plain = args.steps / gpu["plain_wall_s"] if "plain_wall_s" in gpu else None
     k = gpu["kernels"]["composite_bwd"]
-    traffic = traffic_from_profiles(os.path.join(ROOT, "paper_2601_09417_amd", "csrc", "raster.hip"))
+    # the committed counter run covers the 16x16-tile kernel of the workload's own loss only
+    traffic = (traffic_from_profiles(os.path.join(ROOT, "paper_2601_09417_amd", "csrc", "raster.hip"))
+               if gpu["tile"] == 16 and gpu["loss_kind"] == wl["loss"] else None)
     result = {
         "metric": "fine-tune iters/sec (fwd+bwd, 1M Gaussians, 1080p, 8 views) batched vs plain",
         "value": round(value, 4),
@@ -328,7 +347,9 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl['desc']}", "gaussians": wl["K"], "views": wl["views"],
-                   "width": wl["W"], "height": wl["H"], "tile": wl["tile"], "schedule": "batched, HIP graph"},
+                   "width": wl["W"], "height": wl["H"], "tile": gpu["tile"], "sort_bits": gpu["sort_bits"],
+                   "loss": gpu["loss_kind"], "schedule": "batched, HIP graph"},
+        "autotune": gpu.get("autotune"),
         "plain_value": None if plain is None else round(plain, 4),
         "batched_over_plain": None if plain is None else round(value / plain, 3),
         "pairs_per_step": gpu["pairs_per_step"],

@@ -8,8 +8,12 @@
     batched  every view (and scene) in one launch per phase, counts kept on the device
     graph    the batched step captured once in a HIP graph and replayed
   All three produce identical pair lists and images; gradients agree up to float atomics order.
+* ``autotune``   -- times the batched step for each (tile, radix digit) candidate and picks the
+  fastest; run before capture, on a copy of the parameters.
 """
 from __future__ import annotations
+
+import time
 
 import numpy as np
 import torch
@@ -142,3 +146,35 @@ class FineTuner:
 
     def loss(self) -> float:
         return float(self.loss_fn.loss.item())
+
+
+TUNE_CANDIDATES = ((16, 8), (8, 8), (32, 8), (16, 4))
+
+
+def autotune(P: torch.Tensor, cams, targets: torch.Tensor, scene_offsets=None, view_scene=None, loss: str = "l1",
+             lam: float = 0.2, candidates=TUNE_CANDIDATES, steps: int = 3, warmup: int = 1) -> dict:
+    """Chooses the tile edge and the radix digit width of the tile sort for a batch.
+
+    Each candidate (tile, sort_bits) gets its own plan (exact pair counts, capacity margin) and runs
+    ``warmup`` + ``steps`` eager batched iterations on a copy of P (FineTuner clones it), timed with a
+    device synchronisation on both sides.  Returns the fastest as dict(tile, sort_bits, ms) plus the
+    table of every candidate's ms per step.
+    """
+    table = []
+    for tile, bits in candidates:
+        ft = FineTuner(P, cams, targets, scene_offsets, view_scene, tile=tile, sort_bits=bits, loss=loss, lam=lam,
+                       schedule="batched")
+        for _ in range(warmup):
+            ft.step()
+        torch.cuda.synchronize(P.device)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ft.step()
+        torch.cuda.synchronize(P.device)
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        if ft.overflowed():
+            ms = float("inf")
+        table.append(dict(tile=tile, sort_bits=bits, ms=ms))
+        del ft
+    best = min(table, key=lambda d: d["ms"])
+    return dict(tile=best["tile"], sort_bits=best["sort_bits"], ms=best["ms"], table=table)
