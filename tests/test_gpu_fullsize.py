@@ -1,0 +1,175 @@
+"""GPU parity at the benchmark's full size, checked on samples the oracle computes one by one.
+
+Workload: the 512^3 turbulence volume and its transfer function, bior4.4 J=5, the top 1,000,000
+Gaussians, 8 orbit views at 1920x1080, 16x16 tiles, one batched launch over all views (the launch
+configuration bench.py times).  Checked against the oracle:
+
+* DWT: sampled coefficients of every level as inner products of the transfer-functioned volume with
+  three 1D analysis rows (the oracle's own analysis step applied to an identity matrix);
+* selection: the complete top-K set, stage-isolated on the GPU's float32 coefficients (bit-exact);
+* construction: a random sample of the kept Gaussians against the oracle's bank and construction;
+* rendering: two views' pair lists (bit-exact) and the images of sampled tiles; for the backward,
+  dL/dI is nonzero only on those tiles, so the oracle's autodiff over the same tiles gives every
+  Gaussian's exact gradient.
+"""
+import numpy as np
+import pytest
+import torch
+
+import vbm_inputs as vi
+from oracle import bank as obank
+from oracle import binning, render
+from oracle import construct as oconstruct
+from oracle import dwt as odwt
+from oracle import select as oselect
+from oracle import tf as otf
+from oracle import wavelets
+from tests.gpu_common import GRAD_TOL, IMG_TOL, ROWS, dev, group_error, say
+
+pytestmark = pytest.mark.gpu
+
+G, J, WAV, K = 512, 5, "bior4.4", 1_000_000
+VIEWS, W, H, TILE = 8, 1920, 1080, 16
+
+
+@pytest.fixture(scope="module")
+def h_case():
+    from paper_2601_09417_amd import api
+    say("full size: building the 512^3 volume and its 1M Gaussians")
+    vol = vi.volume_for_config(3)
+    tfn = vi.transfer_function(3)
+    coeffs = api.dwt3d(torch.from_numpy(vol).to(dev()), J, WAV, (tfn.xs, tfn.rgba))
+    _, packed = api.bank_build(WAV, J)
+    P, kept = api.build_gaussians(coeffs, G, J, packed, K, s_mode="none")
+    torch.cuda.synchronize()
+    return dict(api=api, vol=vol, tf=tfn, coeffs=coeffs, P=P, kept=kept,
+                cams=vi.orbit_cameras(VIEWS, W, H))
+
+
+def _analysis_rows(bank, j: int):
+    """1D level-j analysis operators: {band: matrix [G >> j][G]} with row k the filter of output k."""
+    cur = np.eye(G)
+    for _ in range(j - 1):
+        cur = odwt.analysis_1d(cur, bank, 0)[0]
+    lo, hi = odwt.analysis_1d(cur, bank, 0)
+    return {0: lo, 1: hi}
+
+
+def test_fullsize_dwt_sampled_coefficients(h_case):
+    bank = wavelets.get(WAV)
+    rng = np.random.default_rng(31)
+    offs = odwt.block_offsets(G, J)
+    samples = [(J, 0)] + [(j, o) for j in (1, J) for o in range(1, 8)] + \
+              [(j, int(rng.integers(1, 8))) for j in range(2, J)]
+    idx = [offs[b][0] + int(rng.integers(0, offs[b][1] ** 3)) for b in samples]
+    rows = {j: _analysis_rows(bank, j) for j in range(1, J + 1)}
+    gpu = h_case["coeffs"][:, torch.as_tensor(idx, device=dev())].cpu().numpy().astype(np.float64)
+    scale = {b: max(float(h_case["coeffs"][:, offs[b][0]:offs[b][0] + offs[b][1] ** 3].abs().max()), 1e-12)
+             for b in set(samples)}
+    ref = np.zeros((4, len(idx)))
+    rf = otf.apply(h_case["vol"], h_case["tf"].xs, h_case["tf"].rgba)      # [4][z][y][x] FP64
+    for c in range(4):
+        flat = rf[c].reshape(G * G, G)                               # [z*y][x]
+        for s, p in enumerate(idx):
+            j, o, (kx, ky, kz) = odwt.decode_index(p, G, J)
+            vx, vy, vz = (rows[j][(o >> d) & 1][k] for d, k in ((0, kx), (1, ky), (2, kz)))
+            t = (flat @ vx).reshape(G, G)                           # [z][y]
+            ref[c, s] = vz @ (t @ vy)
+    del rf
+    for s, b in enumerate(samples):
+        err = np.abs(gpu[:, s] - ref[:, s]).max() / scale[b]
+        assert err <= 1e-5, (b, idx[s], err)
+    say(f"  {len(idx)} sampled coefficients within 1e-5 of their subband maximum")
+
+
+def test_fullsize_selection_and_construction(h_case):
+    coeffs = h_case["coeffs"].cpu().numpy()
+    ref_kept = oselect.topk(coeffs, K)                      # stage-isolated: same float32 values
+    assert np.array_equal(h_case["kept"].cpu().numpy(), ref_kept)
+    rng = np.random.default_rng(32)
+    pick = np.sort(rng.choice(K, 2000, replace=False))
+    ref = oconstruct.construct(coeffs, ref_kept[pick], G, J, obank.build_bank(WAV, J), s_mode="none")
+    Pn = h_case["P"][:, torch.as_tensor(pick, device=dev())].cpu().numpy()
+    for name, rows in ROWS.items():
+        r = ref[name].reshape(rows.stop - rows.start, -1)
+        err = np.abs(Pn[rows] - r).max() / max(np.abs(r).max(), 1e-6)
+        assert err <= 1e-6, (name, err)
+
+
+def _gaussian_set(P: torch.Tensor) -> vi.GaussianSet:
+    p = P.cpu().numpy()
+    return vi.GaussianSet(means=p[0:3].copy(), scales=p[3:6].copy(), quats=p[6:10].copy(), opacity=p[10].copy(),
+                          rgb=p[11:14].copy())
+
+
+def test_fullsize_render_sampled_tiles(h_case):
+    api, P, cams = h_case["api"], h_case["P"], h_case["cams"]
+    N = P.shape[1]
+    rp = api.plan_batch(cams, [0, N], tile=TILE, sort_bits=8, pair_capacity=32_000_000, mode="batched")
+    out = api.render_fwd(rp, P)
+    torch.cuda.synchronize()
+    assert int(out.status[0]) == 0
+    gs = _gaussian_set(P)
+    toff = binning.tile_grid(cams, TILE)
+    ptile = rp.region("pair_tile", torch.int32).cpu().numpy()
+    pitem = rp.region("pair_item", torch.int32).cpu().numpy()
+    ranges = rp.region("ranges", torch.int32).cpu().numpy().reshape(-1, 2)
+    imgs = [t.cpu().numpy() for t in api.split_views(out.image, cams)]
+    rng = np.random.default_rng(33)
+    dL = [np.zeros((3, H, W), np.float32) for _ in cams]
+    tiles = []                                              # (view, tx, ty, items, pixel xs, ys, flagged)
+    err_img, img_max = 0.0, 0.0
+    for v in (1, 6):
+        ref = binning.pair_lists(gs, [cams[v]], TILE)
+        TX = -(-W // TILE)
+        nonempty = np.nonzero(ref["ranges"][:, 1] > ref["ranges"][:, 0])[0]
+        longest = int(np.argmax(ref["ranges"][:, 1] - ref["ranges"][:, 0]))
+        for lt in np.unique(np.concatenate([rng.choice(nonempty, 10, replace=False), [longest]])):
+            s, e = ref["ranges"][lt]
+            gs_, ge_ = ranges[toff[v] + lt]
+            assert np.array_equal(ptile[gs_:ge_], np.full(e - s, toff[v] + lt))
+            items = ref["item"][s:e]
+            assert np.array_equal(pitem[gs_:ge_] - v * N, items)            # view v's items start at v*N
+            tx, ty = int(lt % TX), int(lt // TX)
+            xs, ys = render._tile_pixels(cams[v], TILE, tx, ty)
+            it = torch.as_tensor(items, dtype=torch.int64)
+            m2d, con, _ = render.project_fp64(render._t(gs.means)[:, it], render._t(gs.scales)[:, it],
+                                              render._t(gs.quats)[:, it], cams[v])
+            pix = torch.stack([render._t(xs + 0.5), render._t(ys + 0.5)], 1)
+            col, _, _, fl, _ = render.composite_tile(pix, m2d, con, render._t(gs.opacity)[it],
+                                                     render._t(gs.rgb)[:, it].T, render._t(cams[v].bg))
+            col, fl = col.numpy(), fl.numpy()
+            ok = ~fl
+            err_img = max(err_img, float(np.abs(imgs[v][:, ys, xs].T - col)[ok].max(initial=0.0)))
+            img_max = max(img_max, float(np.abs(col).max()))
+            d = rng.normal(size=(3, xs.size)).astype(np.float32)
+            d[:, fl] = 0.0
+            dL[v][:, ys, xs] = d
+            tiles.append((v, items, xs, ys, d))
+    assert err_img <= IMG_TOL * max(img_max, 1e-6), (err_img, img_max)
+    say(f"  {len(tiles)} sampled tiles: image error {err_img / max(img_max, 1e-6):.2e}")
+
+    flat = torch.from_numpy(np.concatenate([d.reshape(-1) for d in dL])).to(dev())
+    g = api.render_bwd(rp, P, flat, out).cpu().numpy()
+    involved = np.unique(np.concatenate([t[1] for t in tiles]))
+    outside = np.setdiff1d(np.arange(N), involved)
+    assert np.all(g[:, outside] == 0.0)
+    inv = torch.as_tensor(involved, dtype=torch.int64)
+    leaf = {k: render._t(np.asarray(getattr(gs, k), np.float64))[..., inv].clone().requires_grad_(True)
+            for k in ("means", "scales", "quats", "opacity", "rgb")}
+    pos = {int(gi): i for i, gi in enumerate(involved)}
+    total = 0.0
+    for v, items, xs, ys, d in tiles:
+        loc = torch.as_tensor([pos[int(i)] for i in items], dtype=torch.int64)
+        m2d, con, _ = render.project_fp64(leaf["means"][:, loc], leaf["scales"][:, loc], leaf["quats"][:, loc],
+                                          cams[v])
+        pix = torch.stack([render._t(xs + 0.5), render._t(ys + 0.5)], 1)
+        col, _, _, _, _ = render.composite_tile(pix, m2d, con, leaf["opacity"][loc], leaf["rgb"][:, loc].T,
+                                                render._t(cams[v].bg))
+        total = total + (col * render._t(d.T.astype(np.float64))).sum()
+    total.backward()
+    for name, rows in ROWS.items():
+        r = leaf[name].grad.numpy().reshape(rows.stop - rows.start, -1)
+        e = group_error(g[rows][:, involved], r)
+        say(f"  grad {name}: {e:.2e}")
+        assert e <= GRAD_TOL, name
