@@ -33,6 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+METRIC = "fine-tune iters/sec (fwd+bwd, 1M Gaussians, 1080p, 8 views) batched vs plain"
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 # Algorithmic cost per (pixel, Gaussian) evaluation of the compositing kernels.
@@ -332,9 +333,11 @@ def main() -> int:
     k = gpu["kernels"]["composite_bwd"]
     # the committed counter run covers the 16x16-tile kernel of the workload's own loss only
     traffic = (traffic_from_profiles(os.path.join(ROOT, "paper_2601_09417_amd", "csrc", "raster.hip"))
-               if gpu["tile"] == 16 and gpu["loss_kind"] == wl["loss"] else None)
+               if args.workload == "H" and gpu["tile"] == 16 and gpu["loss_kind"] == wl["loss"] else None)
     result = {
-        "metric": "fine-tune iters/sec (fwd+bwd, 1M Gaussians, 1080p, 8 views) batched vs plain",
+        "metric": (METRIC if args.workload == "H" else
+                   f"fine-tune iters/sec (fwd+bwd, {wl['K']} Gaussians, {wl['W']}x{wl['H']}, {wl['views']} views) "
+                   "batched vs plain"),
         "value": round(value, 4),
         "unit": "iters/sec",
         "n_gpus": 1,
