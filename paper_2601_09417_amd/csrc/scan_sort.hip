@@ -4,7 +4,8 @@
 // offset added.  Sort: per pass a digit histogram per 4096-key tile, an exclusive scan of the
 // digit-major histogram (digit * n_tiles + tile), then a stable scatter that ranks equal digits
 // inside each wave with ballots (a lane's rank = set bits of its digit-match mask below it) and
-// across the block's waves and rounds through LDS counters.
+// across the block's waves and rounds through LDS counters, partitions the tile in LDS, and writes
+// it out in digit order (coalesced runs).
 #include <hip/hip_runtime.h>
 
 #include "block_scan.h"
@@ -18,6 +19,7 @@ constexpr int kThreads = 256;
 constexpr int kItems = 16;
 constexpr int kChunk = kThreads * kItems;  // elements per block
 constexpr int kWaves = kThreads / 64;
+static_assert(kThreads == 256, "one thread per 8-bit digit in the scatter's LDS bookkeeping");
 
 __device__ __forceinline__ int64_t active_count(int64_t n_max, const uint32_t* n_dev) {
   if (!n_dev) return n_max;
@@ -126,28 +128,55 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const K* __restrict__ k
   for (int d = threadIdx.x; d < radix; d += kThreads) hist[static_cast<int64_t>(d) * n_blocks + blockIdx.x] = s_hist[d];
 }
 
+// Stable scatter of one 4096-key tile: the tile is first partitioned by digit inside LDS (ranks
+// from wave ballots, in index order), then written out in digit order, so consecutive lanes store
+// to consecutive addresses of a digit's output run instead of 64 different buckets.
 template <class K>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                             K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                             const uint32_t* __restrict__ offsets, int64_t n_max,
                                                             const uint32_t* n_dev, int shift, int bits,
                                                             int64_t n_blocks) {
-  __shared__ uint32_t s_run[256];
+  __shared__ K s_key[kChunk];
+  __shared__ uint32_t s_val[kChunk];
+  __shared__ uint32_t s_start[256];   // local start of each digit in the partitioned tile
+  __shared__ uint32_t s_run[256];     // next free local slot of each digit while ranking
+  __shared__ uint32_t s_glob[256];    // global start of this tile's run of each digit
   __shared__ uint32_t s_wave_cnt[kWaves][256];
   const int64_t n = active_count(n_max, n_dev);
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kChunk;
   if (base >= n) return;  // uniform per block
+  const int count = static_cast<int>(min(static_cast<int64_t>(kChunk), n - base));
   const int radix = 1 << bits;
   const uint32_t mask = static_cast<uint32_t>(radix - 1);
   const int w = threadIdx.x >> 6;
-  for (int d = threadIdx.x; d < radix; d += kThreads) s_run[d] = offsets[static_cast<int64_t>(d) * n_blocks + blockIdx.x];
+  K keys[kItems];
+  uint32_t vals[kItems];
+#pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    const int64_t i = base + r * kThreads + threadIdx.x;
-    const bool valid = i < n;
-    K key = valid ? kin[i] : K(0);
-    uint32_t val = valid ? vin[i] : 0u;
-    const uint32_t d = static_cast<uint32_t>(key >> shift) & mask;
-    for (int x = threadIdx.x; x < kWaves * radix; x += kThreads) (&s_wave_cnt[0][0])[(x / radix) * 256 + (x % radix)] = 0;
+    const int li = r * kThreads + threadIdx.x;
+    keys[r] = li < count ? kin[base + li] : K(0);
+    vals[r] = li < count ? vin[base + li] : 0u;
+  }
+  // local digit histogram -> local starts
+  s_run[threadIdx.x] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r)
+    if (r * kThreads + static_cast<int>(threadIdx.x) < count)
+      atomicAdd(&s_run[static_cast<uint32_t>(keys[r] >> shift) & mask], 1u);
+  __syncthreads();
+  uint32_t tot;
+  const uint32_t start = block_excl_scan(s_run[threadIdx.x], &tot);
+  s_start[threadIdx.x] = start;
+  s_run[threadIdx.x] = start;
+  if (static_cast<int>(threadIdx.x) < radix)
+    s_glob[threadIdx.x] = offsets[static_cast<int64_t>(threadIdx.x) * n_blocks + blockIdx.x];
+  // rank in index order and place into LDS
+  for (int r = 0; r < kItems; ++r) {
+    const bool valid = r * kThreads + static_cast<int>(threadIdx.x) < count;
+    const uint32_t d = static_cast<uint32_t>(keys[r] >> shift) & mask;
+    for (int x = threadIdx.x; x < kWaves * 256; x += kThreads) (&s_wave_cnt[0][0])[x] = 0;
     __syncthreads();
     uint64_t m = __ballot(valid);
     for (int b = 0; b < bits; ++b) {
@@ -161,17 +190,29 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const K* __restrict_
     if (valid) {
       uint32_t pos = s_run[d] + rank;
       for (int ww = 0; ww < w; ++ww) pos += s_wave_cnt[ww][d];
-      kout[pos] = key;
-      vout[pos] = val;
+      s_key[pos] = keys[r];
+      s_val[pos] = vals[r];
     }
     __syncthreads();
-    for (int dd = threadIdx.x; dd < radix; dd += kThreads) {
+    {
       uint32_t add = 0;
 #pragma unroll
-      for (int ww = 0; ww < kWaves; ++ww) add += s_wave_cnt[ww][dd];
-      s_run[dd] += add;
+      for (int ww = 0; ww < kWaves; ++ww) add += s_wave_cnt[ww][threadIdx.x];
+      s_run[threadIdx.x] += add;
     }
-    __syncthreads();
+    __syncthreads();  // s_run complete and s_wave_cnt read before the next round clears it
+  }
+  // write out in digit order
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int lp = r * kThreads + threadIdx.x;
+    if (lp < count) {
+      const K key = s_key[lp];
+      const uint32_t d = static_cast<uint32_t>(key >> shift) & mask;
+      const uint32_t gp = s_glob[d] + (static_cast<uint32_t>(lp) - s_start[d]);
+      kout[gp] = key;
+      vout[gp] = s_val[lp];
+    }
   }
 }
 
