@@ -55,10 +55,13 @@ def tile_reached(mx, my, A, B, C, tau, tx, ty, T, W, H):
         return ((A * dx) * dx + (B2 * dx) * dy) + (C * dy) * dy
 
     with np.errstate(all="ignore"):
-        ya = np.minimum(np.maximum(-((B * dx0) / C), dy0), dy1)
-        yb = np.minimum(np.maximum(-((B * dx1) / C), dy0), dy1)
-        xa = np.minimum(np.maximum(-((B * dy0) / A), dx0), dx1)
-        xb = np.minimum(np.maximum(-((B * dy1) / A), dx0), dx1)
+        # Stationary points of q on the four edges: dy = -(B/C) dx on a vertical edge, dx = -(B/A) dy
+        # on a horizontal one, with the two ratios rounded once per Gaussian.
+        nBC, nBA = -(B / C), -(B / A)
+        ya = np.minimum(np.maximum(dx0 * nBC, dy0), dy1)
+        yb = np.minimum(np.maximum(dx1 * nBC, dy0), dy1)
+        xa = np.minimum(np.maximum(dy0 * nBA, dx0), dx1)
+        xb = np.minimum(np.maximum(dy1 * nBA, dx0), dx1)
         qm = np.minimum(np.minimum(q(dx0, ya), q(dx1, yb)), np.minimum(q(xa, dy0), q(xb, dy1)))
     return inside | (qm <= tau)
 

@@ -65,9 +65,10 @@ __device__ __forceinline__ float quad_form(float A, float B2, float C, float dx,
 // True when the footprint {q <= tau} can reach a pixel centre of the tile (tx, ty): the minimum of
 // q over the rectangle spanned by the tile's pixel centres (clipped to the image) is <= tau.  The
 // minimum is 0 with the centre inside; otherwise it lies on one of the four edges, where q is a
-// 1D quadratic minimised at a clamped stationary point.
-__device__ __forceinline__ bool tile_reached(float mx, float my, float A, float B, float C, float tau, int tx,
-                                             int ty, int tile, int W, int H) {
+// 1D quadratic minimised at a clamped stationary point: dy = dx nBC on a vertical edge and
+// dx = dy nBA on a horizontal one, with nBC = -(B/C) and nBA = -(B/A) rounded once per Gaussian.
+__device__ __forceinline__ bool tile_reached(float mx, float my, float A, float B, float C, float nBA, float nBC,
+                                             float tau, int tx, int ty, int tile, int W, int H) {
   const float X0 = static_cast<float>(tx * tile) + 0.5f;
   const float X1 = static_cast<float>(min((tx + 1) * tile, W)) - 0.5f;
   const float Y0 = static_cast<float>(ty * tile) + 0.5f;
@@ -75,10 +76,10 @@ __device__ __forceinline__ bool tile_reached(float mx, float my, float A, float 
   const float dx0 = X0 - mx, dx1 = X1 - mx, dy0 = Y0 - my, dy1 = Y1 - my;
   if (dx0 <= 0.0f && dx1 >= 0.0f && dy0 <= 0.0f && dy1 >= 0.0f) return true;
   const float B2 = 2.0f * B;
-  const float ya = fminf(fmaxf(-__fdiv_rn(B * dx0, C), dy0), dy1);
-  const float yb = fminf(fmaxf(-__fdiv_rn(B * dx1, C), dy0), dy1);
-  const float xa = fminf(fmaxf(-__fdiv_rn(B * dy0, A), dx0), dx1);
-  const float xb = fminf(fmaxf(-__fdiv_rn(B * dy1, A), dx0), dx1);
+  const float ya = fminf(fmaxf(dx0 * nBC, dy0), dy1);
+  const float yb = fminf(fmaxf(dx1 * nBC, dy0), dy1);
+  const float xa = fminf(fmaxf(dy0 * nBA, dx0), dx1);
+  const float xb = fminf(fmaxf(dy1 * nBA, dx0), dx1);
   const float q = fminf(fminf(quad_form(A, B2, C, dx0, ya), quad_form(A, B2, C, dx1, yb)),
                         fminf(quad_form(A, B2, C, xa, dy0), quad_form(A, B2, C, xb, dy1)));
   return q <= tau;
@@ -178,11 +179,12 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
   uint32_t nt = 0, mask = 0;
   if (p.visible) {
     const float tau = footprint_tau(op);
+    const float nBA = -__fdiv_rn(p.cb, p.ca), nBC = -__fdiv_rn(p.cb, p.cc);
     uint32_t bit = 0;
     for (uint32_t ty = p.y0; ty < p.y1; ++ty)
       for (uint32_t tx = p.x0; tx < p.x1; ++tx, ++bit) {
-        const bool hit = tile_reached(p.px, p.py, p.ca, p.cb, p.cc, tau, static_cast<int>(tx), static_cast<int>(ty),
-                                      tile, v.width, v.height);
+        const bool hit = tile_reached(p.px, p.py, p.ca, p.cb, p.cc, nBA, nBC, tau, static_cast<int>(tx),
+                                      static_cast<int>(ty), tile, v.width, v.height);
         nt += hit ? 1u : 0u;
         mask |= (hit && bit < 32) ? (1u << bit) : 0u;
       }
@@ -248,17 +250,22 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
     bool over = false;
     const uint32_t w = x1 - x0;
     if (w * (y1 - y0) <= 32) {
-      // Small rectangle: the projection's mask lists the reached tiles in row-major order.
-      for (uint32_t m = reach_mask[item]; m; m &= m - 1) {
-        const uint32_t b = static_cast<uint32_t>(__builtin_ctz(m));
-        const uint32_t tx = x0 + b % w, ty = y0 + b / w;
-        if (o < capacity) {
-          pair_tile[o] = static_cast<uint32_t>(v.tile_offset) + ty * static_cast<uint32_t>(v.tiles_x) + tx;
-          pair_item[o] = item;
-        } else {
-          over = true;
+      // Small rectangle: the projection's mask lists the reached tiles in row-major order; it is
+      // walked row by row (w bits per row), which needs no integer division.
+      uint32_t m = reach_mask[item];
+      const uint32_t row_mask = w >= 32 ? 0xFFFFFFFFu : (1u << w) - 1u;
+      uint32_t t_row = static_cast<uint32_t>(v.tile_offset) + y0 * static_cast<uint32_t>(v.tiles_x) + x0;
+      for (; m; m >>= w, t_row += static_cast<uint32_t>(v.tiles_x)) {
+        for (uint32_t r = m & row_mask; r; r &= r - 1) {
+          if (o < capacity) {
+            pair_tile[o] = t_row + static_cast<uint32_t>(__builtin_ctz(r));
+            pair_item[o] = item;
+          } else {
+            over = true;
+          }
+          ++o;
         }
-        ++o;
+        if (w >= 32) break;
       }
       if (over) counters[2] = 1u;
       continue;
@@ -266,10 +273,11 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
     const float4 ra = rec[2 * static_cast<int64_t>(item)];
     const float4 rb = rec[2 * static_cast<int64_t>(item) + 1];
     const float tau = footprint_tau(rb.y);
+    const float nBA = -__fdiv_rn(ra.w, ra.z), nBC = -__fdiv_rn(ra.w, rb.x);
     for (uint32_t ty = y0; ty < y1; ++ty)
       for (uint32_t tx = x0; tx < x1; ++tx) {
-        if (!tile_reached(ra.x, ra.y, ra.z, ra.w, rb.x, tau, static_cast<int>(tx), static_cast<int>(ty), tile, v.width,
-                          v.height))
+        if (!tile_reached(ra.x, ra.y, ra.z, ra.w, rb.x, nBA, nBC, tau, static_cast<int>(tx), static_cast<int>(ty), tile,
+                          v.width, v.height))
           continue;
         if (o < capacity) {
           pair_tile[o] = static_cast<uint32_t>(v.tile_offset) + ty * static_cast<uint32_t>(v.tiles_x) + tx;
