@@ -56,7 +56,7 @@ struct DevView {
   int32_t tile_offset;   // first global tile of this view
   int32_t pixel_offset;  // first pixel of this view
   int32_t scene;
-  int32_t pad[2];
+  float lim_x, lim_y;    // FOV clamp of the projection Jacobian: 1.3 (0.5 W / fx), 1.3 (0.5 H / fy) in float32
 };
 static_assert(sizeof(DevView) % 16 == 0, "DevView must stay 16-byte aligned");
 

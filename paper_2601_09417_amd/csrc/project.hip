@@ -102,8 +102,7 @@ __device__ __forceinline__ ProjResult project_one(const DevView& v, int tile, fl
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int k = 0; k < 3; ++k) M[i][k] = Rq[i][k] * s[k];
-  const float limx = 1.3f * __fdiv_rn(0.5f * static_cast<float>(v.width), v.fx);
-  const float limy = 1.3f * __fdiv_rn(0.5f * static_cast<float>(v.height), v.fy);
+  const float limx = v.lim_x, limy = v.lim_y;
   const float txz = __fdiv_rn(Xc, Zc);
   const float tyz = __fdiv_rn(Yc, Zc);
   const float Xt = fminf(limx, fmaxf(-limx, txz)) * Zc;
@@ -136,11 +135,12 @@ __device__ __forceinline__ ProjResult project_one(const DevView& v, int tile, fl
   const float r = ceilf(3.0f * __fsqrt_rn(lam));
   const float px = v.fx * txz + v.cx;
   const float py = v.fy * tyz + v.cy;
-  const float Tf = static_cast<float>(tile);
-  const float fx0 = fminf(fmaxf(floorf(__fdiv_rn(px - r, Tf)), 0.0f), static_cast<float>(v.tiles_x));
-  const float fx1 = fminf(fmaxf(floorf(__fdiv_rn(px + r, Tf)) + 1.0f, 0.0f), static_cast<float>(v.tiles_x));
-  const float fy0 = fminf(fmaxf(floorf(__fdiv_rn(py - r, Tf)), 0.0f), static_cast<float>(v.tiles_y));
-  const float fy1 = fminf(fmaxf(floorf(__fdiv_rn(py + r, Tf)) + 1.0f, 0.0f), static_cast<float>(v.tiles_y));
+  // the tile edge is a power of two, so multiplying by its reciprocal is the exact quotient
+  const float iT = 1.0f / static_cast<float>(tile);
+  const float fx0 = fminf(fmaxf(floorf((px - r) * iT), 0.0f), static_cast<float>(v.tiles_x));
+  const float fx1 = fminf(fmaxf(floorf((px + r) * iT) + 1.0f, 0.0f), static_cast<float>(v.tiles_x));
+  const float fy0 = fminf(fmaxf(floorf((py - r) * iT), 0.0f), static_cast<float>(v.tiles_y));
+  const float fy1 = fminf(fmaxf(floorf((py + r) * iT) + 1.0f, 0.0f), static_cast<float>(v.tiles_y));
   vis = vis && isfinite(px) && isfinite(py) && isfinite(r) && opacity >= 1.0f / 255.0f;
   o.x0 = vis ? static_cast<uint32_t>(fx0) : 0u;
   o.x1 = vis ? static_cast<uint32_t>(fx1) : 0u;
@@ -323,8 +323,7 @@ __device__ __forceinline__ void project_bwd_one(const DevView& v, const float m[
   const float Y = ((R[3] * m[0] + R[4] * m[1]) + R[5] * m[2]) + v.t[1];
   const float Z = ((R[6] * m[0] + R[7] * m[1]) + R[8] * m[2]) + v.t[2];
   const float fx = v.fx, fy = v.fy;
-  const float limx = 1.3f * (0.5f * static_cast<float>(v.width) / fx);
-  const float limy = 1.3f * (0.5f * static_cast<float>(v.height) / fy);
+  const float limx = v.lim_x, limy = v.lim_y;
   const float txz = X / Z, tyz = Y / Z;
   const bool clx = txz < -limx || txz > limx;
   const bool cly = tyz < -limy || tyz > limy;

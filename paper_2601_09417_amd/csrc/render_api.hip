@@ -245,6 +245,9 @@ extern "C" vbm_status vbm_plan_make(const vbm_view* views, int32_t n_views, cons
     for (int c = 0; c < 3; ++c) d.bg[c] = in.bg[c];
     d.width = in.width;
     d.height = in.height;
+    // same float32 operations as the projection's specification
+    d.lim_x = 1.3f * ((0.5f * static_cast<float>(in.width)) / in.fx);
+    d.lim_y = 1.3f * ((0.5f * static_cast<float>(in.height)) / in.fy);
     d.tiles_x = static_cast<int32_t>(ceil_div(in.width, sch->tile));
     d.tiles_y = static_cast<int32_t>(ceil_div(in.height, sch->tile));
     const int64_t ng = scene_offsets[in.scene + 1] - scene_offsets[in.scene];
