@@ -181,6 +181,8 @@ __device__ __forceinline__ void add_stats(unsigned long long* stats, uint32_t n_
 // then overflows to -inf, alpha underflows to 0 and it never contributes again, so the step needs
 // no separate liveness test.
 constexpr float kDeadRow = 1e30f;
+// log2(1/255) - 0.001: below it 2^e2 < 1/255 with a margin far above the exponential's error.
+constexpr float kE2Skip = -7.9953534f;
 constexpr float kLiveBound = 1e29f;
 
 template <int PPL>
@@ -204,7 +206,14 @@ __device__ __forceinline__ void fwd_step(const Rec& r, int pos, float fx, float 
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     const float dy = r.my - fy[k];
-    const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(exponent2(r, u, vb, dy)));
+    const float e2 = exponent2(r, u, vb, dy);
+    // A lane group where every pixel has 2^e2 clearly below 1/255 (or is terminated, e2 = -inf)
+    // takes nothing from this Gaussian: skip the exponential and the update with one uniform branch.
+    if (!__any(e2 >= kE2Skip)) {
+      if (STATS) n_eval += fy[k] < kLiveBound ? 1u : 0u;
+      continue;
+    }
+    const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e2));
     const bool ok = alpha >= kAlphaMin;
     const float w = alpha * T[k];
     const float Tn = T[k] - w;
