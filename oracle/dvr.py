@@ -69,7 +69,8 @@ def render(vol: np.ndarray, xs, rgba, cam, step_vox: float = 0.5, t_min: float =
     H, W = d.shape[0], d.shape[1]
     C = np.zeros((H, W, 3))
     T = np.ones((H, W))
-    nsteps = np.where(hit, np.floor((tf - tn) / dt).astype(np.int64) + 1, 0)
+    span = np.where(hit, tf - tn, 0.0)          # rays that miss the cube have non-finite spans
+    nsteps = np.where(hit, np.floor(span / dt).astype(np.int64) + 1, 0)
     for k in range(int(nsteps.max()) if nsteps.size else 0):
         act = (k < nsteps) & (T >= t_min)
         if not act.any():
