@@ -115,25 +115,38 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
     }
   }
   __syncthreads();
-  const int col = threadIdx.x % TX;
-  for (int r = threadIdx.x / TX; r < EY; r += 256 / TX) {
-    float a = 0, b = 0, aa = 0, bb = 0, ab = 0;
+  // Horizontal pass: a task filters four adjacent columns of one halo row, so each of the 14 input
+  // values it reads forms its three products once for all four outputs.
+  constexpr int CPT = 4;                          // columns per task
+  for (int task = threadIdx.x; task < EY * (TX / CPT); task += 256) {
+    const int r = task / (TX / CPT), c0 = (task % (TX / CPT)) * CPT;
+    float acc[5][CPT];
 #pragma unroll
-    for (int k = 0; k < 2 * RAD + 1; ++k) {
-      const float u = sx[r][col + k], v = sy[r][col + k], wk = win.w[k];
-      a = fmaf(wk, u, a);
-      b = fmaf(wk, v, b);
-      aa = fmaf(wk * u, u, aa);
-      bb = fmaf(wk * v, v, bb);
-      ab = fmaf(wk * u, v, ab);
+    for (int f = 0; f < 5; ++f)
+#pragma unroll
+      for (int o = 0; o < CPT; ++o) acc[f][o] = 0.0f;
+#pragma unroll
+    for (int t = 0; t < CPT + 2 * RAD; ++t) {
+      const float u = sx[r][c0 + t], v = sy[r][c0 + t];
+      const float uu = u * u, vv = v * v, uv = u * v;
+#pragma unroll
+      for (int o = 0; o < CPT; ++o) {
+        if (t - o < 0 || t - o > 2 * RAD) continue;
+        const float wk = win.w[t - o];
+        acc[0][o] = fmaf(wk, u, acc[0][o]);
+        acc[1][o] = fmaf(wk, v, acc[1][o]);
+        acc[2][o] = fmaf(wk, uu, acc[2][o]);
+        acc[3][o] = fmaf(wk, vv, acc[3][o]);
+        acc[4][o] = fmaf(wk, uv, acc[4][o]);
+      }
     }
-    hb[0][r][col] = a;
-    hb[1][r][col] = b;
-    hb[2][r][col] = aa;
-    hb[3][r][col] = bb;
-    hb[4][r][col] = ab;
+#pragma unroll
+    for (int f = 0; f < 5; ++f)
+#pragma unroll
+      for (int o = 0; o < CPT; ++o) hb[f][r][c0 + o] = acc[f][o];
   }
   __syncthreads();
+  const int col = threadIdx.x % TX;
   const int r0 = (threadIdx.x / TX) * RPT;
   const int gx = blockIdx.x * TX + col;
   float m[RPT][5];
@@ -160,11 +173,14 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
       const float vx = m[o][2] - mx * mx, vy = m[o][3] - my * my, cxy = m[o][4] - mx * my;
       const float A1 = 2.0f * mx * my + kC1, A2 = 2.0f * cxy + kC2;
       const float B1 = mx * mx + my * my + kC1, B2 = vx + vy + kC2;
-      const float sv = (A1 * A2) / (B1 * B2);
+      // four hardware reciprocals (about 1 ulp) instead of six divisions
+      const float iA1 = __builtin_amdgcn_rcpf(A1), iA2 = __builtin_amdgcn_rcpf(A2);
+      const float iB1 = __builtin_amdgcn_rcpf(B1), iB2 = __builtin_amdgcn_rcpf(B2);
+      const float sv = (A1 * A2) * (iB1 * iB2);
       const int64_t pix = c * HW + static_cast<int64_t>(gy) * W + gx;
-      p1[pix] = sv * (2.0f * my / A1 - 2.0f * my / A2 - 2.0f * mx / B1 + 2.0f * mx / B2);
-      p2[pix] = -sv / B2;
-      p3[pix] = 2.0f * sv / A2;
+      p1[pix] = 2.0f * sv * (my * (iA1 - iA2) + mx * (iB2 - iB1));
+      p2[pix] = -sv * iB2;
+      p3[pix] = 2.0f * sv * iA2;
       sval += sv;
       l1 += fabsf(sx[r0 + o + RAD][col + RAD] - sy[r0 + o + RAD][col + RAD]);
     }
