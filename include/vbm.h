@@ -209,7 +209,10 @@ typedef struct {
 #define VBM_REGION_ITEM_REC 4    /* float32 [n_items][8]: mean2d.xy, conic.abc, opacity, r, g */
 #define VBM_REGION_ITEM_BLUE 5   /* float32 [n_items]: blue */
 #define VBM_REGION_PAIR_TILE 6   /* uint32 [pair_capacity]: sorted global tile of each pair */
-#define VBM_REGION_PAIR_ITEM 7   /* uint32 [pair_capacity]: sorted item of each pair */
+#define VBM_REGION_PAIR_ITEM 7   /* uint32 [pair_capacity]: sorted item of each pair in bits 0..26;
+                                  * with 8x8 and 16x16 tiles vbm_render_fwd sets bit 27 + k of a pair
+                                  * it visited when lane group k (pixel rows k*64/tile of the tile)
+                                  * was evaluated, and vbm_render_bwd reads those marks */
 #define VBM_REGION_RANGES 8      /* uint32 [n_tiles][2]: [start, end) of each tile's list */
 #define VBM_REGION_GRAD2D 9      /* float32 [n_items][16]: dmean2d.xy, dconic.abc, dopacity, drgb in
                                   * columns 0..8 after vbm_render_bwd (rows of items never binned

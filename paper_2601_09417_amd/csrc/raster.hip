@@ -34,6 +34,10 @@ namespace vbm {
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
+// Item ids stay below 2^27 (the plan enforces it); the forward keeps per-pair lane-group marks in
+// the bits above.
+constexpr int kItemBits = 27;
+constexpr uint32_t kItemMask = (1u << kItemBits) - 1u;
 
 template <int TILE>
 struct TileCfg {
@@ -87,7 +91,17 @@ __device__ __forceinline__ uint32_t load_item(const ListSrc& s, int j) {
   return static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b32(s.items, 0, 4 * j, 0));
 }
 
-__device__ __forceinline__ Rec load_rec(const ListSrc& s, uint32_t it) {
+// Rewrites the n <= 3 pair values j, j + 1, j + 2 (uniform v0, v1, v2) with one vector store from
+// lanes 0 .. n - 1.
+__device__ __forceinline__ void store_pair_values(const ListSrc& s, int lane, int j, int n, uint32_t v0, uint32_t v1,
+                                                  uint32_t v2) {
+  const uint32_t v = lane == 0 ? v0 : lane == 1 ? v1 : v2;
+  if (lane < n) __builtin_amdgcn_raw_buffer_store_b32(v, s.items, 4 * lane, 4 * j, 0);
+}
+
+// The record of a pair value (the item id in its low kItemBits bits).
+__device__ __forceinline__ Rec load_rec(const ListSrc& s, uint32_t pv) {
+  const uint32_t it = pv & kItemMask;
   const int off = static_cast<int>(32u * it);
   const v4i a = __builtin_amdgcn_raw_buffer_load_b128(s.coef, 0, off, 0);
   const v4i b = __builtin_amdgcn_raw_buffer_load_b128(s.coef, 16, off, 0);
@@ -105,6 +119,9 @@ __device__ __forceinline__ Rec load_rec(const ListSrc& s, uint32_t it) {
 }
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// True when the predicate holds on some active lane: one scalar test of the predicate's lane mask.
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
 
 // Base-2 exponent of the Gaussian at a pixel whose per-lane terms u = hA dx^2 + log2(o) and
 // v = hB dx are precomputed; one expression shared by the forward and the backward so that both
@@ -190,16 +207,18 @@ __device__ __forceinline__ bool any_live(const float (&fy)[PPL]) {
   float m = fy[0];
 #pragma unroll
   for (int k = 1; k < PPL; ++k) m = fminf(m, fy[k]);
-  return __any(m < kLiveBound);
+  return wave_any(m < kLiveBound);
 }
 
 // One list step of the forward for the lane's pixels: alpha = min(0.99, 2^e2); a pixel takes the
 // Gaussian when alpha >= 1/255, unless the new transmittance would fall below 1e-4, in which case
-// the pixel stops without it.
+// the pixel stops without it.  Returns the mask of lane groups k that were evaluated: every group
+// with a pixel that took the Gaussian is among them.
 template <int PPL, bool STATS>
-__device__ __forceinline__ void fwd_step(const Rec& r, int pos, float fx, float (&fy)[PPL], float (&T)[PPL],
-                                         float (&cr)[PPL], float (&cg)[PPL], float (&cb)[PPL], int (&last)[PPL],
-                                         uint32_t& n_eval, uint32_t& n_used) {
+__device__ __forceinline__ uint32_t fwd_step(const Rec& r, int pos, float fx, float (&fy)[PPL], float (&T)[PPL],
+                                             float (&cr)[PPL], float (&cg)[PPL], float (&cb)[PPL], int (&last)[PPL],
+                                             uint32_t& n_eval, uint32_t& n_used) {
+  uint32_t groups = 0;
   const float dx = r.mx - fx;
   const float u = fmaf(r.hA, dx * dx, r.lo);
   const float vb = r.hB * dx;
@@ -209,10 +228,11 @@ __device__ __forceinline__ void fwd_step(const Rec& r, int pos, float fx, float 
     const float e2 = exponent2(r, u, vb, dy);
     // A lane group where every pixel has 2^e2 clearly below 1/255 (or is terminated, e2 = -inf)
     // takes nothing from this Gaussian: skip the exponential and the update with one uniform branch.
-    if (!__any(e2 >= kE2Skip)) {
+    if (!wave_any(e2 >= kE2Skip)) {
       if (STATS) n_eval += fy[k] < kLiveBound ? 1u : 0u;
       continue;
     }
+    groups |= 1u << k;
     const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e2));
     const bool ok = alpha >= kAlphaMin;
     const float w = alpha * T[k];
@@ -231,12 +251,13 @@ __device__ __forceinline__ void fwd_step(const Rec& r, int pos, float fx, float 
     fy[k] = stop ? kDeadRow : fy[k];
     last[k] = use ? pos : last[k];
   }
+  return groups;
 }
 
 template <int TILE, bool STATS>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
     const DevView* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
-    const uint32_t* __restrict__ pair_item, int64_t n_pairs, const float* __restrict__ coef,
+    uint32_t* __restrict__ pair_item, int64_t n_pairs, const float* __restrict__ coef,
     const float* __restrict__ blue, int64_t n_items, float* __restrict__ image, float* __restrict__ final_T,
     int32_t* __restrict__ n_contrib, unsigned long long* __restrict__ stats) {
   using C = TileCfg<TILE>;
@@ -273,23 +294,35 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
   // a clamped duplicate whose log-opacity is set to -inf, so alpha = 0 and it changes nothing.
   const ListSrc src = make_list_src(pair_item, n_pairs, coef, blue, n_items);
   const int lastj = end > start ? end - 1 : start;
-  Rec R0 = load_rec(src, uniform(load_item(src, start)));
-  Rec R1 = load_rec(src, uniform(load_item(src, min(start + 1, lastj))));
+  // With one wave per tile, each processed pair value is written back with the mask of the lane
+  // groups that the step evaluated in bits kItemBits.. (see fwd_step): the backward visits only
+  // those groups.
+  constexpr bool kMark = C::kWaves == 1;
+  uint32_t u0 = uniform(load_item(src, start)), u1 = uniform(load_item(src, min(start + 1, lastj))), u2;
+  Rec R0 = load_rec(src, u0);
+  Rec R1 = load_rec(src, u1);
   Rec R2;
   uint32_t L1, L2 = load_item(src, min(start + 2, lastj)), L0 = load_item(src, min(start + 3, lastj));
   for (int j = start; j < end; j += 3) {
     if (!any_live(fy)) break;
-    R2 = load_rec(src, uniform(L2));
+    u2 = uniform(L2);
+    R2 = load_rec(src, u2);
     L1 = load_item(src, min(j + 4, lastj));
-    fwd_step<PPL, STATS>(R0, j - start + 1, fx, fy, T, cr, cg, cb, last, n_eval, n_used);
+    const uint32_t m0 = (u0 & kItemMask) | (fwd_step<PPL, STATS>(R0, j - start + 1, fx, fy, T, cr, cg, cb, last,
+                                                                  n_eval, n_used) << kItemBits);
     R1.lo = j + 1 < end ? R1.lo : -__builtin_inff();
-    R0 = load_rec(src, uniform(L0));
+    u0 = uniform(L0);
+    R0 = load_rec(src, u0);
     L2 = load_item(src, min(j + 5, lastj));
-    fwd_step<PPL, STATS>(R1, j - start + 2, fx, fy, T, cr, cg, cb, last, n_eval, n_used);
+    const uint32_t m1 = (u1 & kItemMask) | (fwd_step<PPL, STATS>(R1, j - start + 2, fx, fy, T, cr, cg, cb, last,
+                                                                  n_eval, n_used) << kItemBits);
     R2.lo = j + 2 < end ? R2.lo : -__builtin_inff();
-    R1 = load_rec(src, uniform(L1));
+    u1 = uniform(L1);
+    R1 = load_rec(src, u1);
     L0 = load_item(src, min(j + 6, lastj));
-    fwd_step<PPL, STATS>(R2, j - start + 3, fx, fy, T, cr, cg, cb, last, n_eval, n_used);
+    const uint32_t m2 = (u2 & kItemMask) | (fwd_step<PPL, STATS>(R2, j - start + 3, fx, fy, T, cr, cg, cb, last,
+                                                                  n_eval, n_used) << kItemBits);
+    if (kMark) store_pair_values(src, lane, j, min(end - j, 3), m0, m1, m2);
   }
   if (STATS) add_stats(stats, n_eval, n_used);
   const int64_t HW = static_cast<int64_t>(v.width) * v.height;
@@ -318,58 +351,58 @@ struct BwdPix {
 // Gaussian is T / (1 - alpha), dL/dalpha = T_before * sum_c dL/dC_c (c_c - acc_c) with acc the
 // normalised colour behind the Gaussian (the background at first), which then becomes
 // alpha c + (1 - alpha) acc.  dL/dpower = alpha dL/dalpha unless alpha was clamped.
-template <int PPL, bool STATS>
-__device__ __forceinline__ void bwd_step(const Rec& r, uint32_t it, int j, float fx, BwdPix<PPL>& P, int lane,
+template <int PPL, bool MARKED, bool STATS>
+__device__ __forceinline__ void bwd_step(const Rec& r, uint32_t pv, int j, float fx, BwdPix<PPL>& P, int lane,
                                          int out_k, bool out_lane, float* __restrict__ grad2d, uint32_t& n_eval,
                                          uint32_t& n_used) {
+  if (STATS)
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) n_eval += j < P.nc[k] ? 1u : 0u;
+  // MARKED: the forward left in the pair value the lane groups it evaluated, a superset of those
+  // with a contributing pixel; each is handled wholly inside its own uniform branch.
+  const uint32_t groups = MARKED ? pv >> kItemBits : (1u << PPL) - 1u;
+  if (groups == 0) return;
   const float dx = r.mx - fx;
   const float dx2 = dx * dx;
   const float u = fmaf(r.hA, dx2, r.lo);
   const float vb = r.hB * dx;
-  float G2[PPL], alpha[PPL];
-  bool c[PPL];
-  bool anyc = false;
-#pragma unroll
-  for (int k = 0; k < PPL; ++k) {
-    const float dy = r.my - P.fy[k];
-    G2[k] = __builtin_amdgcn_exp2f(exponent2(r, u, vb, dy));
-    alpha[k] = fminf(kAlphaMax, G2[k]);
-    c[k] = j < P.nc[k] && alpha[k] >= kAlphaMin;
-    anyc |= c[k];
-    if (STATS) {
-      n_eval += j < P.nc[k] ? 1u : 0u;
-      n_used += c[k] ? 1u : 0u;
-    }
-  }
-  if (!__any(anyc)) return;
   // Per-lane sums: s0 = sum dp, s1 = sum dp dy, s2 = sum dp dy^2 (dp = dL/dpower), and the colour
   // weights alpha T_before dL/dC.
   float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, wr = 0.0f, wg = 0.0f, wb = 0.0f;
+  bool anyc = false;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
-    if (c[k]) {
-      const float Tk = P.T[k] * __builtin_amdgcn_rcpf(1.0f - alpha[k]);
+    if (!((groups >> k) & 1u)) continue;
+    const float dy = r.my - P.fy[k];
+    const float G2 = __builtin_amdgcn_exp2f(exponent2(r, u, vb, dy));
+    const float alpha = fminf(kAlphaMax, G2);
+    const bool c = j < P.nc[k] && alpha >= kAlphaMin;
+    if (STATS) n_used += c ? 1u : 0u;
+    anyc |= c;
+    if (c) {
+      const float Tk = P.T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
       P.T[k] = Tk;
       const float er = r.r - P.accr[k], eg = r.g - P.accg[k], eb = r.b - P.accb[k];
       const float dLda = Tk * fmaf(P.dr[k], er, fmaf(P.dg[k], eg, P.db[k] * eb));
-      P.accr[k] = fmaf(alpha[k], er, P.accr[k]);
-      P.accg[k] = fmaf(alpha[k], eg, P.accg[k]);
-      P.accb[k] = fmaf(alpha[k], eb, P.accb[k]);
-      const float w = alpha[k] * Tk;
+      P.accr[k] = fmaf(alpha, er, P.accr[k]);
+      P.accg[k] = fmaf(alpha, eg, P.accg[k]);
+      P.accb[k] = fmaf(alpha, eb, P.accb[k]);
+      const float w = alpha * Tk;
       wr = fmaf(w, P.dr[k], wr);
       wg = fmaf(w, P.dg[k], wg);
       wb = fmaf(w, P.db[k], wb);
-      const float dp = G2[k] <= kAlphaMax ? dLda * alpha[k] : 0.0f;
-      const float dy = r.my - P.fy[k];
+      const float dp = G2 <= kAlphaMax ? dLda * alpha : 0.0f;
       const float t = dp * dy;
       s0 += dp;
       s1 += t;
       s2 = fmaf(t, dy, s2);
     }
   }
+  // (with marks the superset is tight enough that the test does not pay for itself)
+  if (!MARKED && !wave_any(anyc)) return;
   const float g[9] = {dx * s0, s1, dx2 * s0, dx * s1, s2, s0, wr, wg, wb};
   const float sum = reduce_scatter9(g, lane);
-  if (out_lane && sum != 0.0f) unsafeAtomicAdd(&grad2d[16 * static_cast<size_t>(it) + out_k], sum);
+  if (out_lane && sum != 0.0f) unsafeAtomicAdd(&grad2d[16 * static_cast<size_t>(pv & kItemMask) + out_k], sum);
 }
 
 template <int TILE, bool STATS>
@@ -428,6 +461,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
   // order, and the newest operation a step waits for was issued two steps earlier.  Positions
   // below 0 are clamped to 0 and their loads never used.
   const ListSrc src = make_list_src(pair_item, n_pairs, coef, blue, n_items);
+  constexpr bool kMarked = C::kWaves == 1;   // the forward marked each pair's evaluated groups
   const int top = max(maxn - 1, 0);
   uint32_t u0 = uniform(load_item(src, start + top));
   uint32_t u1 = uniform(load_item(src, start + max(top - 1, 0)));
@@ -440,24 +474,24 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
     u2 = uniform(L2);
     R2 = load_rec(src, u2);
     L1 = load_item(src, start + max(j - 4, 0));
-    bwd_step<PPL, STATS>(R0, u0, j, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
+    bwd_step<PPL, kMarked, STATS>(R0, u0, j, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
     if (j == 0) break;
     u0 = uniform(L0);
     R0 = load_rec(src, u0);
     L2 = load_item(src, start + max(j - 5, 0));
-    bwd_step<PPL, STATS>(R1, u1, j - 1, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
+    bwd_step<PPL, kMarked, STATS>(R1, u1, j - 1, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
     if (j == 1) break;
     u1 = uniform(L1);
     R1 = load_rec(src, u1);
     L0 = load_item(src, start + max(j - 6, 0));
-    bwd_step<PPL, STATS>(R2, u2, j - 2, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
+    bwd_step<PPL, kMarked, STATS>(R2, u2, j - 2, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
   }
   if (STATS) add_stats(stats, n_eval, n_used);
 }
 
 template <int TILE>
 static vbm_status launch_fwd_t(const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
-                               const uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
+                               uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
                                int64_t n_items, float* image, float* final_T, int32_t* n_contrib,
                                unsigned long long* stats, hipStream_t s) {
   const dim3 block(TileCfg<TILE>::kThreads);
@@ -489,7 +523,7 @@ static vbm_status launch_bwd_t(const DevView* views, int n_views, int64_t n_tile
 }
 
 vbm_status launch_composite_fwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
-                                const uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
+                                uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
                                 int64_t n_items, float* image, float* final_T, int32_t* n_contrib,
                                 unsigned long long* stats, hipStream_t s) {
   switch (tile) {

@@ -31,7 +31,7 @@ __global__ void k_status(const uint32_t*, int32_t*);
 __global__ void k_project_bwd(const DevView*, int, const DevScene*, int, vbm_gaussians_c, float*, const float4*,
                               int64_t, const uint32_t*, vbm_gaussians, int, int64_t);
 vbm_status launch_composite_fwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
-                                const uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
+                                uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
                                 int64_t n_items, float* image, float* final_T, int32_t* n_contrib,
                                 unsigned long long* stats, hipStream_t s);
 vbm_status launch_composite_bwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,

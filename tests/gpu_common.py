@@ -10,6 +10,7 @@ import vbm_inputs as vi
 
 IMG_TOL = 1e-5      # images: max |gpu - oracle| / max |oracle| over unflagged pixels
 GRAD_TOL = 1e-4     # gradients: per parameter group, max |gpu - oracle| / max |oracle|
+ITEM_MASK = (1 << 27) - 1   # pair values: item id below bit 27, forward lane-group marks above
 ROWS = dict(means=slice(0, 3), scales=slice(3, 6), quats=slice(6, 10), opacity=slice(10, 11), rgb=slice(11, 14))
 
 

@@ -24,7 +24,7 @@ from oracle import dwt as odwt
 from oracle import select as oselect
 from oracle import tf as otf
 from oracle import wavelets
-from tests.gpu_common import GRAD_TOL, IMG_TOL, ROWS, dev, group_error, say
+from tests.gpu_common import GRAD_TOL, IMG_TOL, ITEM_MASK, ROWS, dev, group_error, say
 
 pytestmark = pytest.mark.gpu
 
@@ -112,7 +112,7 @@ def test_fullsize_render_sampled_tiles(h_case):
     gs = _gaussian_set(P)
     toff = binning.tile_grid(cams, TILE)
     ptile = rp.region("pair_tile", torch.int32).cpu().numpy()
-    pitem = rp.region("pair_item", torch.int32).cpu().numpy()
+    pitem = rp.region("pair_item", torch.int32).cpu().numpy() & ITEM_MASK        # marks above bit 26
     ranges = rp.region("ranges", torch.int32).cpu().numpy().reshape(-1, 2)
     imgs = [t.cpu().numpy() for t in api.split_views(out.image, cams)]
     rng = np.random.default_rng(33)

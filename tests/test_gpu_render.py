@@ -6,7 +6,7 @@ import torch
 
 import vbm_inputs as vi
 from oracle import binning, render
-from tests.gpu_common import (GRAD_TOL, IMG_TOL, ROWS, dev, flat, group_error, image_error, masked_dL, say,
+from tests.gpu_common import (GRAD_TOL, IMG_TOL, ITEM_MASK, ROWS, dev, flat, group_error, image_error, masked_dL, say,
                               to_dev)
 
 pytestmark = pytest.mark.gpu
@@ -51,7 +51,7 @@ def test_projection_and_pair_lists_bit_exact(tile):
         assert np.array_equal(rect[I:][sl][vis] & 0xFFFF, pr["y0"][vis])
         assert np.array_equal(rect[I:][sl][vis] >> 16, pr["y1"][vis])
     ptile = rp.region("pair_tile", torch.int32).cpu().numpy()[:P_ref]
-    pitem = rp.region("pair_item", torch.int32).cpu().numpy()[:P_ref]
+    pitem = rp.region("pair_item", torch.int32).cpu().numpy()[:P_ref] & ITEM_MASK   # marks above bit 26
     assert np.array_equal(ptile, ref["tile"])
     assert np.array_equal(pitem, ref["item"])
     ranges = rp.region("ranges", torch.int32).cpu().numpy().reshape(-1, 2)
