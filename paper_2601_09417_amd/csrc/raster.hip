@@ -181,6 +181,50 @@ __device__ __forceinline__ int rs_index(int lane) {
   return (lane & 1) ? 8 : ((lane >> 1) & 1) * 4 + ((lane >> 2) & 1) * 2 + ((lane >> 3) & 1);
 }
 
+// a + b over the wave's halves: lanes 0..31 get a[l] + a[l + 32], lanes 32..63 b[l - 32] + b[l].
+__device__ __forceinline__ float add_halves(float a, float b) {
+  const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(h[0]) + __uint_as_float(h[1]);
+}
+// The same over 16-lane row pairs: rows 0 and 2 get a's rows (0 + 1) and (2 + 3), rows 1 and 3 b's.
+__device__ __forceinline__ float add_row_pairs(float a, float b) {
+  const auto h = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(h[0]) + __uint_as_float(h[1]);
+}
+
+// Wave sums of the nine gradient terms {dx s0, s1, dx^2 s0, dx s1, s2, s0, wr, wg, wb} when lanes
+// l, l + 16, l + 32, l + 48 share a pixel column (so dx): the six per-lane sums are first added
+// over those lanes (row k of 16 lanes then holds s0, s1, wr, wg column sums in P and s2, s2, wb, wb
+// in Q), scaled by dx, dx^2, and the four values P, P dx, P dx^2, Q reduced inside each row.  The
+// sums land in the lanes that col_index names.
+__device__ __forceinline__ float reduce_cols9(float s0, float s1, float s2, float wr, float wg, float wb, float dx,
+                                              float dx2, int lane) {
+  const float P = add_row_pairs(add_halves(s0, wr), add_halves(s1, wg));
+  const float Z = add_halves(s2, wb);
+  const float Q = add_row_pairs(Z, Z);
+  const bool b3 = lane & 8, b2 = lane & 4;
+  const float V1 = rs_pair<kRowMirror>(P, P * dx, b3);       // lanes 0..7: P, 8..15: P dx
+  const float V2 = rs_pair<kRowMirror>(P * dx2, Q, b3);      // lanes 0..7: P dx^2, 8..15: Q
+  const float W = rs_pair<kRowHalfMirror>(V1, V2, b2);       // quads: P, P dx^2, P dx, Q
+  return rs_single<kQuadXor1>(rs_single<kQuadXor2>(W));
+}
+
+// Gradient column (0..8) whose sum reduce_cols9 leaves in the lane, or -1.
+__device__ __forceinline__ int col_index(int lane) {
+  switch (lane) {
+    case 0: return 5;    // s0
+    case 4: return 2;    // dx^2 s0
+    case 8: return 0;    // dx s0
+    case 12: return 4;   // s2
+    case 16: return 1;   // s1
+    case 24: return 3;   // dx s1
+    case 32: return 6;   // wr
+    case 44: return 8;   // wb
+    case 48: return 7;   // wg
+    default: return -1;
+  }
+}
+
 // Measurement aid: adds the wave's evaluated / contributing (pixel, Gaussian) counts to stats[0..1].
 __device__ __forceinline__ void add_stats(unsigned long long* stats, uint32_t n_eval, uint32_t n_used) {
   unsigned long long e = n_eval, u = n_used;
@@ -351,7 +395,7 @@ struct BwdPix {
 // Gaussian is T / (1 - alpha), dL/dalpha = T_before * sum_c dL/dC_c (c_c - acc_c) with acc the
 // normalised colour behind the Gaussian (the background at first), which then becomes
 // alpha c + (1 - alpha) acc.  dL/dpower = alpha dL/dalpha unless alpha was clamped.
-template <int PPL, bool MARKED, bool STATS>
+template <int PPL, bool MARKED, bool COLS, bool STATS>
 __device__ __forceinline__ void bwd_step(const Rec& r, uint32_t pv, int j, float fx, BwdPix<PPL>& P, int lane,
                                          int out_k, bool out_lane, float* __restrict__ grad2d, uint32_t& n_eval,
                                          uint32_t& n_used) {
@@ -400,8 +444,13 @@ __device__ __forceinline__ void bwd_step(const Rec& r, uint32_t pv, int j, float
   }
   // (with marks the superset is tight enough that the test does not pay for itself)
   if (!MARKED && !wave_any(anyc)) return;
-  const float g[9] = {dx * s0, s1, dx2 * s0, dx * s1, s2, s0, wr, wg, wb};
-  const float sum = reduce_scatter9(g, lane);
+  float sum;
+  if constexpr (COLS) {
+    sum = reduce_cols9(s0, s1, s2, wr, wg, wb, dx, dx2, lane);
+  } else {
+    const float g[9] = {dx * s0, s1, dx2 * s0, dx * s1, s2, s0, wr, wg, wb};
+    sum = reduce_scatter9(g, lane);
+  }
   if (out_lane && sum != 0.0f) unsafeAtomicAdd(&grad2d[16 * static_cast<size_t>(pv & kItemMask) + out_k], sum);
 }
 
@@ -452,8 +501,10 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
   for (int d = 32; d >= 1; d >>= 1) maxn = max(maxn, __shfl_xor(maxn, d, 64));
   maxn = __builtin_amdgcn_readfirstlane(maxn);
   const int start = static_cast<int>(ranges[tile].x);
-  const int out_k = rs_index(lane & 15);
-  const bool out_lane = lane < 16 && ((lane & 1) == 0 || lane == 1);
+  // Lanes l, l + 16, l + 32, l + 48 share a pixel column when the tile is at most 16 wide.
+  constexpr bool kCols = 16 % TILE == 0;
+  const int out_k = kCols ? col_index(lane) : rs_index(lane & 15);
+  const bool out_lane = kCols ? out_k >= 0 : lane < 16 && ((lane & 1) == 0 || lane == 1);
   uint32_t n_eval = 0, n_used = 0;
   // The forward's load pipeline, walking list positions maxn - 1 .. 0 (a step's record is
   // requested two steps ahead, its item id four).  The distance also keeps every wait clear of
@@ -474,17 +525,17 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
     u2 = uniform(L2);
     R2 = load_rec(src, u2);
     L1 = load_item(src, start + max(j - 4, 0));
-    bwd_step<PPL, kMarked, STATS>(R0, u0, j, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
+    bwd_step<PPL, kMarked, kCols, STATS>(R0, u0, j, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
     if (j == 0) break;
     u0 = uniform(L0);
     R0 = load_rec(src, u0);
     L2 = load_item(src, start + max(j - 5, 0));
-    bwd_step<PPL, kMarked, STATS>(R1, u1, j - 1, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
+    bwd_step<PPL, kMarked, kCols, STATS>(R1, u1, j - 1, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
     if (j == 1) break;
     u1 = uniform(L1);
     R1 = load_rec(src, u1);
     L0 = load_item(src, start + max(j - 6, 0));
-    bwd_step<PPL, kMarked, STATS>(R2, u2, j - 2, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
+    bwd_step<PPL, kMarked, kCols, STATS>(R2, u2, j - 2, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
   }
   if (STATS) add_stats(stats, n_eval, n_used);
 }
