@@ -386,7 +386,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
 // Per-wave gradient state of one list step of the backward (see bwd_step).
 template <int PPL>
 struct BwdPix {
-  float fy[PPL], T[PPL], dr[PPL], dg[PPL], db[PPL], accr[PPL], accg[PPL], accb[PPL];
+  float fy[PPL], T[PPL], dr[PPL], dg[PPL], db[PPL], S[PPL];
   int nc[PPL];
 };
 
@@ -394,7 +394,9 @@ struct BwdPix {
 // part when j < n_contrib and the forward's alpha test holds; its transmittance before the
 // Gaussian is T / (1 - alpha), dL/dalpha = T_before * sum_c dL/dC_c (c_c - acc_c) with acc the
 // normalised colour behind the Gaussian (the background at first), which then becomes
-// alpha c + (1 - alpha) acc.  dL/dpower = alpha dL/dalpha unless alpha was clamped.
+// alpha c + (1 - alpha) acc.  Only the projection S = sum_c dL/dC_c acc_c enters, so that scalar is
+// what the pixel carries: dL/dalpha = T_before (D_c - S) with D_c = sum_c dL/dC_c c_c, and S moves
+// to S + alpha (D_c - S).  dL/dpower = alpha dL/dalpha unless alpha was clamped.
 template <int PPL, bool MARKED, bool COLS, bool STATS>
 __device__ __forceinline__ void bwd_step(const Rec& r, uint32_t pv, int j, float fx, BwdPix<PPL>& P, int lane,
                                          int out_k, bool out_lane, float* __restrict__ grad2d, uint32_t& n_eval,
@@ -426,16 +428,13 @@ __device__ __forceinline__ void bwd_step(const Rec& r, uint32_t pv, int j, float
     if (c) {
       const float Tk = P.T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
       P.T[k] = Tk;
-      const float er = r.r - P.accr[k], eg = r.g - P.accg[k], eb = r.b - P.accb[k];
-      const float dLda = Tk * fmaf(P.dr[k], er, fmaf(P.dg[k], eg, P.db[k] * eb));
-      P.accr[k] = fmaf(alpha, er, P.accr[k]);
-      P.accg[k] = fmaf(alpha, eg, P.accg[k]);
-      P.accb[k] = fmaf(alpha, eb, P.accb[k]);
+      const float D = fmaf(P.dr[k], r.r, fmaf(P.dg[k], r.g, P.db[k] * r.b)) - P.S[k];
+      P.S[k] = fmaf(alpha, D, P.S[k]);
       const float w = alpha * Tk;
       wr = fmaf(w, P.dr[k], wr);
       wg = fmaf(w, P.dg[k], wg);
       wb = fmaf(w, P.db[k], wb);
-      const float dp = G2 <= kAlphaMax ? dLda * alpha : 0.0f;
+      const float dp = G2 <= kAlphaMax ? w * D : 0.0f;     // alpha dL/dalpha
       const float t = dp * dy;
       s0 += dp;
       s1 += t;
@@ -492,9 +491,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
       P.dg[k] = g[HW + pix];
       P.db[k] = g[2 * HW + pix];
     }
-    P.accr[k] = v.bg[0];
-    P.accg[k] = v.bg[1];
-    P.accb[k] = v.bg[2];
+    P.S[k] = fmaf(P.dr[k], v.bg[0], fmaf(P.dg[k], v.bg[1], P.db[k] * v.bg[2]));
     maxn = max(maxn, P.nc[k]);
   }
 #pragma unroll
