@@ -303,6 +303,17 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ pai
   }
 }
 
+// Sort keys that put the tiles with the longest lists first (one key step per 8 list entries,
+// lists of 2040 or more share the first key); the values are the tile indices.
+__global__ __launch_bounds__(256) void k_tile_keys(const uint2* __restrict__ ranges, int64_t n_tiles,
+                                                   uint32_t* __restrict__ keys, uint32_t* __restrict__ tiles) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (t >= n_tiles) return;
+  const uint2 r = ranges[t];
+  keys[t] = 255u - min(255u, (r.y - r.x) >> 3);
+  tiles[t] = static_cast<uint32_t>(t);
+}
+
 __global__ void k_status(const uint32_t* __restrict__ counters, int32_t* __restrict__ status) {
   if (threadIdx.x == 0) {
     status[0] = static_cast<int32_t>(counters[2]);

@@ -301,6 +301,7 @@ __device__ __forceinline__ uint32_t fwd_step(const Rec& r, int pos, float fx, fl
 template <int TILE, bool STATS>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
     const DevView* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ tile_order,
     uint32_t* __restrict__ pair_item, int64_t n_pairs, const float* __restrict__ coef,
     const float* __restrict__ blue, int64_t n_items, float* __restrict__ image, float* __restrict__ final_T,
     int32_t* __restrict__ n_contrib, unsigned long long* __restrict__ stats) {
@@ -308,7 +309,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
   constexpr int PPL = C::kPPL;
   const int lane = static_cast<int>(threadIdx.x) & 63;
   const int wave = static_cast<int>(threadIdx.x) >> 6;
-  const int tile = blockIdx.x;
+  const int tile = static_cast<int>(tile_order[blockIdx.x]);
   const DevView& v = views[find_view(views, n_views, tile)];
   const int local = tile - v.tile_offset;
   const int tx = local % v.tiles_x, ty = local / v.tiles_x;
@@ -456,6 +457,7 @@ __device__ __forceinline__ void bwd_step(const Rec& r, uint32_t pv, int j, float
 template <int TILE, bool STATS>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
     const DevView* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ tile_order,
     const uint32_t* __restrict__ pair_item, int64_t n_pairs, const float* __restrict__ coef,
     const float* __restrict__ blue, const float* __restrict__ final_T, const int32_t* __restrict__ n_contrib,
     const float* __restrict__ dL_dimg, float* __restrict__ grad2d, int64_t n_items,
@@ -464,7 +466,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
   constexpr int PPL = C::kPPL;
   const int lane = static_cast<int>(threadIdx.x) & 63;
   const int wave = static_cast<int>(threadIdx.x) >> 6;
-  const int tile = blockIdx.x;
+  const int tile = static_cast<int>(tile_order[blockIdx.x]);
   const DevView& v = views[find_view(views, n_views, tile)];
   const int local = tile - v.tile_offset;
   const int tx = local % v.tiles_x, ty = local / v.tiles_x;
@@ -538,60 +540,60 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
 }
 
 template <int TILE>
-static vbm_status launch_fwd_t(const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
+static vbm_status launch_fwd_t(const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges, const uint32_t* tile_order,
                                uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
                                int64_t n_items, float* image, float* final_T, int32_t* n_contrib,
                                unsigned long long* stats, hipStream_t s) {
   const dim3 block(TileCfg<TILE>::kThreads);
   if (stats)
-    hipLaunchKernelGGL((k_composite_fwd<TILE, true>), dim3(n_tiles), block, 0, s, views, n_views, ranges, pair_item,
+    hipLaunchKernelGGL((k_composite_fwd<TILE, true>), dim3(n_tiles), block, 0, s, views, n_views, ranges, tile_order, pair_item,
                        n_pairs, coef, blue, n_items, image, final_T, n_contrib, stats);
   else
-    hipLaunchKernelGGL((k_composite_fwd<TILE, false>), dim3(n_tiles), block, 0, s, views, n_views, ranges, pair_item,
+    hipLaunchKernelGGL((k_composite_fwd<TILE, false>), dim3(n_tiles), block, 0, s, views, n_views, ranges, tile_order, pair_item,
                        n_pairs, coef, blue, n_items, image, final_T, n_contrib, stats);
   VBM_LAUNCH_CHECK("composite_fwd");
   return VBM_OK;
 }
 
 template <int TILE>
-static vbm_status launch_bwd_t(const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
+static vbm_status launch_bwd_t(const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges, const uint32_t* tile_order,
                                const uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
                                const float* final_T,
                                const int32_t* n_contrib, const float* dL_dimg, float* grad2d, int64_t n_items,
                                unsigned long long* stats, hipStream_t s) {
   const dim3 block(TileCfg<TILE>::kThreads);
   if (stats)
-    hipLaunchKernelGGL((k_composite_bwd<TILE, true>), dim3(n_tiles), block, 0, s, views, n_views, ranges, pair_item,
+    hipLaunchKernelGGL((k_composite_bwd<TILE, true>), dim3(n_tiles), block, 0, s, views, n_views, ranges, tile_order, pair_item,
                        n_pairs, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats);
   else
-    hipLaunchKernelGGL((k_composite_bwd<TILE, false>), dim3(n_tiles), block, 0, s, views, n_views, ranges, pair_item,
+    hipLaunchKernelGGL((k_composite_bwd<TILE, false>), dim3(n_tiles), block, 0, s, views, n_views, ranges, tile_order, pair_item,
                        n_pairs, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats);
   VBM_LAUNCH_CHECK("composite_bwd");
   return VBM_OK;
 }
 
-vbm_status launch_composite_fwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
+vbm_status launch_composite_fwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges, const uint32_t* tile_order,
                                 uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
                                 int64_t n_items, float* image, float* final_T, int32_t* n_contrib,
                                 unsigned long long* stats, hipStream_t s) {
   switch (tile) {
-    case 8: return launch_fwd_t<8>(views, n_views, n_tiles, ranges, pair_item, n_pairs, coef, blue, n_items, image, final_T, n_contrib, stats, s);
-    case 16: return launch_fwd_t<16>(views, n_views, n_tiles, ranges, pair_item, n_pairs, coef, blue, n_items, image, final_T, n_contrib, stats, s);
-    case 32: return launch_fwd_t<32>(views, n_views, n_tiles, ranges, pair_item, n_pairs, coef, blue, n_items, image, final_T, n_contrib, stats, s);
+    case 8: return launch_fwd_t<8>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, coef, blue, n_items, image, final_T, n_contrib, stats, s);
+    case 16: return launch_fwd_t<16>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, coef, blue, n_items, image, final_T, n_contrib, stats, s);
+    case 32: return launch_fwd_t<32>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, coef, blue, n_items, image, final_T, n_contrib, stats, s);
   }
   set_error("unsupported tile size %d", tile);
   return VBM_ERR_UNSUPPORTED;
 }
 
-vbm_status launch_composite_bwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
+vbm_status launch_composite_bwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges, const uint32_t* tile_order,
                                 const uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
                                 const float* final_T,
                                 const int32_t* n_contrib, const float* dL_dimg, float* grad2d, int64_t n_items,
                                 unsigned long long* stats, hipStream_t s) {
   switch (tile) {
-    case 8: return launch_bwd_t<8>(views, n_views, n_tiles, ranges, pair_item, n_pairs, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s);
-    case 16: return launch_bwd_t<16>(views, n_views, n_tiles, ranges, pair_item, n_pairs, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s);
-    case 32: return launch_bwd_t<32>(views, n_views, n_tiles, ranges, pair_item, n_pairs, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s);
+    case 8: return launch_bwd_t<8>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s);
+    case 16: return launch_bwd_t<16>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s);
+    case 32: return launch_bwd_t<32>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s);
   }
   set_error("unsupported tile size %d", tile);
   return VBM_ERR_UNSUPPORTED;

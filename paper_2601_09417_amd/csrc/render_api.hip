@@ -28,13 +28,16 @@ __global__ void k_emit(const DevView*, const uint64_t*, const uint32_t*, const u
                        const uint32_t*);
 __global__ void k_ranges(const uint32_t*, const uint32_t*, int64_t, uint2*);
 __global__ void k_status(const uint32_t*, int32_t*);
+__global__ void k_tile_keys(const uint2*, int64_t, uint32_t*, uint32_t*);
 __global__ void k_project_bwd(const DevView*, int, const DevScene*, int, vbm_gaussians_c, float*, const float4*,
                               int64_t, const uint32_t*, vbm_gaussians, int, int64_t);
 vbm_status launch_composite_fwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
+                                const uint32_t* tile_order,
                                 uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
                                 int64_t n_items, float* image, float* final_T, int32_t* n_contrib,
                                 unsigned long long* stats, hipStream_t s);
 vbm_status launch_composite_bwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
+                                const uint32_t* tile_order,
                                 const uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
                                 const float* final_T,
                                 const int32_t* n_contrib, const float* dL_dimg, float* grad2d, int64_t n_items,
@@ -64,7 +67,8 @@ enum Region {
   R_VISFLAG = 18,
   R_COEF = VBM_REGION_ITEM_COEF,
   R_MASK = 20,
-  R_COUNT = 21
+  R_TORDER = 21,   // uint32 [4][n_tiles]: sort keys, tiles, and the sorted keys and tiles (the launch order)
+  R_COUNT = 22
 };
 
 int ceil_log2(int64_t x) {
@@ -100,10 +104,13 @@ void layout(vbm_plan* p) {
   const size_t r2 = radix_scratch_bytes(P, p->sort_bits);
   if (r1 > scr) scr = r1;
   if (r2 > scr) scr = r2;
+  const size_t r3 = radix_scratch_bytes(NT, 8);
+  if (r3 > scr) scr = r3;
   sz[R_SCRATCH] = scr;
   sz[R_VISFLAG] = I * 4;
   sz[R_COEF] = I * 32;
   sz[R_MASK] = I * 4;
+  sz[R_TORDER] = 4 * NT * 4;
   size_t off = 0;
   for (int r = 0; r < VBM_WS_REGIONS; ++r) {
     p->region_offset[r] = 0;
@@ -122,6 +129,10 @@ template <class T>
 T* region(const vbm_plan* p, void* ws, int r) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + p->region_offset[r]);
 }
+
+// Launch order of the tiles for compositing (written by the forward): the sorted-tiles quarter of
+// the order region.
+uint32_t* tile_order(const vbm_plan* p, void* ws) { return region<uint32_t>(p, ws, R_TORDER) + 3 * p->n_tiles; }
 
 vbm_status check_gaussians(const vbm_gaussians_c& g, const vbm_plan* p, const char* who) {
   if (!g.means || !g.scales || !g.quats || !g.opacity || !g.rgb) {
@@ -364,8 +375,17 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
     hipLaunchKernelGGL(k_ranges, dim3(grid_cap(pair_n, 16384)), dim3(256), 0, s, pt[0], counters, cap, ranges);
     VBM_LAUNCH_CHECK("ranges");
   }
+  if (p->n_tiles > 0) {
+    // Longest lists first: one stable 8-bit pass over coarse length keys.
+    const int64_t NT = p->n_tiles;
+    uint32_t* tk = region<uint32_t>(p, ws, R_TORDER);
+    hipLaunchKernelGGL(k_tile_keys, dim3(ceil_div(NT, 256)), dim3(256), 0, s, ranges, NT, tk, tk + NT);
+    VBM_LAUNCH_CHECK("tile_keys");
+    bool in_alt = false;   // one pass, so the sorted tiles land in the last quarter
+    VBM_TRY(radix_sort_pairs<uint32_t>(tk, tk + NT, tk + 2 * NT, tk + 3 * NT, NT, nullptr, 8, 8, scratch, s, &in_alt));
+  }
   VBM_TRY(record(0, s));
-  VBM_TRY(launch_composite_fwd(p->tile, views, p->n_views, p->n_tiles, ranges, pi[0], cap, reinterpret_cast<const float*>(coef), blue, I, image, final_T,
+  VBM_TRY(launch_composite_fwd(p->tile, views, p->n_views, p->n_tiles, ranges, tile_order(p, ws), pi[0], cap, reinterpret_cast<const float*>(coef), blue, I, image, final_T,
                                n_contrib, g_stats, s));
   VBM_TRY(record(1, s));
   hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, s, counters, status);
@@ -396,7 +416,7 @@ extern "C" vbm_status vbm_render_bwd(const vbm_plan* p, const void* view_table, 
   float* grad2d = region<float>(p, ws, R_GRAD2D);
   VBM_TRY(fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, 16 * I, s));
   VBM_TRY(record(2, s));
-  VBM_TRY(launch_composite_bwd(p->tile, views, p->n_views, p->n_tiles, region<uint2>(p, ws, R_RANGES),
+  VBM_TRY(launch_composite_bwd(p->tile, views, p->n_views, p->n_tiles, region<uint2>(p, ws, R_RANGES), tile_order(p, ws),
                                region<uint32_t>(p, ws, R_PITEM), p->pair_capacity, region<float>(p, ws, R_COEF),
                                region<float>(p, ws, R_BLUE), final_T, n_contrib, dL_dimg, grad2d, I,
                                g_stats ? g_stats + 2 : nullptr, s));

@@ -62,13 +62,15 @@ def test_plan_validation_and_layout():
         st = lib.vbm_plan_make(views, 1, so.ctypes.data_as(C.POINTER(C.c_int64)), 1, C.byref(sch), C.byref(p), None)
         assert st == expect, (tile, bits, cap, mode, st)
     assert p.n_items == 100 and p.n_tiles == 2 * 2 and p.n_pixels == 64 * 48 and p.tile_key_bits == 2
-    offs = [p.region_offset[r] for r in range(20)]
-    sizes = [p.region_bytes[r] for r in range(20)]
-    for r in range(19):
+    n_regions = 22                                        # 20 documented, then mask and tile-order scratch
+    offs = [p.region_offset[r] for r in range(n_regions)]
+    sizes = [p.region_bytes[r] for r in range(n_regions)]
+    for r in range(n_regions - 1):
         assert offs[r] + sizes[r] <= offs[r + 1]
         assert offs[r] % 256 == 0
-    assert p.ws_bytes >= offs[19] + sizes[19]
+    assert p.ws_bytes >= offs[-1] + sizes[-1]
     assert sizes[19] == 32 * p.n_items
+    assert sizes[21] == 16 * p.n_tiles
     bad = (L.vbm_view * 1)(api.make_view(_cam()))
     bad[0].scene = 3
     sch = L.vbm_schedule(16, 8, 100, 0, 0)
