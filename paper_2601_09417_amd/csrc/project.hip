@@ -85,6 +85,31 @@ __device__ __forceinline__ bool tile_reached(float mx, float my, float A, float 
   return q <= tau;
 }
 
+// Rectangles of more than this many tiles are tested by a whole wave (64 tiles per round) after
+// the per-thread pass of the block, so that one large footprint does not hold up 63 lanes.
+constexpr uint32_t kSmallRect = 32;
+
+// Column and row of tile t (row-major) of a rectangle w tiles wide, with inv_w = 1/w rounded: the
+// float quotient is off by at most one and corrected.
+__device__ __forceinline__ void rect_tile(uint32_t t, uint32_t w, float inv_w, uint32_t& tx, uint32_t& ty) {
+  int r = static_cast<int>((static_cast<float>(t) + 0.5f) * inv_w);
+  int c = static_cast<int>(t) - r * static_cast<int>(w);
+  if (c < 0) {
+    --r;
+    c += static_cast<int>(w);
+  } else if (c >= static_cast<int>(w)) {
+    ++r;
+    c -= static_cast<int>(w);
+  }
+  tx = static_cast<uint32_t>(c);
+  ty = static_cast<uint32_t>(r);
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+}
+
 __device__ __forceinline__ ProjResult project_one(const DevView& v, int tile, float mx, float my, float mz, float sx,
                                                   float sy, float sz, float qw, float qx, float qy, float qz,
                                                   float opacity) {
@@ -164,45 +189,91 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
                                                  float4* __restrict__ coef, float* __restrict__ blue,
                                                  uint32_t* __restrict__ vis_flag, uint32_t* __restrict__ reach_mask,
                                                  int64_t n_items) {
+  // Large rectangles of the block, counted by whole waves after the per-thread pass.
+  __shared__ float s_par[8][256];   // mean2d.xy, conic A B C, tau, nBA, nBC
+  __shared__ uint32_t s_rect[2][256];
+  __shared__ uint32_t s_item[256];
+  __shared__ uint32_t s_n;
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
   const DevView& v = views[blockIdx.y];
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= v.n_gauss) return;
-  const int64_t gi = v.gauss_offset + i;
-  const int64_t item = v.item_offset + i;
-  const int64_t S = g.stride;
-  const float op = g.opacity[gi];
-  const ProjResult p = project_one(v, tile, g.means[gi], g.means[S + gi], g.means[2 * S + gi], g.scales[gi],
-                                   g.scales[S + gi], g.scales[2 * S + gi], g.quats[gi], g.quats[S + gi],
-                                   g.quats[2 * S + gi], g.quats[3 * S + gi], op);
-  // Reached tiles of the rectangle; for rectangles of at most 32 tiles their row-major bit mask is
-  // kept so that emission does not evaluate the footprint test again.
-  uint32_t nt = 0, mask = 0;
-  if (p.visible) {
-    const float tau = footprint_tau(op);
-    const float nBA = -__fdiv_rn(p.cb, p.ca), nBC = -__fdiv_rn(p.cb, p.cc);
-    uint32_t bit = 0;
-    for (uint32_t ty = p.y0; ty < p.y1; ++ty)
-      for (uint32_t tx = p.x0; tx < p.x1; ++tx, ++bit) {
-        const bool hit = tile_reached(p.px, p.py, p.ca, p.cb, p.cc, nBA, nBC, tau, static_cast<int>(tx),
-                                      static_cast<int>(ty), tile, v.width, v.height);
-        nt += hit ? 1u : 0u;
-        mask |= (hit && bit < 32) ? (1u << bit) : 0u;
+  if (i < v.n_gauss) {
+    const int64_t gi = v.gauss_offset + i;
+    const int64_t item = v.item_offset + i;
+    const int64_t S = g.stride;
+    const float op = g.opacity[gi];
+    const ProjResult p = project_one(v, tile, g.means[gi], g.means[S + gi], g.means[2 * S + gi], g.scales[gi],
+                                     g.scales[S + gi], g.scales[2 * S + gi], g.quats[gi], g.quats[S + gi],
+                                     g.quats[2 * S + gi], g.quats[3 * S + gi], op);
+    // Reached tiles of the rectangle; for rectangles of at most 32 tiles their row-major bit mask
+    // is kept so that emission does not evaluate the footprint test again.
+    uint32_t nt = 0, mask = 0;
+    bool deferred = false;
+    if (p.visible) {
+      const float tau = footprint_tau(op);
+      const float nBA = -__fdiv_rn(p.cb, p.ca), nBC = -__fdiv_rn(p.cb, p.cc);
+      if ((p.x1 - p.x0) * (p.y1 - p.y0) <= kSmallRect) {
+        uint32_t bit = 0;
+        for (uint32_t ty = p.y0; ty < p.y1; ++ty)
+          for (uint32_t tx = p.x0; tx < p.x1; ++tx, ++bit) {
+            const bool hit = tile_reached(p.px, p.py, p.ca, p.cb, p.cc, nBA, nBC, tau, static_cast<int>(tx),
+                                          static_cast<int>(ty), tile, v.width, v.height);
+            nt += hit ? 1u : 0u;
+            mask |= hit ? (1u << bit) : 0u;
+          }
+      } else {
+        deferred = true;
+        const uint32_t d = atomicAdd(&s_n, 1u);
+        const float par[8] = {p.px, p.py, p.ca, p.cb, p.cc, tau, nBA, nBC};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s_par[k][d] = par[k];
+        s_rect[0][d] = p.x0 | (p.x1 << 16);
+        s_rect[1][d] = p.y0 | (p.y1 << 16);
+        s_item[d] = static_cast<uint32_t>(item);
       }
+    }
+    reach_mask[item] = mask;
+    depth[item] = p.visible ? p.depth : 0.0f;
+    rect[item] = p.x0 | (p.x1 << 16);
+    rect[n_items + item] = p.y0 | (p.y1 << 16);
+    if (!deferred) {
+      ntiles[item] = nt;
+      vis_flag[item] = nt ? 1u : 0u;
+    }
+    rec[2 * item] = make_float4(p.px, p.py, p.ca, p.cb);
+    rec[2 * item + 1] = make_float4(p.cc, op, g.rgb[gi], g.rgb[S + gi]);
+    // Compositing record: the exponent in base 2 with log2(opacity) folded in,
+    // e2 = hA dx^2 + hB dx dy + hC dy^2 + log2(o) = log2(o) - (A dx^2 + 2 B dx dy + C dy^2) log2(e) / 2.
+    constexpr float kLog2e = 1.44269504088896341f;
+    coef[2 * item] = make_float4(p.px, p.py, (-0.5f * kLog2e) * p.ca, -kLog2e * p.cb);
+    coef[2 * item + 1] =
+        make_float4((-0.5f * kLog2e) * p.cc, p.visible ? __log2f(op) : 0.0f, g.rgb[gi], g.rgb[S + gi]);
+    blue[item] = g.rgb[2 * S + gi];
   }
-  reach_mask[item] = mask;
-  depth[item] = p.visible ? p.depth : 0.0f;
-  rect[item] = p.x0 | (p.x1 << 16);
-  rect[n_items + item] = p.y0 | (p.y1 << 16);
-  ntiles[item] = nt;
-  vis_flag[item] = nt ? 1u : 0u;
-  rec[2 * item] = make_float4(p.px, p.py, p.ca, p.cb);
-  rec[2 * item + 1] = make_float4(p.cc, op, g.rgb[gi], g.rgb[S + gi]);
-  // Compositing record: the exponent in base 2 with log2(opacity) folded in,
-  // e2 = hA dx^2 + hB dx dy + hC dy^2 + log2(o) = log2(o) - (A dx^2 + 2 B dx dy + C dy^2) log2(e) / 2.
-  constexpr float kLog2e = 1.44269504088896341f;
-  coef[2 * item] = make_float4(p.px, p.py, (-0.5f * kLog2e) * p.ca, -kLog2e * p.cb);
-  coef[2 * item + 1] = make_float4((-0.5f * kLog2e) * p.cc, p.visible ? __log2f(op) : 0.0f, g.rgb[gi], g.rgb[S + gi]);
-  blue[item] = g.rgb[2 * S + gi];
+  __syncthreads();
+  const uint32_t n_def = s_n;
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  for (uint32_t d = threadIdx.x >> 6; d < n_def; d += 4) {
+    const uint32_t x0 = s_rect[0][d] & 0xFFFFu, x1 = s_rect[0][d] >> 16;
+    const uint32_t y0 = s_rect[1][d] & 0xFFFFu, y1 = s_rect[1][d] >> 16;
+    const uint32_t w = x1 - x0, area = w * (y1 - y0);
+    const float inv_w = 1.0f / static_cast<float>(w);
+    uint32_t nt = 0;
+    for (uint32_t t0 = 0; t0 < area; t0 += 64) {
+      const uint32_t t = t0 + static_cast<uint32_t>(lane);
+      uint32_t tx, ty;
+      rect_tile(t, w, inv_w, tx, ty);
+      const bool hit = t < area && tile_reached(s_par[0][d], s_par[1][d], s_par[2][d], s_par[3][d], s_par[4][d],
+                                                s_par[6][d], s_par[7][d], s_par[5][d], static_cast<int>(x0 + tx),
+                                                static_cast<int>(y0 + ty), tile, v.width, v.height);
+      nt += static_cast<uint32_t>(__popcll(__ballot(hit)));
+    }
+    if (lane == 0) {
+      ntiles[s_item[d]] = nt;
+      vis_flag[s_item[d]] = nt ? 1u : 0u;
+    }
+  }
 }
 
 // Stable compaction of visible items into (view << 32 | depth bits, item) pairs.
@@ -232,62 +303,93 @@ __global__ __launch_bounds__(256) void k_gather_ntiles(const uint32_t* __restric
 }
 
 // Writes each visible item's tiles in (view, depth, item) order.  Pairs past the capacity are
-// dropped and flagged.
+// dropped and flagged.  Rectangles of at most 32 tiles walk the projection's reach mask per thread;
+// larger ones are queued in the block and emitted by whole waves afterwards (64 tiles per round,
+// positions from the ballot of reached tiles).
 __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views, const uint64_t* __restrict__ keys,
                                               const uint32_t* __restrict__ vals, const uint32_t* __restrict__ offs,
                                               const uint32_t* __restrict__ rect, const float4* __restrict__ rec,
                                               int tile, int64_t n_items, uint32_t* __restrict__ counters,
                                               int64_t n_max, int64_t capacity, uint32_t* __restrict__ pair_tile,
                                               uint32_t* __restrict__ pair_item, const uint32_t* __restrict__ reach_mask) {
+  __shared__ uint32_t s_q[256];
+  __shared__ uint32_t s_n;
   const int64_t n = min(static_cast<int64_t>(counters[0]), n_max);
-  for (int64_t p = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; p < n;
-       p += static_cast<int64_t>(gridDim.x) * 256) {
-    const uint32_t item = vals[p];
-    const DevView& v = views[keys[p] >> 32];
-    const uint32_t rx = rect[item], ry = rect[n_items + item];
-    const uint32_t x0 = rx & 0xFFFFu, x1 = rx >> 16, y0 = ry & 0xFFFFu, y1 = ry >> 16;
-    int64_t o = offs[p];
-    bool over = false;
-    const uint32_t w = x1 - x0;
-    if (w * (y1 - y0) <= 32) {
-      // Small rectangle: the projection's mask lists the reached tiles in row-major order; it is
-      // walked row by row (w bits per row), which needs no integer division.
-      uint32_t m = reach_mask[item];
-      const uint32_t row_mask = w >= 32 ? 0xFFFFFFFFu : (1u << w) - 1u;
-      uint32_t t_row = static_cast<uint32_t>(v.tile_offset) + y0 * static_cast<uint32_t>(v.tiles_x) + x0;
-      for (; m; m >>= w, t_row += static_cast<uint32_t>(v.tiles_x)) {
-        for (uint32_t r = m & row_mask; r; r &= r - 1) {
-          if (o < capacity) {
-            pair_tile[o] = t_row + static_cast<uint32_t>(__builtin_ctz(r));
-            pair_item[o] = item;
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * 256; base < n; base += static_cast<int64_t>(gridDim.x) * 256) {
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    const int64_t p = base + threadIdx.x;
+    if (p < n) {
+      const uint32_t item = vals[p];
+      const DevView& v = views[keys[p] >> 32];
+      const uint32_t rx = rect[item], ry = rect[n_items + item];
+      const uint32_t x0 = rx & 0xFFFFu, x1 = rx >> 16, y0 = ry & 0xFFFFu, y1 = ry >> 16;
+      const uint32_t w = x1 - x0;
+      if (w * (y1 - y0) <= kSmallRect) {
+        // The mask lists the reached tiles in row-major order; it is walked row by row (w bits per
+        // row), which needs no integer division.
+        int64_t o = offs[p];
+        bool over = false;
+        uint32_t m = reach_mask[item];
+        const uint32_t row_mask = w >= 32 ? 0xFFFFFFFFu : (1u << w) - 1u;
+        uint32_t t_row = static_cast<uint32_t>(v.tile_offset) + y0 * static_cast<uint32_t>(v.tiles_x) + x0;
+        for (; m; m >>= w, t_row += static_cast<uint32_t>(v.tiles_x)) {
+          for (uint32_t r = m & row_mask; r; r &= r - 1) {
+            if (o < capacity) {
+              pair_tile[o] = t_row + static_cast<uint32_t>(__builtin_ctz(r));
+              pair_item[o] = item;
+            } else {
+              over = true;
+            }
+            ++o;
+          }
+          if (w >= 32) break;
+        }
+        if (over) counters[2] = 1u;
+      } else {
+        s_q[atomicAdd(&s_n, 1u)] = threadIdx.x;
+      }
+    }
+    __syncthreads();
+    const uint32_t n_q = s_n;
+    for (uint32_t d = threadIdx.x >> 6; d < n_q; d += 4) {
+      const int64_t q = base + s_q[d];
+      const uint32_t item = vals[q];
+      const DevView& v = views[keys[q] >> 32];
+      const uint32_t rx = rect[item], ry = rect[n_items + item];
+      const uint32_t x0 = rx & 0xFFFFu, x1 = rx >> 16, y0 = ry & 0xFFFFu, y1 = ry >> 16;
+      const uint32_t w = x1 - x0, area = w * (y1 - y0);
+      const float inv_w = 1.0f / static_cast<float>(w);
+      const float4 ra = rec[2 * static_cast<int64_t>(item)];
+      const float4 rb = rec[2 * static_cast<int64_t>(item) + 1];
+      const float tau = footprint_tau(rb.y);
+      const float nBA = -__fdiv_rn(ra.w, ra.z), nBC = -__fdiv_rn(ra.w, rb.x);
+      int64_t o = offs[q];
+      bool over = false;
+      for (uint32_t t0 = 0; t0 < area; t0 += 64) {
+        const uint32_t t = t0 + static_cast<uint32_t>(lane);
+        uint32_t tx, ty;
+        rect_tile(t, w, inv_w, tx, ty);
+        tx += x0;
+        ty += y0;
+        const bool hit = t < area && tile_reached(ra.x, ra.y, ra.z, ra.w, rb.x, nBA, nBC, tau, static_cast<int>(tx),
+                                                  static_cast<int>(ty), tile, v.width, v.height);
+        const uint64_t m = __ballot(hit);
+        if (hit) {
+          const int64_t oo = o + lanes_below(m);
+          if (oo < capacity) {
+            pair_tile[oo] = static_cast<uint32_t>(v.tile_offset) + ty * static_cast<uint32_t>(v.tiles_x) + tx;
+            pair_item[oo] = item;
           } else {
             over = true;
           }
-          ++o;
         }
-        if (w >= 32) break;
+        o += __popcll(m);
       }
       if (over) counters[2] = 1u;
-      continue;
     }
-    const float4 ra = rec[2 * static_cast<int64_t>(item)];
-    const float4 rb = rec[2 * static_cast<int64_t>(item) + 1];
-    const float tau = footprint_tau(rb.y);
-    const float nBA = -__fdiv_rn(ra.w, ra.z), nBC = -__fdiv_rn(ra.w, rb.x);
-    for (uint32_t ty = y0; ty < y1; ++ty)
-      for (uint32_t tx = x0; tx < x1; ++tx) {
-        if (!tile_reached(ra.x, ra.y, ra.z, ra.w, rb.x, nBA, nBC, tau, static_cast<int>(tx), static_cast<int>(ty), tile,
-                          v.width, v.height))
-          continue;
-        if (o < capacity) {
-          pair_tile[o] = static_cast<uint32_t>(v.tile_offset) + ty * static_cast<uint32_t>(v.tiles_x) + tx;
-          pair_item[o] = item;
-        } else {
-          over = true;
-        }
-        ++o;
-      }
-    if (over) counters[2] = 1u;
+    __syncthreads();
   }
 }
 

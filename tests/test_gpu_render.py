@@ -61,6 +61,34 @@ def test_projection_and_pair_lists_bit_exact(tile):
     assert np.all(ranges[~nonempty, 0] == ranges[~nonempty, 1])      # empty tiles hold an empty range
 
 
+@pytest.mark.parametrize("tile", [8, 16])
+def test_pair_lists_large_footprints(tile):
+    """Rectangles of more than 32 tiles take the wave-cooperative counting and emission paths; mixed
+    with small ones so that blocks hold both kinds (up to a whole block of large ones)."""
+    api = _api()
+    big = vi.random_gaussians(1500, 12, log_scale_mean=-1.8)
+    small = vi.random_gaussians(1500, 13, log_scale_mean=-3.2)
+    gs = vi.GaussianSet.concat([small, big])
+    cams = vi.orbit_cameras(2, 160, 120, azimuth0=0.7)
+    say(f"large footprints tile={tile} n={gs.n}")
+    P = to_dev(gs)
+    rp = api.plan_batch(cams, [0, gs.n], tile=tile, pair_capacity=1 << 20)
+    out = api.render_fwd(rp, P)
+    torch.cuda.synchronize()
+    ref = binning.pair_lists(gs, cams, tile)
+    assert int(out.status[0]) == 0 and int(out.status[1]) == ref["tile"].size
+    ntl = rp.region("item_ntiles", torch.int32).cpu().numpy()
+    rect = rp.region("item_rect", torch.int32).cpu().numpy().view(np.uint32)
+    I = int(rp.plan.n_items)
+    area = ((rect[:I] >> 16) - (rect[:I] & 0xFFFF)) * ((rect[I:] >> 16) - (rect[I:] & 0xFFFF))
+    assert (area > 32).sum() > 300 and (area[ntl > 0] <= 32).sum() > 1000
+    for v in range(2):
+        assert np.array_equal(ntl[v * gs.n:(v + 1) * gs.n], ref["proj"][v]["n_tiles"])
+    n = ref["tile"].size
+    assert np.array_equal(rp.region("pair_tile", torch.int32).cpu().numpy()[:n], ref["tile"])
+    assert np.array_equal(rp.region("pair_item", torch.int32).cpu().numpy()[:n] & ITEM_MASK, ref["item"])
+
+
 @pytest.mark.parametrize("tile,W,H", [(16, 64, 64), (16, 101, 67), (8, 50, 37), (32, 96, 80)])
 def test_forward_backward_parity(tile, W, H):
     api = _api()
