@@ -4,8 +4,8 @@
 // offset added.  Sort: per pass a digit histogram per 4096-key tile, an exclusive scan of the
 // digit-major histogram (digit * n_tiles + tile), then a stable scatter that ranks equal digits
 // inside each wave with ballots (a lane's rank = set bits of its digit-match mask below it) and
-// across the block's waves and rounds through LDS counters, partitions the tile in LDS, and writes
-// it out in digit order (coalesced runs).
+// across a wave's rounds through per-wave LDS counters, partitions the tile in LDS, and writes it
+// out in digit order (coalesced runs).
 #include <hip/hip_runtime.h>
 
 #include "block_scan.h"
@@ -128,21 +128,25 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const K* __restrict__ k
   for (int d = threadIdx.x; d < radix; d += kThreads) hist[static_cast<int64_t>(d) * n_blocks + blockIdx.x] = s_hist[d];
 }
 
-// Stable scatter of one 4096-key tile: the tile is first partitioned by digit inside LDS (ranks
-// from wave ballots, in index order), then written out in digit order, so consecutive lanes store
-// to consecutive addresses of a digit's output run instead of 64 different buckets.
+// Stable scatter of one 4096-key tile.  Wave w owns keys [1024 w, 1024 w + 1024) and ranks them
+// in 16 rounds of 64 against its own LDS digit counters: a lane's rank among the round's equal
+// digits comes from ballots, and the wave's LDS operations complete in issue order, so a round
+// reads its digits' counters before its leaders advance them with no barrier in between.  After
+// one barrier the per-wave counters become per-wave bases (digit start in the tile plus the counts
+// of the lower waves), the tile is partitioned in LDS, and it is written out in digit order, so
+// consecutive lanes store to consecutive addresses of a digit's output run.
 template <class K>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                             K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                             const uint32_t* __restrict__ offsets, int64_t n_max,
                                                             const uint32_t* n_dev, int shift, int bits,
                                                             int64_t n_blocks) {
+  constexpr int kPerWave = kChunk / kWaves;
   __shared__ K s_key[kChunk];
   __shared__ uint32_t s_val[kChunk];
-  __shared__ uint32_t s_start[256];   // local start of each digit in the partitioned tile
-  __shared__ uint32_t s_run[256];     // next free local slot of each digit while ranking
-  __shared__ uint32_t s_glob[256];    // global start of this tile's run of each digit
-  __shared__ uint32_t s_wave_cnt[kWaves][256];
+  __shared__ uint32_t s_cnt[kWaves][256];   // per-wave digit counts, then per-wave digit bases
+  __shared__ uint32_t s_start[256];         // start of each digit in the partitioned tile
+  __shared__ uint32_t s_glob[256];          // global start of this tile's run of each digit
   const int64_t n = active_count(n_max, n_dev);
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kChunk;
   if (base >= n) return;  // uniform per block
@@ -150,58 +154,62 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const K* __restrict_
   const int radix = 1 << bits;
   const uint32_t mask = static_cast<uint32_t>(radix - 1);
   const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  for (int x = threadIdx.x; x < kWaves * 256; x += kThreads) (&s_cnt[0][0])[x] = 0;
+  if (static_cast<int>(threadIdx.x) < radix)
+    s_glob[threadIdx.x] = offsets[static_cast<int64_t>(threadIdx.x) * n_blocks + blockIdx.x];
   K keys[kItems];
   uint32_t vals[kItems];
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    const int li = r * kThreads + threadIdx.x;
+    const int li = w * kPerWave + r * 64 + lane;
     keys[r] = li < count ? kin[base + li] : K(0);
     vals[r] = li < count ? vin[base + li] : 0u;
   }
-  // local digit histogram -> local starts
-  s_run[threadIdx.x] = 0;
   __syncthreads();
+  uint32_t slot[kItems];   // rank among the wave's keys of the same digit
 #pragma unroll
-  for (int r = 0; r < kItems; ++r)
-    if (r * kThreads + static_cast<int>(threadIdx.x) < count)
-      atomicAdd(&s_run[static_cast<uint32_t>(keys[r] >> shift) & mask], 1u);
-  __syncthreads();
-  uint32_t tot;
-  const uint32_t start = block_excl_scan(s_run[threadIdx.x], &tot);
-  s_start[threadIdx.x] = start;
-  s_run[threadIdx.x] = start;
-  if (static_cast<int>(threadIdx.x) < radix)
-    s_glob[threadIdx.x] = offsets[static_cast<int64_t>(threadIdx.x) * n_blocks + blockIdx.x];
-  // rank in index order and place into LDS
   for (int r = 0; r < kItems; ++r) {
-    const bool valid = r * kThreads + static_cast<int>(threadIdx.x) < count;
+    const bool valid = w * kPerWave + r * 64 + lane < count;
     const uint32_t d = static_cast<uint32_t>(keys[r] >> shift) & mask;
-    for (int x = threadIdx.x; x < kWaves * 256; x += kThreads) (&s_wave_cnt[0][0])[x] = 0;
-    __syncthreads();
     uint64_t m = __ballot(valid);
     for (int b = 0; b < bits; ++b) {
       const bool bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(valid && bit);
+      const uint64_t bb = __ballot(bit);
       m &= bit ? bb : ~bb;
     }
     const uint32_t rank = popc_below(m);
-    if (valid && rank == 0) s_wave_cnt[w][d] = static_cast<uint32_t>(__popcll(m));
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = s_run[d] + rank;
-      for (int ww = 0; ww < w; ++ww) pos += s_wave_cnt[ww][d];
+    const uint32_t before = s_cnt[w][d];
+    if (valid && rank == 0) s_cnt[w][d] = before + static_cast<uint32_t>(__popcll(m));
+    slot[r] = before + rank;
+  }
+  __syncthreads();
+  {
+    uint32_t c[kWaves], t = 0;
+#pragma unroll
+    for (int ww = 0; ww < kWaves; ++ww) {
+      c[ww] = s_cnt[ww][threadIdx.x];
+      t += c[ww];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan(t, &tot);
+    s_start[threadIdx.x] = run;
+#pragma unroll
+    for (int ww = 0; ww < kWaves; ++ww) {
+      s_cnt[ww][threadIdx.x] = run;
+      run += c[ww];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    if (w * kPerWave + r * 64 + lane < count) {
+      const uint32_t pos = s_cnt[w][static_cast<uint32_t>(keys[r] >> shift) & mask] + slot[r];
       s_key[pos] = keys[r];
       s_val[pos] = vals[r];
     }
-    __syncthreads();
-    {
-      uint32_t add = 0;
-#pragma unroll
-      for (int ww = 0; ww < kWaves; ++ww) add += s_wave_cnt[ww][threadIdx.x];
-      s_run[threadIdx.x] += add;
-    }
-    __syncthreads();  // s_run complete and s_wave_cnt read before the next round clears it
   }
+  __syncthreads();
   // write out in digit order
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
