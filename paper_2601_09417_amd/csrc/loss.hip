@@ -35,8 +35,9 @@ constexpr int RPT = 4;             // output rows per thread in the vertical pas
 constexpr int kRedBlocks = 256;    // first stage of the partial-sum reduction
 constexpr float kC1 = 0.01f * 0.01f;
 constexpr float kC2 = 0.03f * 0.03f;
-constexpr int kLoads = (EX * EY + 255) / 256;  // halo elements per thread
+constexpr int kRowLoads = (EY + 3) / 4;        // halo rows per wave (a lane per halo column)
 static_assert(TX * (TY / RPT) == 256, "vertical pass covers the tile with 256 threads");
+static_assert(EX <= 64, "a halo row fits one wave");
 
 struct Window {
   float w[2 * RAD + 1];
@@ -80,39 +81,51 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ x, const f
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// Pass 1 of SSIM for one view: grid (tiles_x, tiles_y, 3 channels), 256 threads, 32x32 outputs
-// per block.  The five horizontally filtered maps of the (TY + 10) x TX halo rows are staged in
-// LDS; each thread then filters a 4-row strip of one column vertically.
-__global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, const float* __restrict__ y, int W,
-                                                   int H, Window win, float* __restrict__ p1, float* __restrict__ p2,
-                                                   float* __restrict__ p3, float* __restrict__ partial_s,
-                                                   float* __restrict__ partial_l1) {
-  __shared__ float sx[EY][EX + 1], sy[EY][EX + 1];
-  __shared__ float hb[5][EY][TX];
-  __shared__ float s_red[4];
-  const int c = blockIdx.z;
-  const int64_t HW = static_cast<int64_t>(W) * H;
-  const float* xc = x + c * HW;
-  const float* yc = y + c * HW;
-  const int ox = blockIdx.x * TX - RAD, oy = blockIdx.y * TY - RAD;
-  // All of a thread's halo loads are issued before the first LDS store, so their latencies overlap.
-  float vx[kLoads], vy[kLoads];
+// Loads the (TY + 10) x (TX + 10) halo of one channel into LDS: wave w takes halo rows w, w + 4,
+// ..., a lane per column; every load is issued before the first store so their latencies overlap.
+template <int NF>
+__device__ __forceinline__ void load_halo(const float* const (&src)[NF], int W, int H, int ox, int oy,
+                                          float (*dst)[EY][EX + 1]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int gx = ox + lane;
+  float v[NF][kRowLoads];
 #pragma unroll
-  for (int k = 0; k < kLoads; ++k) {
-    const int i = threadIdx.x + 256 * k;
-    const int r = i / EX, q = i % EX;
-    const int gx = ox + q, gy = oy + r;
-    const bool in = i < EX * EY && gx >= 0 && gx < W && gy >= 0 && gy < H;
-    vx[k] = in ? xc[static_cast<int64_t>(gy) * W + gx] : 0.0f;
-    vy[k] = in ? yc[static_cast<int64_t>(gy) * W + gx] : 0.0f;
+  for (int k = 0; k < kRowLoads; ++k) {
+    const int r = w + 4 * k, gy = oy + r;
+    const bool in = lane < EX && r < EY && gx >= 0 && gx < W && gy >= 0 && gy < H;
+    const int64_t off = static_cast<int64_t>(gy) * W + gx;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) v[f][k] = in ? src[f][off] : 0.0f;
   }
 #pragma unroll
-  for (int k = 0; k < kLoads; ++k) {
-    const int i = threadIdx.x + 256 * k;
-    if (i < EX * EY) {
-      sx[i / EX][i % EX] = vx[k];
-      sy[i / EX][i % EX] = vy[k];
-    }
+  for (int k = 0; k < kRowLoads; ++k) {
+    const int r = w + 4 * k;
+    if (lane < EX && r < EY)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) dst[f][r][lane] = v[f][k];
+  }
+}
+
+// Pass 1 of SSIM over a run of views of equal size: grid (tiles per view, 3 channels, views),
+// 256 threads, 32x32 outputs per block.  The five horizontally filtered maps of the (TY + 10) x TX
+// halo rows are staged in LDS; each thread then filters a 4-row strip of one column vertically.
+__global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, const float* __restrict__ y, int W,
+                                                   int H, int tiles_x, Window win, float* __restrict__ p1,
+                                                   float* __restrict__ p2, float* __restrict__ p3,
+                                                   float* __restrict__ partial_s, float* __restrict__ partial_l1) {
+  __shared__ float sxy[2][EY][EX + 1];
+  __shared__ float hb[5][EY][TX];
+  __shared__ float s_red[4];
+  auto sx = sxy[0];
+  auto sy = sxy[1];
+  const int c = blockIdx.y;
+  const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
+  const int64_t HW = static_cast<int64_t>(W) * H;
+  const int64_t chan = (3 * static_cast<int64_t>(blockIdx.z) + c) * HW;
+  const int ox = bx * TX - RAD, oy = by * TY - RAD;
+  {
+    const float* const src[2] = {x + chan, y + chan};
+    load_halo<2>(src, W, H, ox, oy, sxy);
   }
   __syncthreads();
   // Horizontal pass: a task filters four adjacent columns of one halo row, so each of the 14 input
@@ -148,7 +161,7 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
   __syncthreads();
   const int col = threadIdx.x % TX;
   const int r0 = (threadIdx.x / TX) * RPT;
-  const int gx = blockIdx.x * TX + col;
+  const int gx = bx * TX + col;
   float m[RPT][5];
 #pragma unroll
   for (int o = 0; o < RPT; ++o)
@@ -167,7 +180,7 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
   float sval = 0.0f, l1 = 0.0f;
 #pragma unroll
   for (int o = 0; o < RPT; ++o) {
-    const int gy = blockIdx.y * TY + r0 + o;
+    const int gy = by * TY + r0 + o;
     if (gx < W && gy < H) {
       const float mx = m[o][0], my = m[o][1];
       const float vx = m[o][2] - mx * mx, vy = m[o][3] - my * my, cxy = m[o][4] - mx * my;
@@ -177,7 +190,7 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
       const float iA1 = __builtin_amdgcn_rcpf(A1), iA2 = __builtin_amdgcn_rcpf(A2);
       const float iB1 = __builtin_amdgcn_rcpf(B1), iB2 = __builtin_amdgcn_rcpf(B2);
       const float sv = (A1 * A2) * (iB1 * iB2);
-      const int64_t pix = c * HW + static_cast<int64_t>(gy) * W + gx;
+      const int64_t pix = chan + static_cast<int64_t>(gy) * W + gx;
       p1[pix] = 2.0f * sv * (my * (iA1 - iA2) + mx * (iB2 - iB1));
       p2[pix] = -sv * iB2;
       p3[pix] = 2.0f * sv * iA2;
@@ -193,49 +206,51 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
   if (threadIdx.x == 0) partial_l1[bid] = tl;
 }
 
-// Pass 2: dL/dx = w_l1 sign(x - y) - w_ssim [w*p1 + 2 x (w*p2) + y (w*p3)], same tiling.
+// Pass 2: dL/dx = w_l1 sign(x - y) - w_ssim [w*p1 + 2 x (w*p2) + y (w*p3)], same tiling; the
+// horizontal pass filters four adjacent columns per task, reading each input once for all four.
 __global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ x, const float* __restrict__ y, int W,
-                                                   int H, Window win, const float* __restrict__ p1,
+                                                   int H, int tiles_x, Window win, const float* __restrict__ p1,
                                                    const float* __restrict__ p2, const float* __restrict__ p3,
                                                    float w_l1, float w_ssim, float* __restrict__ grad) {
   __shared__ float sp[3][EY][EX + 1];
   __shared__ float hb[3][EY][TX];
-  const int c = blockIdx.z;
+  const int c = blockIdx.y;
+  const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
   const int64_t HW = static_cast<int64_t>(W) * H;
-  const int ox = blockIdx.x * TX - RAD, oy = blockIdx.y * TY - RAD;
-  const float* P[3] = {p1 + c * HW, p2 + c * HW, p3 + c * HW};
-  float vp[3][kLoads];
-#pragma unroll
-  for (int k = 0; k < kLoads; ++k) {
-    const int i = threadIdx.x + 256 * k;
-    const int r = i / EX, q = i % EX;
-    const int gx = ox + q, gy = oy + r;
-    const bool in = i < EX * EY && gx >= 0 && gx < W && gy >= 0 && gy < H;
-    const int64_t off = static_cast<int64_t>(gy) * W + gx;
-#pragma unroll
-    for (int f = 0; f < 3; ++f) vp[f][k] = in ? P[f][off] : 0.0f;
+  const int64_t chan = (3 * static_cast<int64_t>(blockIdx.z) + c) * HW;
+  const int ox = bx * TX - RAD, oy = by * TY - RAD;
+  {
+    const float* const src[3] = {p1 + chan, p2 + chan, p3 + chan};
+    load_halo<3>(src, W, H, ox, oy, sp);
   }
+  __syncthreads();
+  constexpr int CPT = 4;
+  for (int task = threadIdx.x; task < EY * (TX / CPT); task += 256) {
+    const int r = task / (TX / CPT), c0 = (task % (TX / CPT)) * CPT;
+    float a[3][CPT];
 #pragma unroll
-  for (int k = 0; k < kLoads; ++k) {
-    const int i = threadIdx.x + 256 * k;
-    if (i < EX * EY)
+    for (int f = 0; f < 3; ++f)
 #pragma unroll
-      for (int f = 0; f < 3; ++f) sp[f][i / EX][i % EX] = vp[f][k];
+      for (int o = 0; o < CPT; ++o) a[f][o] = 0.0f;
+#pragma unroll
+    for (int t = 0; t < CPT + 2 * RAD; ++t) {
+#pragma unroll
+      for (int f = 0; f < 3; ++f) {
+        const float u = sp[f][r][c0 + t];
+#pragma unroll
+        for (int o = 0; o < CPT; ++o)
+          if (t - o >= 0 && t - o <= 2 * RAD) a[f][o] = fmaf(win.w[t - o], u, a[f][o]);
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+      for (int o = 0; o < CPT; ++o) hb[f][r][c0 + o] = a[f][o];
   }
   __syncthreads();
   const int col = threadIdx.x % TX;
-  for (int r = threadIdx.x / TX; r < EY; r += 256 / TX) {
-    float a[3] = {0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < 2 * RAD + 1; ++k)
-#pragma unroll
-      for (int f = 0; f < 3; ++f) a[f] = fmaf(win.w[k], sp[f][r][col + k], a[f]);
-#pragma unroll
-    for (int f = 0; f < 3; ++f) hb[f][r][col] = a[f];
-  }
-  __syncthreads();
   const int r0 = (threadIdx.x / TX) * RPT;
-  const int gx = blockIdx.x * TX + col;
+  const int gx = bx * TX + col;
   float b[RPT][3];
 #pragma unroll
   for (int o = 0; o < RPT; ++o)
@@ -254,9 +269,9 @@ __global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ x, 
   if (gx >= W) return;
 #pragma unroll
   for (int o = 0; o < RPT; ++o) {
-    const int gy = blockIdx.y * TY + r0 + o;
+    const int gy = by * TY + r0 + o;
     if (gy >= H) continue;
-    const int64_t pix = c * HW + static_cast<int64_t>(gy) * W + gx;
+    const int64_t pix = chan + static_cast<int64_t>(gy) * W + gx;
     const float xv = x[pix], yv = y[pix];
     const float d = xv - yv;
     const float sg = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
@@ -376,18 +391,24 @@ extern "C" vbm_status vbm_image_loss(const float* image, const float* target, co
   const Window win = make_window();
   const float w_l1 = (1.0f - lambda) / static_cast<float>(n);
   const float w_ss = lambda / static_cast<float>(n);
+  // One launch of each pass per run of consecutive views of equal size (grid.z = the run's views;
+  // their images are consecutive); the partial slots keep the view, channel, tile order.
   int64_t off = 0, boff = 0;
-  for (int v = 0; v < n_views; ++v) {
+  for (int v = 0; v < n_views;) {
     const int W = dims[2 * v], H = dims[2 * v + 1];
-    const dim3 grid(static_cast<unsigned>(ceil_div(W, TX)), static_cast<unsigned>(ceil_div(H, TY)), 3);
-    hipLaunchKernelGGL(k_ssim_maps, grid, dim3(256), 0, s, image + off, target + off, W, H, win, p1 + off, p2 + off,
-                       p3 + off, ps + boff, pl + boff);
+    int nv = 1;
+    while (v + nv < n_views && nv < 65535 && dims[2 * (v + nv)] == W && dims[2 * (v + nv) + 1] == H) ++nv;
+    const int tx = static_cast<int>(ceil_div(W, TX)), ty = static_cast<int>(ceil_div(H, TY));
+    const dim3 grid(static_cast<unsigned>(tx * ty), 3, static_cast<unsigned>(nv));
+    hipLaunchKernelGGL(k_ssim_maps, grid, dim3(256), 0, s, image + off, target + off, W, H, tx, win, p1 + off,
+                       p2 + off, p3 + off, ps + boff, pl + boff);
     VBM_LAUNCH_CHECK("ssim_maps");
-    hipLaunchKernelGGL(k_ssim_grad, grid, dim3(256), 0, s, image + off, target + off, W, H, win, p1 + off, p2 + off,
-                       p3 + off, w_l1, w_ss, grad + off);
+    hipLaunchKernelGGL(k_ssim_grad, grid, dim3(256), 0, s, image + off, target + off, W, H, tx, win, p1 + off,
+                       p2 + off, p3 + off, w_l1, w_ss, grad + off);
     VBM_LAUNCH_CHECK("ssim_grad");
-    off += 3 * static_cast<int64_t>(W) * H;
-    boff += static_cast<int64_t>(grid.x) * grid.y * 3;
+    off += 3 * static_cast<int64_t>(W) * H * nv;
+    boff += static_cast<int64_t>(tx) * ty * 3 * nv;
+    v += nv;
   }
   hipLaunchKernelGGL(k_reduce_stage, dim3(kRedBlocks), dim3(256), 0, s, pl, ps, blocks,
                      ceil_div(blocks, kRedBlocks), parts);

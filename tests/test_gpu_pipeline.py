@@ -95,7 +95,8 @@ def test_select_ties_go_to_lower_index():
 def test_loss_matches_oracle(kind):
     api = _api()
     rng = np.random.default_rng(4)
-    dims = [(37, 29), (64, 48), (101, 70)]   # ragged and multi-tile for 32x32 loss tiles
+    # ragged and multi-tile for 32x32 loss tiles; runs of equal sizes share one launch per pass
+    dims = [(37, 29), (64, 48), (64, 48), (101, 70), (37, 29), (37, 29)]
     imgs = [rng.uniform(size=(3, h, w)).astype(np.float32) for w, h in dims]
     tgts = [np.clip(i + 0.1 * rng.normal(size=i.shape), 0, 1).astype(np.float32) for i in imgs]
     x = torch.from_numpy(np.concatenate([i.reshape(-1) for i in imgs])).to(dev())
