@@ -113,9 +113,13 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
                                                    int H, int tiles_x, Window win, float* __restrict__ p1,
                                                    float* __restrict__ p2, float* __restrict__ p3,
                                                    float* __restrict__ partial_s, float* __restrict__ partial_l1) {
-  __shared__ float sxy[2][EY][EX + 1];
-  __shared__ float hb[5][EY][TX];
+  // The filtered maps 3 and 4 overlay the input halo: the horizontal pass holds them in registers
+  // until every thread has read the halo.
+  constexpr int kHalo = EY * (EX + 1), kMap = EY * TX;
+  __shared__ float lds[3 * kMap + 2 * kHalo];
   __shared__ float s_red[4];
+  auto sxy = reinterpret_cast<float(*)[EY][EX + 1]>(lds + 3 * kMap);
+  auto hb = reinterpret_cast<float(*)[EY][TX]>(lds);
   auto sx = sxy[0];
   auto sy = sxy[1];
   const int c = blockIdx.y;
@@ -128,10 +132,21 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
     load_halo<2>(src, W, H, ox, oy, sxy);
   }
   __syncthreads();
+  const int col = threadIdx.x % TX;
+  const int r0 = (threadIdx.x / TX) * RPT;
+  float l1 = 0.0f;   // |x - y| of the thread's outputs (zero outside the image)
+#pragma unroll
+  for (int o = 0; o < RPT; ++o) l1 += fabsf(sx[r0 + o + RAD][col + RAD] - sy[r0 + o + RAD][col + RAD]);
   // Horizontal pass: a task filters four adjacent columns of one halo row, so each of the 14 input
   // values it reads forms its three products once for all four outputs.
   constexpr int CPT = 4;                          // columns per task
-  for (int task = threadIdx.x; task < EY * (TX / CPT); task += 256) {
+  constexpr int kTasks = EY * (TX / CPT);
+  static_assert(kTasks <= 512, "two rounds of tasks");
+  float keep[2][2][CPT];
+#pragma unroll
+  for (int rd = 0; rd < 2; ++rd) {
+    const int task = threadIdx.x + 256 * rd;
+    if (task >= kTasks) break;
     const int r = task / (TX / CPT), c0 = (task % (TX / CPT)) * CPT;
     float acc[5][CPT];
 #pragma unroll
@@ -154,13 +169,28 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
       }
     }
 #pragma unroll
-    for (int f = 0; f < 5; ++f)
+    for (int f = 0; f < 3; ++f)
 #pragma unroll
       for (int o = 0; o < CPT; ++o) hb[f][r][c0 + o] = acc[f][o];
+#pragma unroll
+    for (int o = 0; o < CPT; ++o) {
+      keep[rd][0][o] = acc[3][o];
+      keep[rd][1][o] = acc[4][o];
+    }
   }
   __syncthreads();
-  const int col = threadIdx.x % TX;
-  const int r0 = (threadIdx.x / TX) * RPT;
+#pragma unroll
+  for (int rd = 0; rd < 2; ++rd) {
+    const int task = threadIdx.x + 256 * rd;
+    if (task >= kTasks) break;
+    const int r = task / (TX / CPT), c0 = (task % (TX / CPT)) * CPT;
+#pragma unroll
+    for (int o = 0; o < CPT; ++o) {
+      hb[3][r][c0 + o] = keep[rd][0][o];
+      hb[4][r][c0 + o] = keep[rd][1][o];
+    }
+  }
+  __syncthreads();
   const int gx = bx * TX + col;
   float m[RPT][5];
 #pragma unroll
@@ -177,7 +207,7 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
         if (t - o >= 0 && t - o <= 2 * RAD) m[o][f] = fmaf(win.w[t - o], h, m[o][f]);
     }
   }
-  float sval = 0.0f, l1 = 0.0f;
+  float sval = 0.0f;
 #pragma unroll
   for (int o = 0; o < RPT; ++o) {
     const int gy = by * TY + r0 + o;
@@ -195,7 +225,6 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
       p2[pix] = -sv * iB2;
       p3[pix] = 2.0f * sv * iA2;
       sval += sv;
-      l1 += fabsf(sx[r0 + o + RAD][col + RAD] - sy[r0 + o + RAD][col + RAD]);
     }
   }
   const int64_t bid = (static_cast<int64_t>(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
@@ -212,8 +241,11 @@ __global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ x, 
                                                    int H, int tiles_x, Window win, const float* __restrict__ p1,
                                                    const float* __restrict__ p2, const float* __restrict__ p3,
                                                    float w_l1, float w_ssim, float* __restrict__ grad) {
-  __shared__ float sp[3][EY][EX + 1];
-  __shared__ float hb[3][EY][TX];
+  // Filtered maps 1 and 2 overlay the input halo (held in registers until it has been read).
+  constexpr int kHalo = EY * (EX + 1), kMap = EY * TX;
+  __shared__ float lds[kMap + 3 * kHalo];
+  auto sp = reinterpret_cast<float(*)[EY][EX + 1]>(lds + kMap);
+  auto hb = reinterpret_cast<float(*)[EY][TX]>(lds);
   const int c = blockIdx.y;
   const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
   const int64_t HW = static_cast<int64_t>(W) * H;
@@ -225,7 +257,13 @@ __global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ x, 
   }
   __syncthreads();
   constexpr int CPT = 4;
-  for (int task = threadIdx.x; task < EY * (TX / CPT); task += 256) {
+  constexpr int kTasks = EY * (TX / CPT);
+  static_assert(kTasks <= 512, "two rounds of tasks");
+  float keep[2][2][CPT];
+#pragma unroll
+  for (int rd = 0; rd < 2; ++rd) {
+    const int task = threadIdx.x + 256 * rd;
+    if (task >= kTasks) break;
     const int r = task / (TX / CPT), c0 = (task % (TX / CPT)) * CPT;
     float a[3][CPT];
 #pragma unroll
@@ -243,9 +281,23 @@ __global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ x, 
       }
     }
 #pragma unroll
-    for (int f = 0; f < 3; ++f)
+    for (int o = 0; o < CPT; ++o) {
+      hb[0][r][c0 + o] = a[0][o];
+      keep[rd][0][o] = a[1][o];
+      keep[rd][1][o] = a[2][o];
+    }
+  }
+  __syncthreads();
 #pragma unroll
-      for (int o = 0; o < CPT; ++o) hb[f][r][c0 + o] = a[f][o];
+  for (int rd = 0; rd < 2; ++rd) {
+    const int task = threadIdx.x + 256 * rd;
+    if (task >= kTasks) break;
+    const int r = task / (TX / CPT), c0 = (task % (TX / CPT)) * CPT;
+#pragma unroll
+    for (int o = 0; o < CPT; ++o) {
+      hb[1][r][c0 + o] = keep[rd][0][o];
+      hb[2][r][c0 + o] = keep[rd][1][o];
+    }
   }
   __syncthreads();
   const int col = threadIdx.x % TX;
