@@ -39,7 +39,7 @@ FP32_PEAK_TFLOPS = 157.3
 # Algorithmic cost per (pixel, Gaussian) evaluation of the compositing kernels.
 FLOPS_FWD_EVAL, FLOPS_FWD_USED = 17, 8
 FLOPS_BWD_EVAL, FLOPS_BWD_USED = 17, 40
-BYTES_PER_PAIR_FWD, BYTES_PER_PIXEL_FWD = 40, 20
+BYTES_PER_PAIR_FWD, BYTES_PER_PIXEL_FWD = 40, 20   # algorithmic (the lane-group marks written back are not counted)
 BYTES_PER_PAIR_BWD, BYTES_PER_PIXEL_BWD = 76, 20
 
 WORKLOADS = {
