@@ -12,10 +12,10 @@
 //   ds/dmu_x = s (2 mu_y / A1 - 2 mu_y / A2 - 2 mu_x / B1 + 2 mu_x / B2),  ds/dSxx = -s / B2,
 //   ds/dSxy = 2 s / A2,  A1 = 2 mu_x mu_y + C1, A2 = 2 sigma_xy + C2, B1 = mu_x^2 + mu_y^2 + C1,
 //   B2 = sigma_x^2 + sigma_y^2 + C2.
-// Two LDS-tiled passes per view over 32x32 output tiles (256 threads, each filtering a 4-row strip
-// of one column vertically): (1) the five filtered maps -> s and the three partials, (2) the
-// filtered partials -> dL/dx.  Partial sums go to per-block slots reduced in two fixed-order
-// stages (256 contiguous chunks, then one block), so the loss value is deterministic.
+// Two LDS-tiled passes over 32x32 output tiles (256 threads, each filtering a 4-row strip of one
+// column vertically): (1) the four filtered maps (x, y, x^2 + y^2, x y) -> s and the three
+// partials, (2) the filtered partials -> dL/dx.  Partial sums go to per-block slots reduced in two
+// fixed-order stages (256 contiguous chunks, then one block), so the loss value is deterministic.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -107,18 +107,20 @@ __device__ __forceinline__ void load_halo(const float* const (&src)[NF], int W, 
 }
 
 // Pass 1 of SSIM over a run of views of equal size: grid (tiles per view, 3 channels, views),
-// 256 threads, 32x32 outputs per block.  The five horizontally filtered maps of the (TY + 10) x TX
-// halo rows are staged in LDS; each thread then filters a 4-row strip of one column vertically.
+// 256 threads, 32x32 outputs per block.  SSIM needs E[x^2] and E[y^2] only through their sum (in
+// sigma_x^2 + sigma_y^2, and d/dx of the sum is that of E[x^2]), so four signals are filtered:
+// x, y, x^2 + y^2 and x y.  Their horizontally filtered maps over the (TY + 10) x TX halo rows are
+// staged in LDS; each thread then filters a 4-row strip of one column vertically.
 __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, const float* __restrict__ y, int W,
                                                    int H, int tiles_x, Window win, float* __restrict__ p1,
                                                    float* __restrict__ p2, float* __restrict__ p3,
                                                    float* __restrict__ partial_s, float* __restrict__ partial_l1) {
-  // The filtered maps 3 and 4 overlay the input halo: the horizontal pass holds them in registers
+  // The filtered maps 2 and 3 overlay the input halo: the horizontal pass holds them in registers
   // until every thread has read the halo.
   constexpr int kHalo = EY * (EX + 1), kMap = EY * TX;
-  __shared__ float lds[3 * kMap + 2 * kHalo];
+  __shared__ float lds[2 * kMap + 2 * kHalo];
   __shared__ float s_red[4];
-  auto sxy = reinterpret_cast<float(*)[EY][EX + 1]>(lds + 3 * kMap);
+  auto sxy = reinterpret_cast<float(*)[EY][EX + 1]>(lds + 2 * kMap);
   auto hb = reinterpret_cast<float(*)[EY][TX]>(lds);
   auto sx = sxy[0];
   auto sy = sxy[1];
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
 #pragma unroll
   for (int o = 0; o < RPT; ++o) l1 += fabsf(sx[r0 + o + RAD][col + RAD] - sy[r0 + o + RAD][col + RAD]);
   // Horizontal pass: a task filters four adjacent columns of one halo row, so each of the 14 input
-  // values it reads forms its three products once for all four outputs.
+  // values it reads forms its two products once for all four outputs.
   constexpr int CPT = 4;                          // columns per task
   constexpr int kTasks = EY * (TX / CPT);
   static_assert(kTasks <= 512, "two rounds of tasks");
@@ -148,34 +150,33 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
     const int task = threadIdx.x + 256 * rd;
     if (task >= kTasks) break;
     const int r = task / (TX / CPT), c0 = (task % (TX / CPT)) * CPT;
-    float acc[5][CPT];
+    float acc[4][CPT];
 #pragma unroll
-    for (int f = 0; f < 5; ++f)
+    for (int f = 0; f < 4; ++f)
 #pragma unroll
       for (int o = 0; o < CPT; ++o) acc[f][o] = 0.0f;
 #pragma unroll
     for (int t = 0; t < CPT + 2 * RAD; ++t) {
       const float u = sx[r][c0 + t], v = sy[r][c0 + t];
-      const float uu = u * u, vv = v * v, uv = u * v;
+      const float qq = fmaf(u, u, v * v), uv = u * v;
 #pragma unroll
       for (int o = 0; o < CPT; ++o) {
         if (t - o < 0 || t - o > 2 * RAD) continue;
         const float wk = win.w[t - o];
         acc[0][o] = fmaf(wk, u, acc[0][o]);
         acc[1][o] = fmaf(wk, v, acc[1][o]);
-        acc[2][o] = fmaf(wk, uu, acc[2][o]);
-        acc[3][o] = fmaf(wk, vv, acc[3][o]);
-        acc[4][o] = fmaf(wk, uv, acc[4][o]);
+        acc[2][o] = fmaf(wk, qq, acc[2][o]);
+        acc[3][o] = fmaf(wk, uv, acc[3][o]);
       }
     }
 #pragma unroll
-    for (int f = 0; f < 3; ++f)
+    for (int f = 0; f < 2; ++f)
 #pragma unroll
       for (int o = 0; o < CPT; ++o) hb[f][r][c0 + o] = acc[f][o];
 #pragma unroll
     for (int o = 0; o < CPT; ++o) {
-      keep[rd][0][o] = acc[3][o];
-      keep[rd][1][o] = acc[4][o];
+      keep[rd][0][o] = acc[2][o];
+      keep[rd][1][o] = acc[3][o];
     }
   }
   __syncthreads();
@@ -186,21 +187,21 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
     const int r = task / (TX / CPT), c0 = (task % (TX / CPT)) * CPT;
 #pragma unroll
     for (int o = 0; o < CPT; ++o) {
-      hb[3][r][c0 + o] = keep[rd][0][o];
-      hb[4][r][c0 + o] = keep[rd][1][o];
+      hb[2][r][c0 + o] = keep[rd][0][o];
+      hb[3][r][c0 + o] = keep[rd][1][o];
     }
   }
   __syncthreads();
   const int gx = bx * TX + col;
-  float m[RPT][5];
+  float m[RPT][4];
 #pragma unroll
   for (int o = 0; o < RPT; ++o)
 #pragma unroll
-    for (int f = 0; f < 5; ++f) m[o][f] = 0.0f;
+    for (int f = 0; f < 4; ++f) m[o][f] = 0.0f;
 #pragma unroll
   for (int t = 0; t < RPT + 2 * RAD; ++t) {
 #pragma unroll
-    for (int f = 0; f < 5; ++f) {
+    for (int f = 0; f < 4; ++f) {
       const float h = hb[f][r0 + t][col];
 #pragma unroll
       for (int o = 0; o < RPT; ++o)
@@ -213,9 +214,9 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
     const int gy = by * TY + r0 + o;
     if (gx < W && gy < H) {
       const float mx = m[o][0], my = m[o][1];
-      const float vx = m[o][2] - mx * mx, vy = m[o][3] - my * my, cxy = m[o][4] - mx * my;
+      const float mm = mx * mx + my * my, cxy = m[o][3] - mx * my;
       const float A1 = 2.0f * mx * my + kC1, A2 = 2.0f * cxy + kC2;
-      const float B1 = mx * mx + my * my + kC1, B2 = vx + vy + kC2;
+      const float B1 = mm + kC1, B2 = (m[o][2] - mm) + kC2;   // sigma_x^2 + sigma_y^2 + C2
       // four hardware reciprocals (about 1 ulp) instead of six divisions
       const float iA1 = __builtin_amdgcn_rcpf(A1), iA2 = __builtin_amdgcn_rcpf(A2);
       const float iB1 = __builtin_amdgcn_rcpf(B1), iB2 = __builtin_amdgcn_rcpf(B2);

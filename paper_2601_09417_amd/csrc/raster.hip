@@ -279,20 +279,27 @@ __device__ __forceinline__ uint32_t fwd_step(const Rec& r, int pos, float fx, fl
     groups |= 1u << k;
     const float alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e2));
     const bool ok = alpha >= kAlphaMin;
-    const float w = alpha * T[k];
-    const float Tn = T[k] - w;
-    const bool stop = ok && Tn < kTMin;
+    // A pixel that fails the alpha test takes weight 0, which leaves T and its colour unchanged.
+    float w = (ok ? alpha : 0.0f) * T[k];
+    float Tn = T[k] - w;
+    // A live pixel keeps T >= 1e-4, so only one that takes the Gaussian can fall below: it stops
+    // without it (rare, so handled in a uniform branch).
+    const bool stop = Tn < kTMin;
+    if (wave_any(stop)) {
+      __asm__ volatile("" ::: "memory");   // keeps this a branch: the compiler would select both ways
+      w = stop ? 0.0f : w;
+      Tn = stop ? T[k] : Tn;
+      fy[k] = stop ? kDeadRow : fy[k];
+    }
     const bool use = ok && !stop;
     if (STATS) {
-      n_eval += fy[k] < kLiveBound ? 1u : 0u;
+      n_eval += fy[k] < kLiveBound || stop ? 1u : 0u;
       n_used += use ? 1u : 0u;
     }
-    const float wu = use ? w : 0.0f;
-    cr[k] = fmaf(r.r, wu, cr[k]);
-    cg[k] = fmaf(r.g, wu, cg[k]);
-    cb[k] = fmaf(r.b, wu, cb[k]);
-    T[k] = use ? Tn : T[k];
-    fy[k] = stop ? kDeadRow : fy[k];
+    cr[k] = fmaf(r.r, w, cr[k]);
+    cg[k] = fmaf(r.g, w, cg[k]);
+    cb[k] = fmaf(r.b, w, cb[k]);
+    T[k] = Tn;
     last[k] = use ? pos : last[k];
   }
   return groups;

@@ -124,6 +124,27 @@ def test_forward_backward_parity(tile, W, H):
         assert e <= GRAD_TOL, name
 
 
+def test_tile_launch_order_is_longest_list_first():
+    """The compositing launch order (last quarter of workspace region 21) is a permutation of the
+    tiles whose list lengths, in steps of 8 entries, never increase; equal steps keep tile order."""
+    api = _api()
+    gs, cams = _scene(4000, 17, 2, 150, 90, log_scale=-2.6)
+    P = to_dev(gs)
+    rp = api.plan_batch(cams, [0, gs.n], tile=8, pair_capacity=1 << 20)
+    out = api.render_fwd(rp, P)
+    torch.cuda.synchronize()
+    assert int(out.status[0]) == 0
+    nt = int(rp.plan.n_tiles)
+    off = int(rp.plan.region_offset[21])
+    order = rp.ws[off:off + 16 * nt].view(torch.int32).cpu().numpy()[3 * nt:]
+    assert np.array_equal(np.sort(order), np.arange(nt))
+    ranges = rp.region("ranges", torch.int32).cpu().numpy().reshape(-1, 2)
+    step = np.minimum((ranges[:, 1] - ranges[:, 0]) >> 3, 255)[order]
+    assert np.all(np.diff(step) <= 0) and step[0] > step[-1]
+    for k in np.unique(step):
+        assert np.all(np.diff(order[step == k]) > 0)
+
+
 def test_empty_and_fully_culled_views():
     api = _api()
     gs, cams = _scene(50, 5, 1, 40, 30)
