@@ -7,6 +7,7 @@
 // any implementation following the same order.
 #include <hip/hip_runtime.h>
 
+#include "block_scan.h"
 #include "common.h"
 
 #pragma clang fp contract(off)
@@ -76,10 +77,12 @@ __device__ __forceinline__ bool tile_reached(float mx, float my, float A, float 
   const float dx0 = X0 - mx, dx1 = X1 - mx, dy0 = Y0 - my, dy1 = Y1 - my;
   if (dx0 <= 0.0f && dx1 >= 0.0f && dy0 <= 0.0f && dy1 >= 0.0f) return true;
   const float B2 = 2.0f * B;
-  const float ya = fminf(fmaxf(dx0 * nBC, dy0), dy1);
-  const float yb = fminf(fmaxf(dx1 * nBC, dy0), dy1);
-  const float xa = fminf(fmaxf(dy0 * nBA, dx0), dx1);
-  const float xb = fminf(fmaxf(dy1 * nBA, dx0), dx1);
+  // Clamps to [d0, d1] with d0 <= d1 (the centres span at least one pixel): for finite values the
+  // median of three is min(max(v, d0), d1), in one instruction.
+  const float ya = __builtin_amdgcn_fmed3f(dx0 * nBC, dy0, dy1);
+  const float yb = __builtin_amdgcn_fmed3f(dx1 * nBC, dy0, dy1);
+  const float xa = __builtin_amdgcn_fmed3f(dy0 * nBA, dx0, dx1);
+  const float xb = __builtin_amdgcn_fmed3f(dy1 * nBA, dx0, dx1);
   const float q = fminf(fminf(quad_form(A, B2, C, dx0, ya), quad_form(A, B2, C, dx1, yb)),
                         fminf(quad_form(A, B2, C, xa, dy0), quad_form(A, B2, C, xb, dy1)));
   return q <= tau;
@@ -182,65 +185,63 @@ __device__ __forceinline__ ProjResult project_one(const DevView& v, int tile, fl
 }
 
 // grid: x over Gaussians of the view's scene, y over views.  Writes the per-item records and the
-// visibility flag consumed by the compaction scan.
+// visibility flag consumed by the compaction scan.  Each thread projects one item; the reached tiles
+// are then counted block-wide so that the footprint tests do not diverge with the rectangle sizes:
+// the tiles of all rectangles of at most 32 tiles are numbered consecutively (a block prefix sum of
+// their areas, an LDS map from test number to item) and shared round-robin by the block's threads,
+// which set the reached bits of the items' row-major masks; larger rectangles are tested by whole
+// waves, 64 tiles per round.
 __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ views, int tile, vbm_gaussians_c g,
                                                  float* __restrict__ depth, uint32_t* __restrict__ rect,
                                                  uint32_t* __restrict__ ntiles, float4* __restrict__ rec,
                                                  float4* __restrict__ coef, float* __restrict__ blue,
                                                  uint32_t* __restrict__ vis_flag, uint32_t* __restrict__ reach_mask,
                                                  int64_t n_items) {
-  // Large rectangles of the block, counted by whole waves after the per-thread pass.
-  __shared__ float s_par[8][256];   // mean2d.xy, conic A B C, tau, nBA, nBC
-  __shared__ uint32_t s_rect[2][256];
-  __shared__ uint32_t s_item[256];
+  __shared__ float s_par[8][256];      // per thread: mean2d.xy, conic A B C, tau, nBA, nBC
+  __shared__ uint32_t s_org[256];      // rectangle origin x0 | y0 << 16
+  __shared__ uint32_t s_w[256];        // rectangle width
+  __shared__ uint32_t s_h[256];        // rectangle height
+  __shared__ float s_invw[256];        // 1 / width
+  __shared__ uint32_t s_start[256];    // first test number of a small rectangle
+  __shared__ uint32_t s_mask[256];     // reached-tile mask of a small rectangle
+  __shared__ uint8_t s_map[256 * kSmallRect];   // test number -> thread of its rectangle
+  __shared__ uint32_t s_q[256];        // threads with a large rectangle
   __shared__ uint32_t s_n;
   if (threadIdx.x == 0) s_n = 0;
+  s_mask[threadIdx.x] = 0u;
   __syncthreads();
   const DevView& v = views[blockIdx.y];
   const int i = blockIdx.x * 256 + threadIdx.x;
+  const int64_t item = v.item_offset + i;
+  uint32_t small_area = 0;
+  bool deferred = false;
   if (i < v.n_gauss) {
     const int64_t gi = v.gauss_offset + i;
-    const int64_t item = v.item_offset + i;
     const int64_t S = g.stride;
     const float op = g.opacity[gi];
     const ProjResult p = project_one(v, tile, g.means[gi], g.means[S + gi], g.means[2 * S + gi], g.scales[gi],
                                      g.scales[S + gi], g.scales[2 * S + gi], g.quats[gi], g.quats[S + gi],
                                      g.quats[2 * S + gi], g.quats[3 * S + gi], op);
-    // Reached tiles of the rectangle; for rectangles of at most 32 tiles their row-major bit mask
-    // is kept so that emission does not evaluate the footprint test again.
-    uint32_t nt = 0, mask = 0;
-    bool deferred = false;
     if (p.visible) {
-      const float tau = footprint_tau(op);
-      const float nBA = -__fdiv_rn(p.cb, p.ca), nBC = -__fdiv_rn(p.cb, p.cc);
-      if ((p.x1 - p.x0) * (p.y1 - p.y0) <= kSmallRect) {
-        uint32_t bit = 0;
-        for (uint32_t ty = p.y0; ty < p.y1; ++ty)
-          for (uint32_t tx = p.x0; tx < p.x1; ++tx, ++bit) {
-            const bool hit = tile_reached(p.px, p.py, p.ca, p.cb, p.cc, nBA, nBC, tau, static_cast<int>(tx),
-                                          static_cast<int>(ty), tile, v.width, v.height);
-            nt += hit ? 1u : 0u;
-            mask |= hit ? (1u << bit) : 0u;
-          }
+      const float par[8] = {p.px, p.py, p.ca, p.cb, p.cc, footprint_tau(op), -__fdiv_rn(p.cb, p.ca),
+                            -__fdiv_rn(p.cb, p.cc)};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s_par[k][threadIdx.x] = par[k];
+      s_org[threadIdx.x] = p.x0 | (p.y0 << 16);
+      s_w[threadIdx.x] = p.x1 - p.x0;
+      s_h[threadIdx.x] = p.y1 - p.y0;
+      s_invw[threadIdx.x] = 1.0f / static_cast<float>(p.x1 - p.x0);
+      const uint32_t area = (p.x1 - p.x0) * (p.y1 - p.y0);
+      if (area <= kSmallRect) {
+        small_area = area;
       } else {
         deferred = true;
-        const uint32_t d = atomicAdd(&s_n, 1u);
-        const float par[8] = {p.px, p.py, p.ca, p.cb, p.cc, tau, nBA, nBC};
-#pragma unroll
-        for (int k = 0; k < 8; ++k) s_par[k][d] = par[k];
-        s_rect[0][d] = p.x0 | (p.x1 << 16);
-        s_rect[1][d] = p.y0 | (p.y1 << 16);
-        s_item[d] = static_cast<uint32_t>(item);
+        s_q[atomicAdd(&s_n, 1u)] = threadIdx.x;
       }
     }
-    reach_mask[item] = mask;
     depth[item] = p.visible ? p.depth : 0.0f;
     rect[item] = p.x0 | (p.x1 << 16);
     rect[n_items + item] = p.y0 | (p.y1 << 16);
-    if (!deferred) {
-      ntiles[item] = nt;
-      vis_flag[item] = nt ? 1u : 0u;
-    }
     rec[2 * item] = make_float4(p.px, p.py, p.ca, p.cb);
     rec[2 * item + 1] = make_float4(p.cc, op, g.rgb[gi], g.rgb[S + gi]);
     // Compositing record: the exponent in base 2 with log2(opacity) folded in,
@@ -251,27 +252,56 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
         make_float4((-0.5f * kLog2e) * p.cc, p.visible ? __log2f(op) : 0.0f, g.rgb[gi], g.rgb[S + gi]);
     blue[item] = g.rgb[2 * S + gi];
   }
+  uint32_t n_tests;
+  const uint32_t start = block_excl_scan(small_area, &n_tests);
+  s_start[threadIdx.x] = start;
+  for (uint32_t k = 0; k < small_area; ++k) s_map[start + k] = static_cast<uint8_t>(threadIdx.x);
   __syncthreads();
+  for (uint32_t t = threadIdx.x; t < n_tests; t += 256) {
+    const uint32_t o = s_map[t];
+    const uint32_t k = t - s_start[o];
+    uint32_t tx, ty;
+    rect_tile(k, s_w[o], s_invw[o], tx, ty);
+    const uint32_t org = s_org[o];
+    if (tile_reached(s_par[0][o], s_par[1][o], s_par[2][o], s_par[3][o], s_par[4][o], s_par[6][o], s_par[7][o],
+                     s_par[5][o], static_cast<int>((org & 0xFFFFu) + tx), static_cast<int>((org >> 16) + ty), tile,
+                     v.width, v.height))
+      atomicOr(&s_mask[o], 1u << k);
+  }
+  __syncthreads();
+  if (i < v.n_gauss) {
+    // small or invisible rectangles here, large ones below
+    const uint32_t mask = small_area ? s_mask[threadIdx.x] : 0u;
+    reach_mask[item] = mask;
+    if (!deferred) {
+      const uint32_t nt = static_cast<uint32_t>(__popc(mask));
+      ntiles[item] = nt;
+      vis_flag[item] = nt ? 1u : 0u;
+    }
+  }
   const uint32_t n_def = s_n;
   const int lane = static_cast<int>(threadIdx.x) & 63;
   for (uint32_t d = threadIdx.x >> 6; d < n_def; d += 4) {
-    const uint32_t x0 = s_rect[0][d] & 0xFFFFu, x1 = s_rect[0][d] >> 16;
-    const uint32_t y0 = s_rect[1][d] & 0xFFFFu, y1 = s_rect[1][d] >> 16;
-    const uint32_t w = x1 - x0, area = w * (y1 - y0);
-    const float inv_w = 1.0f / static_cast<float>(w);
+    const uint32_t o = s_q[d];
+    const uint32_t org = s_org[o];
+    const uint32_t x0 = org & 0xFFFFu, y0 = org >> 16;
+    const int64_t it = v.item_offset + static_cast<int64_t>(blockIdx.x) * 256 + o;
+    const uint32_t w = s_w[o];
+    const uint32_t area = w * s_h[o];
+    const float inv_w = s_invw[o];
     uint32_t nt = 0;
     for (uint32_t t0 = 0; t0 < area; t0 += 64) {
       const uint32_t t = t0 + static_cast<uint32_t>(lane);
       uint32_t tx, ty;
       rect_tile(t, w, inv_w, tx, ty);
-      const bool hit = t < area && tile_reached(s_par[0][d], s_par[1][d], s_par[2][d], s_par[3][d], s_par[4][d],
-                                                s_par[6][d], s_par[7][d], s_par[5][d], static_cast<int>(x0 + tx),
+      const bool hit = t < area && tile_reached(s_par[0][o], s_par[1][o], s_par[2][o], s_par[3][o], s_par[4][o],
+                                                s_par[6][o], s_par[7][o], s_par[5][o], static_cast<int>(x0 + tx),
                                                 static_cast<int>(y0 + ty), tile, v.width, v.height);
       nt += static_cast<uint32_t>(__popcll(__ballot(hit)));
     }
     if (lane == 0) {
-      ntiles[s_item[d]] = nt;
-      vis_flag[s_item[d]] = nt ? 1u : 0u;
+      ntiles[it] = nt;
+      vis_flag[it] = nt ? 1u : 0u;
     }
   }
 }
