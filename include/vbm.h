@@ -157,6 +157,49 @@ vbm_status vbm_build_gaussians(const float* coeffs, int32_t G, int32_t J, const 
                                size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------------------------
+ * vbm_adaptive_select -- adaptive per-subband selection (Supp. A: global budget allocation
+ * across subbands, joint multi-channel sparsification, robust MAD-based thresholding, top-K
+ * selection under sparsity constraints).  For every subband of the packed layout (the LLL block
+ * and the seven detail blocks of each level, 7J+1 subbands):
+ *   E = sum_k A_{j,o,k,ref}^2 (float64), N = #k, S = E^alpha N^beta,
+ *   K_{j,o} = max(min_band, floor(K_tot S / sum S))        (sum S = 0 gives 0)
+ *   v = sqrt(((R^2 + G^2) + B^2) + A^2) in float32 (the vbm_build_gaussians key)
+ *   MAD = median |v - median(v)|, medians of an even count = (a + b) * 0.5 (float32),
+ *   sigma = MAD / 0.6745, T = lambda sigma (float32)
+ *   K = min(K_{j,o}, #(v >= T)); keep v >= max(T, v_(K)) (all ties with v_(K); none if K = 0)
+ * The kept packed indices are written in ascending order to kept_index[0 .. capacity) (device,
+ * int64) and their total to *count_dev (device, int64); a total above capacity means the list was
+ * cut at capacity.  band_stats (device, optional) receives VBM_ADAPTIVE_STATS doubles per subband:
+ * E, N, K_tot S / sum S, K_{j,o}, median, MAD, sigma, T, #(v >= T), K, v_(K), kept count.
+ * The total can exceed K_tot when the per-band minimum applies.  Enqueues only (no host sync).
+ * Errors: VBM_ERR_INVALID for bad G/J, K_tot outside 1..G^3, negative alpha/beta/lambda,
+ * ref_channel outside 0..3, null pointers; VBM_ERR_WORKSPACE if ws_bytes is too small.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+  int64_t K_tot;       /* global budget */
+  double alpha, beta;  /* S = E^alpha N^beta */
+  float lambda;        /* T = lambda sigma */
+  int32_t ref_channel; /* 0..3 (R, G, B, A); the supplement's typical choice is A */
+  int64_t min_band;    /* per-subband minimum budget (10 in the supplement) */
+} vbm_adaptive_opts;
+
+#define VBM_ADAPTIVE_STATS 12
+size_t vbm_adaptive_workspace_size(int32_t G, int32_t J);
+vbm_status vbm_adaptive_select(const float* coeffs, int32_t G, int32_t J, const vbm_adaptive_opts* opts_host,
+                               int64_t capacity, int64_t* kept_index, int64_t* count_dev, double* band_stats,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------------------------
+ * vbm_construct_gaussians -- the construction of vbm_build_gaussians (Sec. 4.3) for a given list
+ * of n packed indices (device, int64), one Gaussian per entry in list order; an entry outside
+ * [0, G^3) leaves its output slot untouched.  Enqueues only.  Errors: VBM_ERR_INVALID for bad G/J, n < 0, out.stride < n, null pointers or
+ * bad opts.
+ * ------------------------------------------------------------------------------------------ */
+vbm_status vbm_construct_gaussians(const float* coeffs, int32_t G, int32_t J, const float* bank_dev,
+                                   const int64_t* kept_index, int64_t n, const vbm_build_opts* opts_host,
+                                   vbm_gaussians out, void* stream);
+
+/* ------------------------------------------------------------------------------------------
  * Rendering batches.  A batch renders n_views views; view v shows scene `scene` of a
  * concatenated Gaussian set whose scene s occupies Gaussians [scene_offsets[s], scene_offsets[s+1]).
  * Pinhole camera, OpenCV axes (x right, y down, z forward); viewmat is world->camera [R|t],

@@ -42,6 +42,15 @@ class vbm_build_opts(C.Structure):
                 ("opacity_max", C.c_float)]
 
 
+class vbm_adaptive_opts(C.Structure):
+    _fields_ = [("K_tot", C.c_int64), ("alpha", C.c_double), ("beta", C.c_double), ("lam", C.c_float),
+                ("ref_channel", C.c_int32), ("min_band", C.c_int64)]
+
+
+VBM_ADAPTIVE_STATS = 12
+ADAPTIVE_STATS = ("E", "N", "quotient", "K_band", "median", "mad", "sigma", "T", "C", "K", "vK", "kept")
+
+
 class vbm_view(C.Structure):
     _fields_ = [("scene", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("pad", C.c_int32),
                 ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
@@ -79,6 +88,11 @@ _SIGS = {
     "vbm_build_gaussians": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64,
                                         C.POINTER(vbm_build_opts), vbm_gaussians, C.c_void_p, C.c_void_p,
                                         C.c_size_t, C.c_void_p]),
+    "vbm_adaptive_workspace_size": (C.c_size_t, [C.c_int32, C.c_int32]),
+    "vbm_adaptive_select": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(vbm_adaptive_opts), C.c_int64,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "vbm_construct_gaussians": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
+                                            C.POINTER(vbm_build_opts), vbm_gaussians, C.c_void_p]),
     "vbm_plan_make": (C.c_int32, [C.POINTER(vbm_view), C.c_int32, C.POINTER(C.c_int64), C.c_int32,
                                   C.POINTER(vbm_schedule), C.POINTER(vbm_plan), C.c_void_p]),
     "vbm_render_fwd": (C.c_int32, [C.POINTER(vbm_plan), C.c_void_p, vbm_gaussians_c, C.c_void_p, C.c_void_p,

@@ -108,6 +108,48 @@ def build_gaussians(coeffs: torch.Tensor, G: int, J: int, bank_packed, K: int, s
     return P, kept
 
 
+def adaptive_select(coeffs: torch.Tensor, G: int, J: int, K_tot: int, alpha: float = 1.0, beta: float = 0.0,
+                    lam: float = 3.0, ref: int = 3, min_band: int = 10, capacity: int | None = None):
+    """Adaptive per-subband selection.  Returns (kept int64 [count] ascending packed indices,
+    band statistics float64 [7J+1][12] with columns L.ADAPTIVE_STATS).  One host sync reads the count;
+    a count above the capacity (default: G^3) raises."""
+    lib = L.load()
+    _require_cuda(coeffs)
+    dev = coeffs.device
+    cap = G ** 3 if capacity is None else int(capacity)
+    kept = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    stats = torch.zeros(7 * J + 1, L.VBM_ADAPTIVE_STATS, dtype=torch.float64, device=dev)
+    ws = torch.empty(lib.vbm_adaptive_workspace_size(G, J), dtype=torch.uint8, device=dev)
+    opts = L.vbm_adaptive_opts(int(K_tot), float(alpha), float(beta), float(lam), int(ref), int(min_band))
+    st = lib.vbm_adaptive_select(coeffs.data_ptr(), G, J, C.byref(opts), cap, kept.data_ptr(), count.data_ptr(),
+                                 stats.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev))
+    L.check(st, "vbm_adaptive_select")
+    n = int(count.item())
+    if n > cap:
+        raise L.VBMError(f"vbm_adaptive_select kept {n} > capacity {cap}")
+    return kept[:n], stats
+
+
+def construct_gaussians(coeffs: torch.Tensor, G: int, J: int, bank_packed, kept: torch.Tensor, s_mode: str = "paper",
+                        delta: float = 0.5, opacity_min: float = 1e-3, opacity_max: float = 0.99,
+                        stride: int | None = None):
+    """Construction for a given list of packed indices (int64, device).  Returns P [14, stride]."""
+    lib = L.load()
+    _require_cuda(coeffs)
+    dev = coeffs.device
+    n = int(kept.numel())
+    kept = kept.to(device=dev, dtype=torch.int64).contiguous()
+    bank = torch.as_tensor(np.ascontiguousarray(bank_packed, dtype=np.float32)).to(dev)
+    stride = stride or max(n, 1)
+    P = torch.zeros(N_ROWS, stride, dtype=torch.float32, device=dev)
+    opts = L.vbm_build_opts(0 if s_mode == "paper" else 1, delta, opacity_min, opacity_max)
+    st = lib.vbm_construct_gaussians(coeffs.data_ptr(), G, J, bank.data_ptr(), kept.data_ptr(), n, C.byref(opts),
+                                     gaussians_struct(P), _stream(dev))
+    L.check(st, "vbm_construct_gaussians")
+    return P
+
+
 # ----------------------------------------------------------------------------- rendering
 
 def make_view(cam, scene: int = 0) -> L.vbm_view:

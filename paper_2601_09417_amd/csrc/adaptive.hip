@@ -1,0 +1,451 @@
+// vbm_adaptive_select: adaptive per-subband coefficient selection (Supp. A: global budget
+// allocation across subbands, joint multi-channel sparsification, robust MAD-based thresholding,
+// top-K selection under sparsity constraints).
+//
+// Every subband of the packed layout (the LLL block, then the seven detail blocks of each level
+// from the coarsest) is cut into chunks of 4096 coefficients that never straddle a subband; one
+// block per chunk.  The order statistics (the two medians and the K-th largest joint norm) come
+// from four-pass 8-bit radix selects on float32 bit patterns (non-negative floats order like their
+// bits), run for all subbands at once with per-subband histograms; the two middle ranks of a median
+// are selected side by side.  Every keep/drop decision uses float32 values computed in a fixed
+// order; energies and budgets are float64.  Nothing is read back to the host.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "block_scan.h"
+#include "common.h"
+
+namespace vbm {
+namespace {
+
+constexpr int kT = 256;
+constexpr int kChunk = 4096;
+constexpr int kPer = kChunk / kT;
+constexpr int kMaxBands = 7 * 10 + 1;
+
+struct BandTable {
+  int32_t nb;
+  int64_t off[kMaxBands];
+  int64_t n[kMaxBands];
+  int64_t chunk0[kMaxBands + 1];   // first chunk of each subband; chunk0[nb] = number of chunks
+};
+
+struct BandState {
+  uint32_t prefix[2];   // key bits fixed so far, per select target
+  uint32_t rank[2];     // ascending 0-based rank still to find inside the prefix's bucket
+  double E, quotient;   // reference energy, K_tot S / sum S
+  int64_t K_band;       // max(min_band, floor(quotient))
+  float med, mad, sigma, T, vK, thr;
+  uint32_t C, K;        // #(v >= T), min(K_band, C)
+};
+
+__device__ __forceinline__ int band_of(const BandTable& bt, int64_t chunk) {
+  int b = 0;
+  while (b + 1 < bt.nb && chunk >= bt.chunk0[b + 1]) ++b;
+  return b;
+}
+
+// [begin, end) of chunk `chunk` inside subband b.
+__device__ __forceinline__ void chunk_range(const BandTable& bt, int b, int64_t chunk, int64_t& begin, int64_t& end) {
+  begin = bt.off[b] + (chunk - bt.chunk0[b]) * kChunk;
+  end = min(begin + kChunk, bt.off[b] + bt.n[b]);
+}
+
+__device__ __forceinline__ double block_sum_f64(double v, double* s_red) {
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  if (lane_id() == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < kT / 64; ++w) t += s_red[w];
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* s_red) {
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  if (lane_id() == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint32_t t = 0;
+  for (int w = 0; w < kT / 64; ++w) t += s_red[w];
+  __syncthreads();
+  return t;
+}
+
+#pragma clang fp contract(off)
+// Joint norm sqrt(((R^2 + G^2) + B^2) + A^2) in float32 (the order of the top-K key) as its bit
+// pattern, and the chunk's reference-channel energy in float64 (fixed summation order).
+__global__ __launch_bounds__(kT) void k_af_norm(const float* __restrict__ coeffs, int64_t M, BandTable bt, int ref,
+                                               uint32_t* __restrict__ keys, double* __restrict__ epart) {
+  __shared__ double s_red[kT / 64];
+  const int b = band_of(bt, blockIdx.x);
+  int64_t begin, end;
+  chunk_range(bt, b, blockIdx.x, begin, end);
+  double e = 0.0;
+  for (int r = 0; r < kPer; ++r) {
+    const int64_t i = begin + r * kT + threadIdx.x;
+    if (i < end) {
+      const float cr = coeffs[i], cg = coeffs[M + i], cb = coeffs[2 * M + i], ca = coeffs[3 * M + i];
+      keys[i] = __float_as_uint(sqrt_rn_f32(((cr * cr + cg * cg) + cb * cb) + ca * ca));
+      const double x = static_cast<double>(coeffs[static_cast<int64_t>(ref) * M + i]);
+      e += x * x;
+    }
+  }
+  e = block_sum_f64(e, s_red);
+  if (threadIdx.x == 0) epart[blockIdx.x] = e;
+}
+
+// E per subband (one block per subband, fixed order).
+__global__ __launch_bounds__(kT) void k_af_energy(BandTable bt, const double* __restrict__ epart,
+                                                 BandState* __restrict__ st) {
+  __shared__ double s_red[kT / 64];
+  const int b = blockIdx.x;
+  double e = 0.0;
+  for (int64_t c = bt.chunk0[b] + threadIdx.x; c < bt.chunk0[b + 1]; c += kT) e += epart[c];
+  e = block_sum_f64(e, s_red);
+  if (threadIdx.x == 0) st[b].E = e;
+}
+
+// Budgets K_{j,o} = max(min_band, floor(K_tot S / sum S)), S = E^alpha N^beta, and the first
+// select: the two middle ranks of each subband's joint norms.
+__global__ void k_af_budget(BandTable bt, BandState* __restrict__ st, int64_t K_tot, double alpha, double beta,
+                            int64_t min_band) {
+  __shared__ double s_S[kMaxBands];
+  __shared__ double s_tot;
+  const int b = threadIdx.x;
+  if (b < bt.nb) s_S[b] = pow(st[b].E, alpha) * pow(static_cast<double>(bt.n[b]), beta);
+  __syncthreads();
+  if (b == 0) {
+    double t = 0.0;
+    for (int k = 0; k < bt.nb; ++k) t += s_S[k];
+    s_tot = t;
+  }
+  __syncthreads();
+  if (b < bt.nb) {
+    const double q = s_tot == 0.0 ? 0.0 : static_cast<double>(K_tot) * s_S[b] / s_tot;
+    const double f = floor(q);
+    st[b].quotient = q;
+    st[b].K_band = f > static_cast<double>(min_band) ? static_cast<int64_t>(f) : min_band;
+    st[b].prefix[0] = st[b].prefix[1] = 0u;
+    st[b].rank[0] = static_cast<uint32_t>((bt.n[b] - 1) / 2);
+    st[b].rank[1] = static_cast<uint32_t>(bt.n[b] / 2);
+  }
+}
+
+// Key of a coefficient for a select: the joint norm (mode 0) or its distance to the subband's
+// median (mode 1), both non-negative float32 bit patterns.
+__device__ __forceinline__ uint32_t select_key(uint32_t v, int mode, float med) {
+  return mode == 0 ? v : __float_as_uint(fabsf(__uint_as_float(v) - med));
+}
+
+// Histogram of digit `shift` over the keys whose higher digits match each target's prefix.
+__global__ __launch_bounds__(kT) void k_af_hist(const uint32_t* __restrict__ keys, BandTable bt,
+                                               const BandState* __restrict__ st, int mode, int shift,
+                                               uint32_t* __restrict__ ghist) {
+  __shared__ uint32_t h[2][256];
+  const int b = band_of(bt, blockIdx.x);
+  int64_t begin, end;
+  chunk_range(bt, b, blockIdx.x, begin, end);
+  h[0][threadIdx.x] = 0;
+  h[1][threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t hi_mask = shift >= 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
+  const uint32_t p0 = st[b].prefix[0] & hi_mask, p1 = st[b].prefix[1] & hi_mask;
+  const bool same = p0 == p1;   // both targets in one bucket: one histogram serves both
+  const float med = st[b].med;
+  for (int r = 0; r < kPer; ++r) {
+    const int64_t i = begin + r * kT + threadIdx.x;
+    if (i >= end) break;
+    const uint32_t k = select_key(keys[i], mode, med);
+    const uint32_t d = (k >> shift) & 255u;
+    if ((k & hi_mask) == p0) atomicAdd(&h[0][d], 1u);
+    else if (!same && (k & hi_mask) == p1) atomicAdd(&h[1][d], 1u);
+  }
+  __syncthreads();
+  const uint32_t c0 = h[0][threadIdx.x], c1 = same ? c0 : h[1][threadIdx.x];
+  uint32_t* g = ghist + static_cast<int64_t>(b) * 512;
+  if (c0) atomicAdd(&g[threadIdx.x], c0);
+  if (c1) atomicAdd(&g[256 + threadIdx.x], c1);
+}
+
+// Picks, per subband and target, the digit whose bucket holds the target rank; clears the
+// histograms for the next pass.
+__global__ __launch_bounds__(kT) void k_af_pick(BandState* __restrict__ st, uint32_t* __restrict__ ghist, int shift) {
+  const int b = blockIdx.x, d = threadIdx.x;
+  uint32_t* g = ghist + static_cast<int64_t>(b) * 512;
+  const uint32_t h0 = g[d], h1 = g[256 + d];
+  uint32_t tot;
+  const uint32_t below0 = block_excl_scan(h0, &tot);
+  const uint32_t below1 = block_excl_scan(h1, &tot);
+  const uint32_t r0 = st[b].rank[0], r1 = st[b].rank[1];
+  __syncthreads();
+  if (below0 <= r0 && r0 < below0 + h0) {
+    st[b].prefix[0] |= static_cast<uint32_t>(d) << shift;
+    st[b].rank[0] = r0 - below0;
+  }
+  if (below1 <= r1 && r1 < below1 + h1) {
+    st[b].prefix[1] |= static_cast<uint32_t>(d) << shift;
+    st[b].rank[1] = r1 - below1;
+  }
+  g[d] = 0;
+  g[256 + d] = 0;
+}
+
+__device__ __forceinline__ float mid_mean(const BandState& s) {
+  return (__uint_as_float(s.prefix[0]) + __uint_as_float(s.prefix[1])) * 0.5f;
+}
+
+// Median of the joint norms; the next select (the same two ranks) runs on |v - median|.
+__global__ void k_af_median(BandTable bt, BandState* __restrict__ st) {
+  const int b = threadIdx.x;
+  if (b >= bt.nb) return;
+  st[b].med = mid_mean(st[b]);
+  st[b].prefix[0] = st[b].prefix[1] = 0u;
+  st[b].rank[0] = static_cast<uint32_t>((bt.n[b] - 1) / 2);
+  st[b].rank[1] = static_cast<uint32_t>(bt.n[b] / 2);
+}
+
+// MAD, sigma = MAD / 0.6745 and the threshold T = lambda sigma (float32).
+__global__ void k_af_thresh(BandTable bt, BandState* __restrict__ st, float lambda) {
+  const int b = threadIdx.x;
+  if (b >= bt.nb) return;
+  const float mad = mid_mean(st[b]);
+  const float sigma = __fdiv_rn(mad, 0.6745f);
+  st[b].mad = mad;
+  st[b].sigma = sigma;
+  st[b].T = lambda * sigma;
+  st[b].C = 0u;
+}
+
+// C = #(v >= T) per subband.
+__global__ __launch_bounds__(kT) void k_af_count(const uint32_t* __restrict__ keys, BandTable bt,
+                                                BandState* __restrict__ st) {
+  __shared__ uint32_t s_red[kT / 64];
+  const int b = band_of(bt, blockIdx.x);
+  int64_t begin, end;
+  chunk_range(bt, b, blockIdx.x, begin, end);
+  const float T = st[b].T;
+  uint32_t c = 0;
+  for (int r = 0; r < kPer; ++r) {
+    const int64_t i = begin + r * kT + threadIdx.x;
+    if (i < end && __uint_as_float(keys[i]) >= T) ++c;
+  }
+  c = block_sum_u32(c, s_red);
+  if (threadIdx.x == 0 && c) atomicAdd(&st[b].C, c);
+}
+
+// K = min(K_band, C); the last select finds the K-th largest joint norm (ascending rank N - K).
+__global__ void k_af_kinit(BandTable bt, BandState* __restrict__ st) {
+  const int b = threadIdx.x;
+  if (b >= bt.nb) return;
+  const int64_t K = st[b].K_band < static_cast<int64_t>(st[b].C) ? st[b].K_band : static_cast<int64_t>(st[b].C);
+  st[b].K = static_cast<uint32_t>(K);
+  st[b].prefix[0] = st[b].prefix[1] = 0u;
+  const uint32_t r = K >= 1 ? static_cast<uint32_t>(bt.n[b] - K) : 0u;
+  st[b].rank[0] = st[b].rank[1] = r;
+}
+
+// Keep threshold max(T, v_(K)), or +inf when K = 0.
+__global__ void k_af_thr(BandTable bt, BandState* __restrict__ st) {
+  const int b = threadIdx.x;
+  if (b >= bt.nb) return;
+  const float vK = __uint_as_float(st[b].prefix[0]);
+  st[b].vK = st[b].K >= 1 ? vK : __builtin_inff();
+  st[b].thr = st[b].K >= 1 ? fmaxf(st[b].T, vK) : __builtin_inff();
+}
+
+// Kept coefficients per chunk.  Each thread owns 16 consecutive coefficients, so the block's scan
+// of its counts numbers the kept ones in ascending index order.
+__global__ __launch_bounds__(kT) void k_af_flags(const uint32_t* __restrict__ keys, BandTable bt,
+                                                const BandState* __restrict__ st, uint32_t* __restrict__ cnt) {
+  __shared__ uint32_t s_red[kT / 64];
+  const int b = band_of(bt, blockIdx.x);
+  int64_t begin, end;
+  chunk_range(bt, b, blockIdx.x, begin, end);
+  const float thr = st[b].thr;
+  uint32_t c = 0;
+  for (int r = 0; r < kPer; ++r) {
+    const int64_t i = begin + static_cast<int64_t>(threadIdx.x) * kPer + r;
+    if (i < end && __uint_as_float(keys[i]) >= thr) ++c;
+  }
+  c = block_sum_u32(c, s_red);
+  if (threadIdx.x == 0) cnt[blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(kT) void k_af_write(const uint32_t* __restrict__ keys, BandTable bt,
+                                                const BandState* __restrict__ st, const uint32_t* __restrict__ offs,
+                                                int64_t capacity, int64_t* __restrict__ kept) {
+  const int b = band_of(bt, blockIdx.x);
+  int64_t begin, end;
+  chunk_range(bt, b, blockIdx.x, begin, end);
+  const float thr = st[b].thr;
+  uint32_t f = 0;
+  for (int r = 0; r < kPer; ++r) {
+    const int64_t i = begin + static_cast<int64_t>(threadIdx.x) * kPer + r;
+    if (i < end && __uint_as_float(keys[i]) >= thr) f |= 1u << r;
+  }
+  uint32_t tot;
+  int64_t pos = static_cast<int64_t>(offs[blockIdx.x]) + block_excl_scan(static_cast<uint32_t>(__popc(f)), &tot);
+  for (int r = 0; r < kPer; ++r) {
+    if (!((f >> r) & 1u)) continue;
+    if (pos < capacity) kept[pos] = begin + static_cast<int64_t>(threadIdx.x) * kPer + r;
+    ++pos;
+  }
+}
+
+// Kept count and the per-subband statistics.
+__global__ void k_af_final(BandTable bt, const BandState* __restrict__ st, const uint32_t* __restrict__ cnt,
+                           const uint32_t* __restrict__ total, int64_t* __restrict__ count_dev,
+                           double* __restrict__ stats) {
+  const int b = threadIdx.x;
+  if (b == 0) count_dev[0] = static_cast<int64_t>(total[0]);
+  if (b >= bt.nb || !stats) return;
+  uint64_t kept = 0;
+  for (int64_t c = bt.chunk0[b]; c < bt.chunk0[b + 1]; ++c) kept += cnt[c];
+  const BandState& s = st[b];
+  double* o = stats + static_cast<int64_t>(b) * VBM_ADAPTIVE_STATS;
+  o[0] = s.E;
+  o[1] = static_cast<double>(bt.n[b]);
+  o[2] = s.quotient;
+  o[3] = static_cast<double>(s.K_band);
+  o[4] = s.med;
+  o[5] = s.mad;
+  o[6] = s.sigma;
+  o[7] = s.T;
+  o[8] = s.C;
+  o[9] = s.K;
+  o[10] = s.vK;
+  o[11] = static_cast<double>(kept);
+}
+
+bool make_table(int G, int J, BandTable* bt) {
+  if (7 * J + 1 > kMaxBands) return false;
+  bt->nb = 7 * J + 1;
+  int64_t off = 0, chunk = 0;
+  for (int b = 0; b < bt->nb; ++b) {
+    const int j = b == 0 ? J : J - (b - 1) / 7;
+    const int64_t side = G >> j;
+    bt->off[b] = off;
+    bt->n[b] = side * side * side;
+    bt->chunk0[b] = chunk;
+    off += bt->n[b];
+    chunk += ceil_div(bt->n[b], kChunk);
+  }
+  bt->chunk0[bt->nb] = chunk;
+  return off == static_cast<int64_t>(G) * G * G;
+}
+
+struct AdaptiveWs {
+  uint32_t* keys;
+  double* epart;
+  uint32_t* cnt;
+  uint32_t* offs;
+  uint32_t* total;
+  BandState* st;
+  uint32_t* ghist;
+  void* scan;
+};
+
+AdaptiveWs carve(Carver& c, int64_t M, int64_t chunks) {
+  AdaptiveWs w;
+  w.keys = c.take<uint32_t>(M);
+  w.epart = c.take<double>(chunks);
+  w.cnt = c.take<uint32_t>(chunks);
+  w.offs = c.take<uint32_t>(chunks);
+  w.total = c.take<uint32_t>(1);
+  w.st = c.take<BandState>(kMaxBands);
+  w.ghist = c.take<uint32_t>(static_cast<size_t>(kMaxBands) * 512);
+  w.scan = c.take<char>(scan_scratch_bytes(chunks));
+  return w;
+}
+
+bool grid_ok(int G, int J) { return G >= 2 && G <= 1024 && J >= 1 && J <= 10 && (G % (1 << J)) == 0 && (G >> J) >= 2; }
+
+}  // namespace
+}  // namespace vbm
+
+using namespace vbm;
+
+extern "C" size_t vbm_adaptive_workspace_size(int32_t G, int32_t J) {
+  BandTable bt;
+  if (!grid_ok(G, J) || !make_table(G, J, &bt)) return 0;
+  Carver c(nullptr);
+  carve(c, static_cast<int64_t>(G) * G * G, bt.chunk0[bt.nb]);
+  return align_up(c.off, 256);
+}
+
+extern "C" vbm_status vbm_adaptive_select(const float* coeffs, int32_t G, int32_t J, const vbm_adaptive_opts* opts,
+                                          int64_t capacity, int64_t* kept_index, int64_t* count_dev,
+                                          double* band_stats, void* ws, size_t ws_bytes, void* stream) {
+  if (!coeffs || !opts || !kept_index || !count_dev || !ws) {
+    set_error("vbm_adaptive_select: null pointer");
+    return VBM_ERR_INVALID;
+  }
+  BandTable bt;
+  if (!grid_ok(G, J) || !make_table(G, J, &bt)) {
+    set_error("vbm_adaptive_select: bad G=%d J=%d", G, J);
+    return VBM_ERR_INVALID;
+  }
+  const int64_t M = static_cast<int64_t>(G) * G * G;
+  if (opts->K_tot < 1 || opts->K_tot > M || opts->min_band < 0 || opts->min_band > M ||
+      !(opts->lambda >= 0.0f) || !std::isfinite(opts->lambda) || !(opts->alpha >= 0.0) || !(opts->beta >= 0.0) ||
+      !std::isfinite(opts->alpha) || !std::isfinite(opts->beta) || opts->ref_channel < 0 || opts->ref_channel > 3) {
+    set_error("vbm_adaptive_select: need 1 <= K_tot <= G^3, 0 <= min_band <= G^3, finite lambda, alpha, "
+              "beta >= 0 and ref_channel in 0..3");
+    return VBM_ERR_INVALID;
+  }
+  if (capacity < 0) {
+    set_error("vbm_adaptive_select: negative capacity");
+    return VBM_ERR_INVALID;
+  }
+  if (ws_bytes < vbm_adaptive_workspace_size(G, J)) {
+    set_error("vbm_adaptive_select: workspace %zu < %zu", ws_bytes, vbm_adaptive_workspace_size(G, J));
+    return VBM_ERR_WORKSPACE;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t chunks = bt.chunk0[bt.nb];
+  Carver c(ws);
+  const AdaptiveWs w = carve(c, M, chunks);
+  const dim3 cg(static_cast<unsigned>(chunks)), blk(kT), nbg(static_cast<unsigned>(bt.nb));
+
+  hipLaunchKernelGGL(k_af_norm, cg, blk, 0, s, coeffs, M, bt, opts->ref_channel, w.keys, w.epart);
+  VBM_LAUNCH_CHECK("adaptive_norm");
+  VBM_TRY(fill_u32(w.ghist, 0u, static_cast<int64_t>(kMaxBands) * 512, s));
+  hipLaunchKernelGGL(k_af_energy, nbg, blk, 0, s, bt, w.epart, w.st);
+  VBM_LAUNCH_CHECK("adaptive_energy");
+  hipLaunchKernelGGL(k_af_budget, dim3(1), dim3(128), 0, s, bt, w.st, opts->K_tot, opts->alpha, opts->beta,
+                     static_cast<int64_t>(opts->min_band));
+  VBM_LAUNCH_CHECK("adaptive_budget");
+  // three radix selects: median(v), median(|v - median|), then the K-th largest v
+  for (int sel = 0; sel < 3; ++sel) {
+    const int mode = sel == 1 ? 1 : 0;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+      hipLaunchKernelGGL(k_af_hist, cg, blk, 0, s, w.keys, bt, w.st, mode, shift, w.ghist);
+      VBM_LAUNCH_CHECK("adaptive_hist");
+      hipLaunchKernelGGL(k_af_pick, nbg, blk, 0, s, w.st, w.ghist, shift);
+      VBM_LAUNCH_CHECK("adaptive_pick");
+    }
+    if (sel == 0) {
+      hipLaunchKernelGGL(k_af_median, dim3(1), dim3(128), 0, s, bt, w.st);
+      VBM_LAUNCH_CHECK("adaptive_median");
+    } else if (sel == 1) {
+      hipLaunchKernelGGL(k_af_thresh, dim3(1), dim3(128), 0, s, bt, w.st, opts->lambda);
+      VBM_LAUNCH_CHECK("adaptive_thresh");
+      hipLaunchKernelGGL(k_af_count, cg, blk, 0, s, w.keys, bt, w.st);
+      VBM_LAUNCH_CHECK("adaptive_count");
+      hipLaunchKernelGGL(k_af_kinit, dim3(1), dim3(128), 0, s, bt, w.st);
+      VBM_LAUNCH_CHECK("adaptive_kinit");
+    } else {
+      hipLaunchKernelGGL(k_af_thr, dim3(1), dim3(128), 0, s, bt, w.st);
+      VBM_LAUNCH_CHECK("adaptive_thr");
+    }
+  }
+  hipLaunchKernelGGL(k_af_flags, cg, blk, 0, s, w.keys, bt, w.st, w.cnt);
+  VBM_LAUNCH_CHECK("adaptive_flags");
+  VBM_TRY(scan_exclusive_u32(w.cnt, w.offs, chunks, nullptr, w.total, w.scan, s));
+  hipLaunchKernelGGL(k_af_write, cg, blk, 0, s, w.keys, bt, w.st, w.offs, capacity, kept_index);
+  VBM_LAUNCH_CHECK("adaptive_write");
+  hipLaunchKernelGGL(k_af_final, dim3(1), dim3(128), 0, s, bt, w.st, w.cnt, w.total, count_dev, band_stats);
+  VBM_LAUNCH_CHECK("adaptive_final");
+  return VBM_OK;
+}

@@ -75,6 +75,15 @@ __device__ __forceinline__ uint32_t popc_below(uint64_t mask) {
                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
 }
 
+// ------------------------------------------------------------------ arithmetic
+// Correctly rounded float32 square root: the square root of the value in float64, rounded to
+// float32.  Rounding twice cannot go wrong here because 53 >= 2 * 24 + 2 (the float64 result,
+// even one unit off in its last place, never crosses a float32 rounding boundary); the float32
+// square-root instruction alone is only accurate to one unit in the last place.
+__device__ __forceinline__ float sqrt_rn_f32(float x) {
+  return static_cast<float>(__dsqrt_rn(static_cast<double>(x)));
+}
+
 // ------------------------------------------------------------------ scan / sort primitives (scan_sort.hip)
 // Exclusive prefix sum of n u32 values (n read from *n_dev when non-null, else n_max), with the
 // total written to *total_dev.  Scratch from scan_scratch_bytes(n_max).

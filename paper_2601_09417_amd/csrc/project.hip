@@ -24,7 +24,7 @@ struct ProjResult {
 
 __device__ __forceinline__ void rot_from_quat(float qw, float qx, float qy, float qz, float Rq[3][3], float qn[4]) {
   const float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
-  const float nq = __fsqrt_rn(n2);
+  const float nq = sqrt_rn_f32(n2);
   const float w = __fdiv_rn(qw, nq), x = __fdiv_rn(qx, nq), y = __fdiv_rn(qy, nq), z = __fdiv_rn(qz, nq);
   qn[0] = w;
   qn[1] = x;
@@ -50,11 +50,11 @@ __device__ __forceinline__ void rot_from_quat(float qw, float qx, float qy, floa
 // the float32 evaluation error of the compositing kernels; a Gaussian with o < 1/255 reaches nothing.
 __device__ __forceinline__ float footprint_tau(float o) {
   float y = 255.0f * o;
-  y = __fsqrt_rn(y);
-  y = __fsqrt_rn(y);
-  y = __fsqrt_rn(y);
-  y = __fsqrt_rn(y);
-  y = __fsqrt_rn(y);
+  y = sqrt_rn_f32(y);
+  y = sqrt_rn_f32(y);
+  y = sqrt_rn_f32(y);
+  y = sqrt_rn_f32(y);
+  y = sqrt_rn_f32(y);
   const float u = 32.0f * (y - 1.0f);
   return (2.0f * u) * 1.01f + 0.01f;
 }
@@ -159,8 +159,8 @@ __device__ __forceinline__ ProjResult project_one(const DevView& v, int tile, fl
   vis = vis && det > 0.0f;
   const float mid = 0.5f * (a + c);
   const float disc = fmaxf(0.1f, mid * mid - det);
-  const float lam = mid + __fsqrt_rn(disc);
-  const float r = ceilf(3.0f * __fsqrt_rn(lam));
+  const float lam = mid + sqrt_rn_f32(disc);
+  const float r = ceilf(3.0f * sqrt_rn_f32(lam));
   const float px = v.fx * txz + v.cx;
   const float py = v.fy * tyz + v.cy;
   // the tile edge is a power of two, so multiplying by its reciprocal is the exact quotient
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
                                                  float* __restrict__ depth, uint32_t* __restrict__ rect,
                                                  uint32_t* __restrict__ ntiles, float4* __restrict__ rec,
                                                  float4* __restrict__ coef, float* __restrict__ blue,
-                                                 uint32_t* __restrict__ vis_flag, uint32_t* __restrict__ reach_mask,
+                                                 uint32_t* __restrict__ vis_flag, uint4* __restrict__ bin,
                                                  int64_t n_items) {
   __shared__ float s_par[8][256];      // per thread: mean2d.xy, conic A B C, tau, nBA, nBC
   __shared__ uint32_t s_org[256];      // rectangle origin x0 | y0 << 16
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
   const DevView& v = views[blockIdx.y];
   const int i = blockIdx.x * 256 + threadIdx.x;
   const int64_t item = v.item_offset + i;
-  uint32_t small_area = 0;
+  uint32_t small_area = 0, rx = 0, ry = 0;
   bool deferred = false;
   if (i < v.n_gauss) {
     const int64_t gi = v.gauss_offset + i;
@@ -240,8 +240,10 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
       }
     }
     depth[item] = p.visible ? p.depth : 0.0f;
-    rect[item] = p.x0 | (p.x1 << 16);
-    rect[n_items + item] = p.y0 | (p.y1 << 16);
+    rx = p.x0 | (p.x1 << 16);
+    ry = p.y0 | (p.y1 << 16);
+    rect[item] = rx;
+    rect[n_items + item] = ry;
     rec[2 * item] = make_float4(p.px, p.py, p.ca, p.cb);
     rec[2 * item + 1] = make_float4(p.cc, op, g.rgb[gi], g.rgb[S + gi]);
     // Compositing record: the exponent in base 2 with log2(opacity) folded in,
@@ -270,11 +272,11 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
   }
   __syncthreads();
   if (i < v.n_gauss) {
-    // small or invisible rectangles here, large ones below
+    // small or invisible rectangles here; a large one gets its tile count below
     const uint32_t mask = small_area ? s_mask[threadIdx.x] : 0u;
-    reach_mask[item] = mask;
+    const uint32_t nt = static_cast<uint32_t>(__popc(mask));
+    bin[item] = make_uint4(rx, ry, mask, nt);
     if (!deferred) {
-      const uint32_t nt = static_cast<uint32_t>(__popc(mask));
       ntiles[item] = nt;
       vis_flag[item] = nt ? 1u : 0u;
     }
@@ -302,6 +304,7 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
     if (lane == 0) {
       ntiles[it] = nt;
       vis_flag[it] = nt ? 1u : 0u;
+      bin[it].w = nt;
     }
   }
 }
@@ -338,10 +341,10 @@ __global__ __launch_bounds__(256) void k_gather_ntiles(const uint32_t* __restric
 // positions from the ballot of reached tiles).
 __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views, const uint64_t* __restrict__ keys,
                                               const uint32_t* __restrict__ vals, const uint32_t* __restrict__ offs,
-                                              const uint32_t* __restrict__ rect, const float4* __restrict__ rec,
-                                              int tile, int64_t n_items, uint32_t* __restrict__ counters,
-                                              int64_t n_max, int64_t capacity, uint32_t* __restrict__ pair_tile,
-                                              uint32_t* __restrict__ pair_item, const uint32_t* __restrict__ reach_mask) {
+                                              const uint4* __restrict__ bin, const float4* __restrict__ rec,
+                                              int tile, uint32_t* __restrict__ counters, int64_t n_max,
+                                              int64_t capacity, uint32_t* __restrict__ pair_tile,
+                                              uint32_t* __restrict__ pair_item) {
   __shared__ uint32_t s_q[256];
   __shared__ uint32_t s_n;
   const int64_t n = min(static_cast<int64_t>(counters[0]), n_max);
@@ -353,15 +356,15 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
     if (p < n) {
       const uint32_t item = vals[p];
       const DevView& v = views[keys[p] >> 32];
-      const uint32_t rx = rect[item], ry = rect[n_items + item];
-      const uint32_t x0 = rx & 0xFFFFu, x1 = rx >> 16, y0 = ry & 0xFFFFu, y1 = ry >> 16;
+      const uint4 b = bin[item];
+      const uint32_t x0 = b.x & 0xFFFFu, x1 = b.x >> 16, y0 = b.y & 0xFFFFu, y1 = b.y >> 16;
       const uint32_t w = x1 - x0;
       if (w * (y1 - y0) <= kSmallRect) {
         // The mask lists the reached tiles in row-major order; it is walked row by row (w bits per
         // row), which needs no integer division.
         int64_t o = offs[p];
         bool over = false;
-        uint32_t m = reach_mask[item];
+        uint32_t m = b.z;
         const uint32_t row_mask = w >= 32 ? 0xFFFFFFFFu : (1u << w) - 1u;
         uint32_t t_row = static_cast<uint32_t>(v.tile_offset) + y0 * static_cast<uint32_t>(v.tiles_x) + x0;
         for (; m; m >>= w, t_row += static_cast<uint32_t>(v.tiles_x)) {
@@ -387,8 +390,8 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
       const int64_t q = base + s_q[d];
       const uint32_t item = vals[q];
       const DevView& v = views[keys[q] >> 32];
-      const uint32_t rx = rect[item], ry = rect[n_items + item];
-      const uint32_t x0 = rx & 0xFFFFu, x1 = rx >> 16, y0 = ry & 0xFFFFu, y1 = ry >> 16;
+      const uint4 b = bin[item];
+      const uint32_t x0 = b.x & 0xFFFFu, x1 = b.x >> 16, y0 = b.y & 0xFFFFu, y1 = b.y >> 16;
       const uint32_t w = x1 - x0, area = w * (y1 - y0);
       const float inv_w = 1.0f / static_cast<float>(w);
       const float4 ra = rec[2 * static_cast<int64_t>(item)];

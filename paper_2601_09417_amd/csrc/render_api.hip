@@ -19,13 +19,12 @@
 namespace vbm {
 
 __global__ void k_project(const DevView*, int, vbm_gaussians_c, float*, uint32_t*, uint32_t*, float4*, float4*,
-                          float*, uint32_t*, uint32_t*, int64_t);
+                          float*, uint32_t*, uint4*, int64_t);
 __global__ void k_compact_visible(const DevView*, const uint32_t*, const float*, const uint32_t*, uint64_t*,
                                   uint32_t*);
 __global__ void k_gather_ntiles(const uint32_t*, const uint32_t*, const uint32_t*, int64_t, uint32_t*);
-__global__ void k_emit(const DevView*, const uint64_t*, const uint32_t*, const uint32_t*, const uint32_t*,
-                       const float4*, int, int64_t, uint32_t*, int64_t, int64_t, uint32_t*, uint32_t*,
-                       const uint32_t*);
+__global__ void k_emit(const DevView*, const uint64_t*, const uint32_t*, const uint32_t*, const uint4*,
+                       const float4*, int, uint32_t*, int64_t, int64_t, uint32_t*, uint32_t*);
 __global__ void k_ranges(const uint32_t*, const uint32_t*, int64_t, uint2*);
 __global__ void k_status(const uint32_t*, int32_t*);
 __global__ void k_tile_keys(const uint2*, int64_t, uint32_t*, uint32_t*);
@@ -66,7 +65,7 @@ enum Region {
   R_SCRATCH = 17,
   R_VISFLAG = 18,
   R_COEF = VBM_REGION_ITEM_COEF,
-  R_MASK = 20,
+  R_BIN = 20,      // uint4 [n_items]: x0 | x1 << 16, y0 | y1 << 16, reached-tile mask, tile count
   R_TORDER = 21,   // uint32 [4][n_tiles]: sort keys, tiles, and the sorted keys and tiles (the launch order)
   R_COUNT = 22
 };
@@ -109,7 +108,7 @@ void layout(vbm_plan* p) {
   sz[R_SCRATCH] = scr;
   sz[R_VISFLAG] = I * 4;
   sz[R_COEF] = I * 32;
-  sz[R_MASK] = I * 4;
+  sz[R_BIN] = I * 16;
   sz[R_TORDER] = 4 * NT * 4;
   size_t off = 0;
   for (int r = 0; r < VBM_WS_REGIONS; ++r) {
@@ -329,7 +328,7 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
   const int gx = static_cast<int>(ceil_div(p->n_gaussians > 0 ? p->n_gaussians : 1, 256));
   if (I > 0) {
     hipLaunchKernelGGL(k_project, dim3(gx, p->n_views), dim3(256), 0, s, views, p->tile, g, depth, rect, ntiles, rec,
-                       coef, blue, visflag, region<uint32_t>(p, ws, R_MASK), I);
+                       coef, blue, visflag, region<uint4>(p, ws, R_BIN), I);
     VBM_LAUNCH_CHECK("project");
     VBM_TRY(scan_exclusive_u32(visflag, visflag, I, nullptr, &counters[0], scratch, s));
     const int view_bits = ceil_log2(p->n_views);
@@ -361,8 +360,8 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
   const int tile_passes = static_cast<int>(ceil_div(p->tile_key_bits, p->sort_bits));
   const int pfirst = tile_passes % 2;
   if (I > 0 && emit_grid_n > 0) {
-    hipLaunchKernelGGL(k_emit, dim3(grid_cap(emit_grid_n, 16384)), dim3(256), 0, s, views, vk[0], vv[0], poffs, rect,
-                       rec, p->tile, I, counters, I, cap, pt[pfirst], pi[pfirst], region<uint32_t>(p, ws, R_MASK));
+    hipLaunchKernelGGL(k_emit, dim3(grid_cap(emit_grid_n, 16384)), dim3(256), 0, s, views, vk[0], vv[0], poffs,
+                       region<uint4>(p, ws, R_BIN), rec, p->tile, counters, I, cap, pt[pfirst], pi[pfirst]);
     VBM_LAUNCH_CHECK("emit");
   }
   if (pair_n > 0) {

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(kT) void k_joint_keys(const float* __restrict__ coe
        i += static_cast<int64_t>(gridDim.x) * kT) {
     const float r = coeffs[i], g = coeffs[M + i], b = coeffs[2 * M + i], a = coeffs[3 * M + i];
     const float s = ((r * r + g * g) + b * b) + a * a;
-    keys[i] = __float_as_uint(__fsqrt_rn(s));
+    keys[i] = __float_as_uint(sqrt_rn_f32(s));
   }
 }
 
@@ -155,12 +155,14 @@ struct BuildParams {
   int64_t M;
 };
 
-__global__ __launch_bounds__(kT) void k_build(const float* __restrict__ coeffs, const uint32_t* __restrict__ kept,
+template <class I>
+__global__ __launch_bounds__(kT) void k_build(const float* __restrict__ coeffs, const I* __restrict__ kept,
                                              int64_t K, const float* __restrict__ bank, BuildParams p,
                                              vbm_gaussians out, int64_t* __restrict__ kept_out) {
   const int64_t n = static_cast<int64_t>(blockIdx.x) * kT + threadIdx.x;
   if (n >= K) return;
-  const uint32_t idx = kept[n];
+  const int64_t idx = static_cast<int64_t>(kept[n]);
+  if (idx < 0 || idx >= p.M) return;   // a caller-given index outside the grid builds nothing
   // decode the packed index: [LLL_J][level J: o=1..7]...[level 1: o=1..7]
   int j = p.J, b = 0;
   int64_t off = idx;
@@ -296,7 +298,45 @@ extern "C" vbm_status vbm_build_gaussians(const float* coeffs, int32_t G, int32_
   p.op_max = opts->opacity_max;
   p.s_mode = opts->s_mode;
   p.M = M;
-  hipLaunchKernelGGL(k_build, dim3(ceil_div(K, kT)), dim3(kT), 0, s, coeffs, kept, K, bank_dev, p, out, kept_index);
+  hipLaunchKernelGGL(k_build<uint32_t>, dim3(ceil_div(K, kT)), dim3(kT), 0, s, coeffs, kept, K, bank_dev, p, out,
+                     kept_index);
   VBM_LAUNCH_CHECK("build");
+  return VBM_OK;
+}
+
+extern "C" vbm_status vbm_construct_gaussians(const float* coeffs, int32_t G, int32_t J, const float* bank_dev,
+                                              const int64_t* kept_index, int64_t n, const vbm_build_opts* opts,
+                                              vbm_gaussians out, void* stream) {
+  if (!coeffs || !bank_dev || !opts || (n > 0 && !kept_index) || !out.means || !out.scales || !out.quats ||
+      !out.opacity || !out.rgb) {
+    set_error("vbm_construct_gaussians: null pointer");
+    return VBM_ERR_INVALID;
+  }
+  if (G < 2 || G > 1024 || J < 1 || J > 10 || (G % (1 << J)) != 0 || (G >> J) < 2) {
+    set_error("vbm_construct_gaussians: bad G=%d J=%d", G, J);
+    return VBM_ERR_INVALID;
+  }
+  if (n < 0 || out.stride < n) {
+    set_error("vbm_construct_gaussians: need 0 <= n <= out.stride");
+    return VBM_ERR_INVALID;
+  }
+  if ((opts->s_mode != 0 && opts->s_mode != 1) ||
+      !(opts->opacity_min >= 0.0f && opts->opacity_min <= opts->opacity_max && opts->opacity_max <= 1.0f)) {
+    set_error("vbm_construct_gaussians: bad opts");
+    return VBM_ERR_INVALID;
+  }
+  if (n == 0) return VBM_OK;
+  BuildParams p;
+  p.G = G;
+  p.J = J;
+  p.h = 2.0f / static_cast<float>(G);
+  p.delta = opts->delta;
+  p.op_min = opts->opacity_min;
+  p.op_max = opts->opacity_max;
+  p.s_mode = opts->s_mode;
+  p.M = static_cast<int64_t>(G) * G * G;
+  hipLaunchKernelGGL(k_build<int64_t>, dim3(ceil_div(n, kT)), dim3(kT), 0, static_cast<hipStream_t>(stream), coeffs,
+                     kept_index, n, bank_dev, p, out, static_cast<int64_t*>(nullptr));
+  VBM_LAUNCH_CHECK("construct");
   return VBM_OK;
 }

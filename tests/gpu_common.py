@@ -53,3 +53,26 @@ def masked_dL(cams, flagged_list, seed=0):
 
 def flat(arrs) -> torch.Tensor:
     return torch.from_numpy(np.concatenate([np.asarray(a, np.float32).reshape(-1) for a in arrs])).to(dev())
+
+
+def adaptive_check(coeffs_np, G, J, kept_gpu, stats_gpu, K_tot, **kw):
+    """Stage-isolated parity of one vbm_adaptive_select result with the oracle (see test_gpu_adaptive)."""
+    from oracle import adaptive as A
+    from paper_2601_09417_amd import _lib as L
+    S = {name: stats_gpu[:, i] for i, name in enumerate(L.ADAPTIVE_STATS)}
+    budgets = S["K_band"].astype(np.int64)
+    kept_o, so = A.select(coeffs_np, G, J, K_tot, band_budgets=budgets, **kw)
+    E = np.array([s["E"] for s in so])
+    q = A.budget_quotients(E, np.array([s["N"] for s in so]), K_tot, kw.get("alpha", 1.0), kw.get("beta", 0.0))
+    assert np.allclose(S["E"], E, rtol=1e-12, atol=0.0)
+    assert np.allclose(S["quotient"], q, rtol=1e-11, atol=1e-300)
+    own = A.budgets(E, np.array([s["N"] for s in so]), K_tot, kw.get("alpha", 1.0), kw.get("beta", 0.0),
+                    kw.get("min_band", 10))
+    near = np.abs(q - np.round(q)) <= 1e-9 * np.maximum(1.0, q)
+    assert np.array_equal(budgets[~near], own[~near])
+    for b, s in enumerate(so):
+        for name in ("median", "mad", "sigma", "T", "vK"):
+            assert np.float32(S[name][b]) == s[name], (b, name, S[name][b], s[name])
+        assert int(S["C"][b]) == s["C"] and int(S["K"][b]) == s["K"] and int(S["kept"][b]) == s["kept"], b
+    assert np.array_equal(kept_gpu, kept_o)
+    return kept_o, so

@@ -6,7 +6,8 @@ configuration bench.py times).  Checked against the oracle:
 
 * DWT: sampled coefficients of every level as inner products of the transfer-functioned volume with
   three 1D analysis rows (the oracle's own analysis step applied to an identity matrix);
-* selection: the complete top-K set, stage-isolated on the GPU's float32 coefficients (bit-exact);
+* selection: the complete top-K set, stage-isolated on the GPU's float32 coefficients (bit-exact),
+  and the adaptive per-subband selection with all its statistics against the oracle;
 * construction: a random sample of the kept Gaussians against the oracle's bank and construction;
 * rendering: two views' pair lists (bit-exact) and the images of sampled tiles; for the backward,
   dL/dI is nonzero only on those tiles, so the oracle's autodiff over the same tiles gives every
@@ -24,7 +25,7 @@ from oracle import dwt as odwt
 from oracle import select as oselect
 from oracle import tf as otf
 from oracle import wavelets
-from tests.gpu_common import GRAD_TOL, IMG_TOL, ITEM_MASK, ROWS, dev, group_error, say
+from tests.gpu_common import GRAD_TOL, IMG_TOL, ITEM_MASK, ROWS, adaptive_check, dev, group_error, say
 
 pytestmark = pytest.mark.gpu
 
@@ -94,6 +95,16 @@ def test_fullsize_selection_and_construction(h_case):
         r = ref[name].reshape(rows.stop - rows.start, -1)
         err = np.abs(Pn[rows] - r).max() / max(np.abs(r).max(), 1e-6)
         assert err <= 1e-6, (name, err)
+
+
+def test_fullsize_adaptive_selection(h_case):
+    """The adaptive per-subband selection on the full coefficient set (26 subbands, 134M locations)
+    against the oracle on the same float32 coefficients, budget 1M."""
+    api = h_case["api"]
+    kept, stats = api.adaptive_select(h_case["coeffs"], G, J, K)
+    kept_o, so = adaptive_check(h_case["coeffs"].cpu().numpy(), G, J, kept.cpu().numpy(), stats.cpu().numpy(), K)
+    say(f"  adaptive: kept {kept_o.size} (budget {K}), T of the finest subbands "
+        f"{[round(float(s['T']), 5) for s in so[-7:]]}")
 
 
 def _gaussian_set(P: torch.Tensor) -> vi.GaussianSet:

@@ -39,12 +39,16 @@ def test_projection_and_pair_lists_bit_exact(tile):
     depth = rp.region("item_depth", torch.float32).cpu().numpy()
     rect = rp.region("item_rect", torch.int32).cpu().numpy().view(np.uint32)
     ntl = rp.region("item_ntiles", torch.int32).cpu().numpy()
+    rec = rp.region("item_rec", torch.float32).cpu().numpy().reshape(-1, 8)
     I = int(rp.plan.n_items)
     for v in range(3):
         pr = ref["proj"][v]
         sl = slice(v * gs.n, (v + 1) * gs.n)
         vis = pr["n_tiles"] > 0
         assert np.array_equal(ntl[sl], pr["n_tiles"])
+        # the float32 spec values themselves (quaternion norm, divisions, square roots in one order)
+        for col, val in ((0, pr["px"]), (1, pr["py"]), (2, pr["conic"][0]), (3, pr["conic"][1]), (4, pr["conic"][2])):
+            assert np.array_equal(rec[sl][vis, col].view(np.uint32), np.asarray(val, np.float32)[vis].view(np.uint32))
         assert np.array_equal(depth[sl][vis].view(np.uint32), pr["depth"][vis].view(np.uint32))
         assert np.array_equal(rect[sl][vis] & 0xFFFF, pr["x0"][vis])
         assert np.array_equal(rect[sl][vis] >> 16, pr["x1"][vis])
