@@ -41,6 +41,9 @@ FLOPS_FWD_EVAL, FLOPS_FWD_USED = 17, 8
 FLOPS_BWD_EVAL, FLOPS_BWD_USED = 17, 40
 BYTES_PER_PAIR_FWD, BYTES_PER_PIXEL_FWD = 40, 20   # algorithmic (the lane-group marks written back are not counted)
 BYTES_PER_PAIR_BWD, BYTES_PER_PIXEL_BWD = 76, 20
+# adaptive selection: 16 B read + 4 B key written, twelve select passes and three flag/count
+# passes over the 4-byte keys, per coefficient
+ADAPTIVE_BYTES_PER_COEF = 16 + 4 + 12 * 4 + 3 * 4
 
 WORKLOADS = {
     "H": dict(config=3, G=512, J=5, wavelet="bior4.4", K=1_000_000, views=8, W=1920, H=1080, tile=16,
@@ -195,7 +198,21 @@ def run_gpu(args, wl):
     P, _ = api.build_gaussians(coeffs, wl["G"], wl["J"], packed, wl["K"], s_mode="none")
     torch.cuda.synchronize()
     out["init_ms"] = (time.perf_counter() - t0) * 1e3
-    del coeffs
+    # the supplement's adaptive per-subband selection on the same coefficients (an alternative to the
+    # global top-K; once per scene): time of vbm_adaptive_select with HIP events, after one warm call
+    api.adaptive_select(coeffs, wl["G"], wl["J"], wl["K"])
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    reps = 3
+    ev[0].record()
+    for _ in range(reps):
+        kept_a, _ = api.adaptive_select(coeffs, wl["G"], wl["J"], wl["K"])
+    ev[1].record()
+    torch.cuda.synchronize()
+    ams = ev[0].elapsed_time(ev[1]) / reps
+    M = wl["G"] ** 3
+    out["adaptive_select"] = dict(ms=round(ams, 3), kept=int(kept_a.numel()), budget=wl["K"],
+                                  algorithmic_gbs=round(ADAPTIVE_BYTES_PER_COEF * M / (ams * 1e-3) / 1e9, 1))
+    del coeffs, kept_a
     targets = api.dvr_render(vol_d, (tfn.xs, tfn.rgba), cams)
     torch.cuda.synchronize()
     log(f"init {out['init_ms']:.1f} ms; targets ready")
@@ -360,6 +377,7 @@ def main() -> int:
         "batched_over_plain": None if plain is None else round(value / plain, 3),
         "pairs_per_step": gpu["pairs_per_step"],
         "init_ms": round(gpu["init_ms"], 2),
+        "adaptive_select": gpu.get("adaptive_select"),
         "kernels_ms": {n: round(d["ms"], 3) for n, d in gpu["kernels"].items()},
         "composite_evals": {n: [int(d["evals"]), int(d["contrib"])] for n, d in gpu["kernels"].items()},
         "roofline": {

@@ -11,8 +11,10 @@ For each subband (j, o) of the packed layout (the LLL block is one subband like 
   keep k  <=>  v(k) >= max(T, v_(K))                                      (none when K = 0)
 
 Readings where the supplement is silent or loose (each one also in the design notes):
-  * alpha, beta and lambda are not given: parameters, defaults alpha = 1, beta = 0 (budget in
-    proportion to the reference energy) and lambda = 3 (a three-sigma noise floor);
+  * alpha, beta and lambda are not given: parameters, defaults alpha = beta = 1/2 (S = sqrt(E N),
+    N times the subband's RMS reference amplitude: with alpha = 1, beta = 0 the LLL block, which
+    holds most of the energy in few locations, would absorb nearly the whole budget) and lambda = 3
+    (a three-sigma noise floor);
   * c_ref is the opacity channel (index 3), the supplement's typical choice;
   * the median of an even count is the mean of the two middle order statistics;
   * v, |v - median|, the medians, sigma and T are float32, evaluated in a fixed order, so that both
@@ -30,7 +32,7 @@ import numpy as np
 from .dwt import block_offsets
 from .select import joint_norm_f32
 
-DEFAULTS = dict(alpha=1.0, beta=0.0, lam=3.0, ref=3, min_band=10)
+DEFAULTS = dict(alpha=0.5, beta=0.5, lam=3.0, ref=3, min_band=10)
 _HALF = np.float32(0.5)
 _MAD_TO_SIGMA = np.float32(0.6745)
 

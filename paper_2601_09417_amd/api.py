@@ -108,7 +108,7 @@ def build_gaussians(coeffs: torch.Tensor, G: int, J: int, bank_packed, K: int, s
     return P, kept
 
 
-def adaptive_select(coeffs: torch.Tensor, G: int, J: int, K_tot: int, alpha: float = 1.0, beta: float = 0.0,
+def adaptive_select(coeffs: torch.Tensor, G: int, J: int, K_tot: int, alpha: float = 0.5, beta: float = 0.5,
                     lam: float = 3.0, ref: int = 3, min_band: int = 10, capacity: int | None = None):
     """Adaptive per-subband selection.  Returns (kept int64 [count] ascending packed indices,
     band statistics float64 [7J+1][12] with columns L.ADAPTIVE_STATS).  One host sync reads the count;

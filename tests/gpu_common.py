@@ -63,11 +63,11 @@ def adaptive_check(coeffs_np, G, J, kept_gpu, stats_gpu, K_tot, **kw):
     budgets = S["K_band"].astype(np.int64)
     kept_o, so = A.select(coeffs_np, G, J, K_tot, band_budgets=budgets, **kw)
     E = np.array([s["E"] for s in so])
-    q = A.budget_quotients(E, np.array([s["N"] for s in so]), K_tot, kw.get("alpha", 1.0), kw.get("beta", 0.0))
+    alpha, beta = kw.get("alpha", A.DEFAULTS["alpha"]), kw.get("beta", A.DEFAULTS["beta"])
+    q = A.budget_quotients(E, np.array([s["N"] for s in so]), K_tot, alpha, beta)
     assert np.allclose(S["E"], E, rtol=1e-12, atol=0.0)
     assert np.allclose(S["quotient"], q, rtol=1e-11, atol=1e-300)
-    own = A.budgets(E, np.array([s["N"] for s in so]), K_tot, kw.get("alpha", 1.0), kw.get("beta", 0.0),
-                    kw.get("min_band", 10))
+    own = A.budgets(E, np.array([s["N"] for s in so]), K_tot, alpha, beta, kw.get("min_band", A.DEFAULTS["min_band"]))
     near = np.abs(q - np.round(q)) <= 1e-9 * np.maximum(1.0, q)
     assert np.array_equal(budgets[~near], own[~near])
     for b, s in enumerate(so):

@@ -33,6 +33,7 @@ def _coeffs(G, J, wav, seed):
 
 @pytest.mark.parametrize("G,J,wav,K_tot,params", [
     (32, 3, "bior4.4", 4000, dict()),
+    (32, 3, "bior4.4", 4000, dict(alpha=1.0, beta=0.0)),
     (32, 2, "haar", 2000, dict(alpha=0.5, beta=0.5, lam=1.5)),
     (48, 3, "bior4.4", 30000, dict(alpha=0.0, beta=1.0, lam=0.0)),
     (32, 3, "haar", 50, dict(lam=2.0)),            # the per-band minimum fires: total above K_tot
