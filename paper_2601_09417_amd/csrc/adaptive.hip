@@ -3,12 +3,13 @@
 // top-K selection under sparsity constraints).
 //
 // Every subband of the packed layout (the LLL block, then the seven detail blocks of each level
-// from the coarsest) is cut into chunks of 4096 coefficients that never straddle a subband; one
+// from the coarsest) is cut into chunks of 16384 coefficients that never straddle a subband; one
 // block per chunk.  The order statistics (the two medians and the K-th largest joint norm) come
 // from four-pass 8-bit radix selects on float32 bit patterns (non-negative floats order like their
 // bits), run for all subbands at once with per-subband histograms; the two middle ranks of a median
 // are selected side by side.  Every keep/drop decision uses float32 values computed in a fixed
-// order; energies and budgets are float64.  Nothing is read back to the host.
+// order; energies and budgets are float64.  Per-subband counts are summed from per-chunk counts
+// (no same-address atomics across blocks).  Nothing is read back to the host.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -20,7 +21,7 @@ namespace vbm {
 namespace {
 
 constexpr int kT = 256;
-constexpr int kChunk = 4096;
+constexpr int kChunk = 16384;
 constexpr int kPer = kChunk / kT;
 constexpr int kMaxBands = 7 * 10 + 1;
 
@@ -38,6 +39,7 @@ struct BandState {
   int64_t K_band;       // max(min_band, floor(quotient))
   float med, mad, sigma, T, vK, thr;
   uint32_t C, K;        // #(v >= T), min(K_band, C)
+  uint32_t kept, pad;
 };
 
 __device__ __forceinline__ int band_of(const BandTable& bt, int64_t chunk) {
@@ -50,6 +52,17 @@ __device__ __forceinline__ int band_of(const BandTable& bt, int64_t chunk) {
 __device__ __forceinline__ void chunk_range(const BandTable& bt, int b, int64_t chunk, int64_t& begin, int64_t& end) {
   begin = bt.off[b] + (chunk - bt.chunk0[b]) * kChunk;
   end = min(begin + kChunk, bt.off[b] + bt.n[b]);
+}
+
+// Keys begin + (r0 + q) * 256 + thread, q < 16, with indices past `end` clamped to end - 1 (a chunk is
+// never empty): the loads are unconditional so that all sixteen are in flight at once.
+__device__ __forceinline__ void load16(const uint32_t* __restrict__ keys, int64_t begin, int64_t end, int r0,
+                                       uint32_t (&k)[16]) {
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int64_t i = begin + static_cast<int64_t>(r0 + q) * kT + threadIdx.x;
+    k[q] = keys[i < end ? i : end - 1];
+  }
 }
 
 __device__ __forceinline__ double block_sum_f64(double v, double* s_red) {
@@ -82,12 +95,23 @@ __global__ __launch_bounds__(kT) void k_af_norm(const float* __restrict__ coeffs
   int64_t begin, end;
   chunk_range(bt, b, blockIdx.x, begin, end);
   double e = 0.0;
-  for (int r = 0; r < kPer; ++r) {
-    const int64_t i = begin + r * kT + threadIdx.x;
-    if (i < end) {
-      const float cr = coeffs[i], cg = coeffs[M + i], cb = coeffs[2 * M + i], ca = coeffs[3 * M + i];
+  for (int r0 = 0; r0 < kPer; r0 += 4) {
+    // four coefficients (sixteen loads) in flight; indices past the chunk are clamped and unused
+    float c[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = begin + static_cast<int64_t>(r0 + q) * kT + threadIdx.x;
+      const int64_t j = i < end ? i : end - 1;
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) c[q][ch] = coeffs[ch * M + j];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = begin + static_cast<int64_t>(r0 + q) * kT + threadIdx.x;
+      if (i >= end) continue;
+      const float cr = c[q][0], cg = c[q][1], cb = c[q][2], ca = c[q][3];
       keys[i] = __float_as_uint(sqrt_rn_f32(((cr * cr + cg * cg) + cb * cb) + ca * ca));
-      const double x = static_cast<double>(coeffs[static_cast<int64_t>(ref) * M + i]);
+      const double x = static_cast<double>(ref == 0 ? cr : ref == 1 ? cg : ref == 2 ? cb : ca);
       e += x * x;
     }
   }
@@ -142,27 +166,37 @@ __device__ __forceinline__ uint32_t select_key(uint32_t v, int mode, float med) 
 __global__ __launch_bounds__(kT) void k_af_hist(const uint32_t* __restrict__ keys, BandTable bt,
                                                const BandState* __restrict__ st, int mode, int shift,
                                                uint32_t* __restrict__ ghist) {
-  __shared__ uint32_t h[2][256];
+  __shared__ uint32_t h[kT / 64][2][256];   // one histogram pair per wave: less contention
   const int b = band_of(bt, blockIdx.x);
   int64_t begin, end;
   chunk_range(bt, b, blockIdx.x, begin, end);
-  h[0][threadIdx.x] = 0;
-  h[1][threadIdx.x] = 0;
+  for (int x = threadIdx.x; x < (kT / 64) * 512; x += kT) (&h[0][0][0])[x] = 0;
   __syncthreads();
+  const int w = threadIdx.x >> 6;
   const uint32_t hi_mask = shift >= 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
   const uint32_t p0 = st[b].prefix[0] & hi_mask, p1 = st[b].prefix[1] & hi_mask;
   const bool same = p0 == p1;   // both targets in one bucket: one histogram serves both
   const float med = st[b].med;
-  for (int r = 0; r < kPer; ++r) {
-    const int64_t i = begin + r * kT + threadIdx.x;
-    if (i >= end) break;
-    const uint32_t k = select_key(keys[i], mode, med);
-    const uint32_t d = (k >> shift) & 255u;
-    if ((k & hi_mask) == p0) atomicAdd(&h[0][d], 1u);
-    else if (!same && (k & hi_mask) == p1) atomicAdd(&h[1][d], 1u);
+  for (int r0 = 0; r0 < kPer; r0 += 16) {
+    uint32_t kk[16];
+    load16(keys, begin, end, r0, kk);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      if (begin + static_cast<int64_t>(r0 + q) * kT + threadIdx.x >= end) continue;
+      const uint32_t k = select_key(kk[q], mode, med);
+      const uint32_t d = (k >> shift) & 255u;
+      if ((k & hi_mask) == p0) atomicAdd(&h[w][0][d], 1u);
+      else if (!same && (k & hi_mask) == p1) atomicAdd(&h[w][1][d], 1u);
+    }
   }
   __syncthreads();
-  const uint32_t c0 = h[0][threadIdx.x], c1 = same ? c0 : h[1][threadIdx.x];
+  uint32_t c0 = 0, c1 = 0;
+#pragma unroll
+  for (int ww = 0; ww < kT / 64; ++ww) {
+    c0 += h[ww][0][threadIdx.x];
+    c1 += h[ww][1][threadIdx.x];
+  }
+  if (same) c1 = c0;
   uint32_t* g = ghist + static_cast<int64_t>(b) * 512;
   if (c0) atomicAdd(&g[threadIdx.x], c0);
   if (c1) atomicAdd(&g[256 + threadIdx.x], c1);
@@ -214,24 +248,41 @@ __global__ void k_af_thresh(BandTable bt, BandState* __restrict__ st, float lamb
   st[b].mad = mad;
   st[b].sigma = sigma;
   st[b].T = lambda * sigma;
-  st[b].C = 0u;
 }
 
-// C = #(v >= T) per subband.
+// #(v >= T) per chunk (summed per subband by k_af_band_sum).
 __global__ __launch_bounds__(kT) void k_af_count(const uint32_t* __restrict__ keys, BandTable bt,
-                                                BandState* __restrict__ st) {
+                                                const BandState* __restrict__ st, uint32_t* __restrict__ cnt) {
   __shared__ uint32_t s_red[kT / 64];
   const int b = band_of(bt, blockIdx.x);
   int64_t begin, end;
   chunk_range(bt, b, blockIdx.x, begin, end);
   const float T = st[b].T;
   uint32_t c = 0;
-  for (int r = 0; r < kPer; ++r) {
-    const int64_t i = begin + r * kT + threadIdx.x;
-    if (i < end && __uint_as_float(keys[i]) >= T) ++c;
+  for (int r0 = 0; r0 < kPer; r0 += 16) {
+    uint32_t kk[16];
+    load16(keys, begin, end, r0, kk);
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      c += begin + static_cast<int64_t>(r0 + q) * kT + threadIdx.x < end && __uint_as_float(kk[q]) >= T ? 1u : 0u;
   }
   c = block_sum_u32(c, s_red);
-  if (threadIdx.x == 0 && c) atomicAdd(&st[b].C, c);
+  if (threadIdx.x == 0) cnt[blockIdx.x] = c;
+}
+
+// Sum of the per-chunk counts of each subband (one block per subband) into C (which = 0) or the
+// kept count (which = 1).
+__global__ __launch_bounds__(kT) void k_af_band_sum(BandTable bt, const uint32_t* __restrict__ cnt, int which,
+                                                   BandState* __restrict__ st) {
+  __shared__ uint32_t s_red[kT / 64];
+  const int b = blockIdx.x;
+  uint32_t c = 0;
+  for (int64_t k = bt.chunk0[b] + threadIdx.x; k < bt.chunk0[b + 1]; k += kT) c += cnt[k];
+  c = block_sum_u32(c, s_red);
+  if (threadIdx.x == 0) {
+    if (which == 0) st[b].C = c;
+    else st[b].kept = c;
+  }
 }
 
 // K = min(K_band, C); the last select finds the K-th largest joint norm (ascending rank N - K).
@@ -254,8 +305,7 @@ __global__ void k_af_thr(BandTable bt, BandState* __restrict__ st) {
   st[b].thr = st[b].K >= 1 ? fmaxf(st[b].T, vK) : __builtin_inff();
 }
 
-// Kept coefficients per chunk.  Each thread owns 16 consecutive coefficients, so the block's scan
-// of its counts numbers the kept ones in ascending index order.
+// Kept coefficients per chunk.
 __global__ __launch_bounds__(kT) void k_af_flags(const uint32_t* __restrict__ keys, BandTable bt,
                                                 const BandState* __restrict__ st, uint32_t* __restrict__ cnt) {
   __shared__ uint32_t s_red[kT / 64];
@@ -264,9 +314,12 @@ __global__ __launch_bounds__(kT) void k_af_flags(const uint32_t* __restrict__ ke
   chunk_range(bt, b, blockIdx.x, begin, end);
   const float thr = st[b].thr;
   uint32_t c = 0;
-  for (int r = 0; r < kPer; ++r) {
-    const int64_t i = begin + static_cast<int64_t>(threadIdx.x) * kPer + r;
-    if (i < end && __uint_as_float(keys[i]) >= thr) ++c;
+  for (int r0 = 0; r0 < kPer; r0 += 16) {
+    uint32_t kk[16];
+    load16(keys, begin, end, r0, kk);
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      c += begin + static_cast<int64_t>(r0 + q) * kT + threadIdx.x < end && __uint_as_float(kk[q]) >= thr ? 1u : 0u;
   }
   c = block_sum_u32(c, s_red);
   if (threadIdx.x == 0) cnt[blockIdx.x] = c;
@@ -278,30 +331,34 @@ __global__ __launch_bounds__(kT) void k_af_write(const uint32_t* __restrict__ ke
   const int b = band_of(bt, blockIdx.x);
   int64_t begin, end;
   chunk_range(bt, b, blockIdx.x, begin, end);
+  // Sub-rounds of 4096 coefficients in which each thread owns 16 consecutive ones, so the block's
+  // scan of the per-thread counts numbers the kept ones in ascending index order.
+  constexpr int kSub = 16;
   const float thr = st[b].thr;
-  uint32_t f = 0;
-  for (int r = 0; r < kPer; ++r) {
-    const int64_t i = begin + static_cast<int64_t>(threadIdx.x) * kPer + r;
-    if (i < end && __uint_as_float(keys[i]) >= thr) f |= 1u << r;
-  }
-  uint32_t tot;
-  int64_t pos = static_cast<int64_t>(offs[blockIdx.x]) + block_excl_scan(static_cast<uint32_t>(__popc(f)), &tot);
-  for (int r = 0; r < kPer; ++r) {
-    if (!((f >> r) & 1u)) continue;
-    if (pos < capacity) kept[pos] = begin + static_cast<int64_t>(threadIdx.x) * kPer + r;
-    ++pos;
+  int64_t pos0 = static_cast<int64_t>(offs[blockIdx.x]);
+  for (int64_t base = begin; base < end; base += kSub * kT) {
+    uint32_t f = 0;
+    for (int r = 0; r < kSub; ++r) {
+      const int64_t i = base + static_cast<int64_t>(threadIdx.x) * kSub + r;
+      if (i < end && __uint_as_float(keys[i]) >= thr) f |= 1u << r;
+    }
+    uint32_t tot;
+    int64_t pos = pos0 + block_excl_scan(static_cast<uint32_t>(__popc(f)), &tot);
+    for (int r = 0; r < kSub; ++r) {
+      if (!((f >> r) & 1u)) continue;
+      if (pos < capacity) kept[pos] = base + static_cast<int64_t>(threadIdx.x) * kSub + r;
+      ++pos;
+    }
+    pos0 += tot;
   }
 }
 
 // Kept count and the per-subband statistics.
-__global__ void k_af_final(BandTable bt, const BandState* __restrict__ st, const uint32_t* __restrict__ cnt,
-                           const uint32_t* __restrict__ total, int64_t* __restrict__ count_dev,
-                           double* __restrict__ stats) {
+__global__ void k_af_final(BandTable bt, const BandState* __restrict__ st, const uint32_t* __restrict__ total,
+                           int64_t* __restrict__ count_dev, double* __restrict__ stats) {
   const int b = threadIdx.x;
   if (b == 0) count_dev[0] = static_cast<int64_t>(total[0]);
   if (b >= bt.nb || !stats) return;
-  uint64_t kept = 0;
-  for (int64_t c = bt.chunk0[b]; c < bt.chunk0[b + 1]; ++c) kept += cnt[c];
   const BandState& s = st[b];
   double* o = stats + static_cast<int64_t>(b) * VBM_ADAPTIVE_STATS;
   o[0] = s.E;
@@ -315,7 +372,7 @@ __global__ void k_af_final(BandTable bt, const BandState* __restrict__ st, const
   o[8] = s.C;
   o[9] = s.K;
   o[10] = s.vK;
-  o[11] = static_cast<double>(kept);
+  o[11] = static_cast<double>(s.kept);
 }
 
 bool make_table(int G, int J, BandTable* bt) {
@@ -431,8 +488,10 @@ extern "C" vbm_status vbm_adaptive_select(const float* coeffs, int32_t G, int32_
     } else if (sel == 1) {
       hipLaunchKernelGGL(k_af_thresh, dim3(1), dim3(128), 0, s, bt, w.st, opts->lambda);
       VBM_LAUNCH_CHECK("adaptive_thresh");
-      hipLaunchKernelGGL(k_af_count, cg, blk, 0, s, w.keys, bt, w.st);
+      hipLaunchKernelGGL(k_af_count, cg, blk, 0, s, w.keys, bt, w.st, w.cnt);
       VBM_LAUNCH_CHECK("adaptive_count");
+      hipLaunchKernelGGL(k_af_band_sum, nbg, blk, 0, s, bt, w.cnt, 0, w.st);
+      VBM_LAUNCH_CHECK("adaptive_band_sum");
       hipLaunchKernelGGL(k_af_kinit, dim3(1), dim3(128), 0, s, bt, w.st);
       VBM_LAUNCH_CHECK("adaptive_kinit");
     } else {
@@ -442,10 +501,12 @@ extern "C" vbm_status vbm_adaptive_select(const float* coeffs, int32_t G, int32_
   }
   hipLaunchKernelGGL(k_af_flags, cg, blk, 0, s, w.keys, bt, w.st, w.cnt);
   VBM_LAUNCH_CHECK("adaptive_flags");
+  hipLaunchKernelGGL(k_af_band_sum, nbg, blk, 0, s, bt, w.cnt, 1, w.st);
+  VBM_LAUNCH_CHECK("adaptive_band_sum");
   VBM_TRY(scan_exclusive_u32(w.cnt, w.offs, chunks, nullptr, w.total, w.scan, s));
   hipLaunchKernelGGL(k_af_write, cg, blk, 0, s, w.keys, bt, w.st, w.offs, capacity, kept_index);
   VBM_LAUNCH_CHECK("adaptive_write");
-  hipLaunchKernelGGL(k_af_final, dim3(1), dim3(128), 0, s, bt, w.st, w.cnt, w.total, count_dev, band_stats);
+  hipLaunchKernelGGL(k_af_final, dim3(1), dim3(128), 0, s, bt, w.st, w.total, count_dev, band_stats);
   VBM_LAUNCH_CHECK("adaptive_final");
   return VBM_OK;
 }
