@@ -149,6 +149,12 @@ typedef struct {
   float delta;
   float opacity_min;
   float opacity_max;
+  /* Ablation variants (Sec. 5): isotropic = 1 replaces every covariance by sigma_iso^2 I (scales
+   * sigma_iso, identity rotation) with sigma_iso the mean over the built Gaussians of the mean of
+   * their three bank scales (the full model's average extent, summed in float64 in a fixed order);
+   * unit_weight = 1 sets w_{j,o} = 1 (no energy projection).  Both 0 for the method itself. */
+  int32_t isotropic;
+  int32_t unit_weight;
 } vbm_build_opts;
 
 size_t vbm_build_workspace_size(int32_t G, int32_t J);

@@ -11,6 +11,12 @@ h = 2/G, so mean_world = -1 + h * centre_idx and scale_world = h * scale_idx.
 Amplitude -> 3DGS parameters: opacity = clamp(amp_alpha, 1e-3, 0.99), rgb = clamp(amp_rgb, 0, 1).
 ``s_mode`` = "paper" applies s_j literally; "none" drops it (the paper's w already carries the
 2^{-3j/2} decay of an orthonormal transform, so the literal factor attenuates twice).
+
+Ablation variants (Sec. 5, ablation studies):
+  * ``isotropic``: without the transition bank's covariances every Gaussian gets sigma_iso^2 I
+    (scales all sigma_iso, identity rotation) with sigma_iso the average spatial extent of the full
+    model, read as the mean over the built Gaussians of the mean of their three full-model scales;
+  * ``unit_weight``: without the energy projection, w_{j,o} = 1.
 """
 from __future__ import annotations
 
@@ -20,7 +26,7 @@ from . import dwt as _dwt
 
 
 def construct(coeffs: np.ndarray, kept: np.ndarray, G: int, J: int, bank: list, s_mode: str = "paper",
-              delta: float = 0.5):
+              delta: float = 0.5, isotropic: bool = False, unit_weight: bool = False):
     """coeffs [4][G^3] packed, kept [K] packed indices, bank in packed block order.
 
     Returns a dict of FP64 arrays: means [3][K], scales [3][K], quats [4][K], opacity [K], rgb [3][K].
@@ -52,7 +58,11 @@ def construct(coeffs: np.ndarray, kept: np.ndarray, G: int, J: int, bank: list, 
         scales[:, sel] = h * e.scale[:, None]
         quats[:, sel] = e.quat[:, None]
         s = 2.0 ** (-1.5 * j) if s_mode == "paper" else 1.0
-        amp = s * A[:, sel] * e.w
+        amp = s * A[:, sel] * (1.0 if unit_weight else e.w)
         rgb[:, sel] = np.clip(amp[:3], 0.0, 1.0)
         opacity[sel] = np.clip(amp[3], 1e-3, 0.99)
+    if isotropic and K > 0:
+        sigma_iso = np.mean(scales.mean(axis=0))
+        scales[:] = sigma_iso
+        quats[:] = np.array([1.0, 0.0, 0.0, 0.0])[:, None]
     return dict(means=means, scales=scales, quats=quats, opacity=opacity, rgb=rgb)

@@ -39,7 +39,7 @@ vbm_gaussians_c = vbm_gaussians  # identical layout; const-ness is only a C-side
 
 class vbm_build_opts(C.Structure):
     _fields_ = [("s_mode", C.c_int32), ("delta", C.c_float), ("opacity_min", C.c_float),
-                ("opacity_max", C.c_float)]
+                ("opacity_max", C.c_float), ("isotropic", C.c_int32), ("unit_weight", C.c_int32)]
 
 
 class vbm_adaptive_opts(C.Structure):

@@ -91,7 +91,8 @@ def bank_build(wavelet: str, J: int, tau: float = 0.1, lam: float = 1e-8):
 
 
 def build_gaussians(coeffs: torch.Tensor, G: int, J: int, bank_packed, K: int, s_mode: str = "paper",
-                    delta: float = 0.5, opacity_min: float = 1e-3, opacity_max: float = 0.99, stride: int | None = None):
+                    delta: float = 0.5, opacity_min: float = 1e-3, opacity_max: float = 0.99, stride: int | None = None,
+                    isotropic: bool = False, unit_weight: bool = False):
     """Top-K + construction.  Returns (P [14, stride] activated parameters, kept int64 [K])."""
     lib = L.load()
     _require_cuda(coeffs)
@@ -101,7 +102,8 @@ def build_gaussians(coeffs: torch.Tensor, G: int, J: int, bank_packed, K: int, s
     P = torch.zeros(N_ROWS, stride, dtype=torch.float32, device=dev)
     kept = torch.empty(K, dtype=torch.int64, device=dev)
     ws = torch.empty(lib.vbm_build_workspace_size(G, J), dtype=torch.uint8, device=dev)
-    opts = L.vbm_build_opts(0 if s_mode == "paper" else 1, delta, opacity_min, opacity_max)
+    opts = L.vbm_build_opts(0 if s_mode == "paper" else 1, delta, opacity_min, opacity_max, int(isotropic),
+                            int(unit_weight))
     st = lib.vbm_build_gaussians(coeffs.data_ptr(), G, J, bank.data_ptr(), K, C.byref(opts), gaussians_struct(P),
                                  kept.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev))
     L.check(st, "vbm_build_gaussians")
@@ -133,7 +135,7 @@ def adaptive_select(coeffs: torch.Tensor, G: int, J: int, K_tot: int, alpha: flo
 
 def construct_gaussians(coeffs: torch.Tensor, G: int, J: int, bank_packed, kept: torch.Tensor, s_mode: str = "paper",
                         delta: float = 0.5, opacity_min: float = 1e-3, opacity_max: float = 0.99,
-                        stride: int | None = None):
+                        stride: int | None = None, isotropic: bool = False, unit_weight: bool = False):
     """Construction for a given list of packed indices (int64, device).  Returns P [14, stride]."""
     lib = L.load()
     _require_cuda(coeffs)
@@ -143,7 +145,8 @@ def construct_gaussians(coeffs: torch.Tensor, G: int, J: int, bank_packed, kept:
     bank = torch.as_tensor(np.ascontiguousarray(bank_packed, dtype=np.float32)).to(dev)
     stride = stride or max(n, 1)
     P = torch.zeros(N_ROWS, stride, dtype=torch.float32, device=dev)
-    opts = L.vbm_build_opts(0 if s_mode == "paper" else 1, delta, opacity_min, opacity_max)
+    opts = L.vbm_build_opts(0 if s_mode == "paper" else 1, delta, opacity_min, opacity_max, int(isotropic),
+                            int(unit_weight))
     st = lib.vbm_construct_gaussians(coeffs.data_ptr(), G, J, bank.data_ptr(), kept.data_ptr(), n, C.byref(opts),
                                      gaussians_struct(P), _stream(dev))
     L.check(st, "vbm_construct_gaussians")

@@ -152,6 +152,7 @@ struct BuildParams {
   float delta;
   float op_min, op_max;
   int s_mode;
+  int unit_weight;
   int64_t M;
 };
 
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(kT) void k_build(const float* __restrict__ coeffs, 
   const int ky = static_cast<int>((off / side) % side);
   const int kz = static_cast<int>(off / (side * side));
   const float* e = bank + static_cast<int64_t>(b) * VBM_BANK_FLOATS;
-  const float w = e[0];
+  const float w = p.unit_weight ? 1.0f : e[0];
   const float step = static_cast<float>(1 << j);
   out.means[n] = -1.0f + p.h * (e[1] + step * kx + p.delta);
   out.means[out.stride + n] = -1.0f + p.h * (e[2] + step * ky + p.delta);
@@ -205,6 +206,30 @@ __global__ __launch_bounds__(kT) void k_build(const float* __restrict__ coeffs, 
   const float amp_a = s * fabsf(coeffs[3 * p.M + idx]) * w;
   out.opacity[n] = fminf(fmaxf(amp_a, p.op_min), p.op_max);
   if (kept_out) kept_out[n] = idx;
+}
+
+// Ablation without the transition bank: sigma_iso = mean over the n built Gaussians of the mean of
+// their three scales (float64, fixed order: thread-strided sums, then a fixed tree), then every
+// Gaussian gets scales sigma_iso and the identity rotation.  One block.
+__global__ __launch_bounds__(1024) void k_isotropize(vbm_gaussians out, int64_t n) {
+  __shared__ double s_sum[1024];
+  const int64_t S = out.stride;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024)
+    acc += (static_cast<double>(out.scales[i]) + static_cast<double>(out.scales[S + i]) +
+            static_cast<double>(out.scales[2 * S + i])) / 3.0;
+  s_sum[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 512; st >= 1; st >>= 1) {
+    if (static_cast<int>(threadIdx.x) < st) s_sum[threadIdx.x] += s_sum[threadIdx.x + st];
+    __syncthreads();
+  }
+  const float sigma = static_cast<float>(s_sum[0] / static_cast<double>(n));
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    out.scales[i] = out.scales[S + i] = out.scales[2 * S + i] = sigma;
+    out.quats[i] = 1.0f;
+    out.quats[S + i] = out.quats[2 * S + i] = out.quats[3 * S + i] = 0.0f;
+  }
 }
 
 int grid_cap(int64_t n, int cap) {
@@ -259,6 +284,10 @@ extern "C" vbm_status vbm_build_gaussians(const float* coeffs, int32_t G, int32_
     set_error("vbm_build_gaussians: need 0 <= opacity_min <= opacity_max <= 1");
     return VBM_ERR_INVALID;
   }
+  if ((opts->isotropic != 0 && opts->isotropic != 1) || (opts->unit_weight != 0 && opts->unit_weight != 1)) {
+    set_error("vbm_build_gaussians: isotropic and unit_weight must be 0 or 1");
+    return VBM_ERR_INVALID;
+  }
   if (ws_bytes < vbm_build_workspace_size(G, J)) {
     set_error("vbm_build_gaussians: workspace %zu < %zu", ws_bytes, vbm_build_workspace_size(G, J));
     return VBM_ERR_WORKSPACE;
@@ -297,10 +326,15 @@ extern "C" vbm_status vbm_build_gaussians(const float* coeffs, int32_t G, int32_
   p.op_min = opts->opacity_min;
   p.op_max = opts->opacity_max;
   p.s_mode = opts->s_mode;
+  p.unit_weight = opts->unit_weight;
   p.M = M;
   hipLaunchKernelGGL(k_build<uint32_t>, dim3(ceil_div(K, kT)), dim3(kT), 0, s, coeffs, kept, K, bank_dev, p, out,
                      kept_index);
   VBM_LAUNCH_CHECK("build");
+  if (opts->isotropic) {
+    hipLaunchKernelGGL(k_isotropize, dim3(1), dim3(1024), 0, s, out, K);
+    VBM_LAUNCH_CHECK("isotropize");
+  }
   return VBM_OK;
 }
 
@@ -321,7 +355,8 @@ extern "C" vbm_status vbm_construct_gaussians(const float* coeffs, int32_t G, in
     return VBM_ERR_INVALID;
   }
   if ((opts->s_mode != 0 && opts->s_mode != 1) ||
-      !(opts->opacity_min >= 0.0f && opts->opacity_min <= opts->opacity_max && opts->opacity_max <= 1.0f)) {
+      !(opts->opacity_min >= 0.0f && opts->opacity_min <= opts->opacity_max && opts->opacity_max <= 1.0f) ||
+      (opts->isotropic != 0 && opts->isotropic != 1) || (opts->unit_weight != 0 && opts->unit_weight != 1)) {
     set_error("vbm_construct_gaussians: bad opts");
     return VBM_ERR_INVALID;
   }
@@ -334,9 +369,14 @@ extern "C" vbm_status vbm_construct_gaussians(const float* coeffs, int32_t G, in
   p.op_min = opts->opacity_min;
   p.op_max = opts->opacity_max;
   p.s_mode = opts->s_mode;
+  p.unit_weight = opts->unit_weight;
   p.M = static_cast<int64_t>(G) * G * G;
   hipLaunchKernelGGL(k_build<int64_t>, dim3(ceil_div(n, kT)), dim3(kT), 0, static_cast<hipStream_t>(stream), coeffs,
                      kept_index, n, bank_dev, p, out, static_cast<int64_t*>(nullptr));
   VBM_LAUNCH_CHECK("construct");
+  if (opts->isotropic) {
+    hipLaunchKernelGGL(k_isotropize, dim3(1), dim3(1024), 0, static_cast<hipStream_t>(stream), out, n);
+    VBM_LAUNCH_CHECK("isotropize");
+  }
   return VBM_OK;
 }

@@ -214,3 +214,30 @@ def test_graph_replay_matches_eager_repeatedly():
         assert d <= 1e-4, (it, d)
         _ = eager.loss()   # host work between replays
     assert int(graph.step_dev.item()) == 4 and int(eager.step_dev.item()) == 4
+
+
+@pytest.mark.parametrize("isotropic,unit_weight", [(True, False), (False, True), (True, True)])
+def test_construction_ablation_variants(isotropic, unit_weight):
+    """Without the bank's covariances (isotropic) and without the energy projection (w = 1),
+    through the top-K build and through construction from an index list."""
+    api = _api()
+    G, J, wav, K = 32, 3, "bior4.4", 4000
+    say(f"ablation isotropic={isotropic} unit_weight={unit_weight}")
+    vol, tf = _dwt_case(G, J, wav, 11)
+    coeffs_d = api.dwt3d(torch.from_numpy(vol).to(dev()), J, wav, (tf.xs, tf.rgba))
+    _, packed = api.bank_build(wav, J)
+    P, kept = api.build_gaussians(coeffs_d, G, J, packed, K, s_mode="none", isotropic=isotropic,
+                                  unit_weight=unit_weight)
+    P2 = api.construct_gaussians(coeffs_d, G, J, packed, kept, s_mode="none", isotropic=isotropic,
+                                 unit_weight=unit_weight)
+    ref = oconstruct.construct(coeffs_d.cpu().numpy(), kept.cpu().numpy(), G, J, obank.build_bank(wav, J),
+                               s_mode="none", isotropic=isotropic, unit_weight=unit_weight)
+    for Pn in (P.cpu().numpy(), P2.cpu().numpy()):
+        for name, rows in (("means", slice(0, 3)), ("scales", slice(3, 6)), ("quats", slice(6, 10)),
+                           ("opacity", slice(10, 11)), ("rgb", slice(11, 14))):
+            r = ref[name].reshape(rows.stop - rows.start, -1)
+            err = np.abs(Pn[rows] - r).max() / max(np.abs(r).max(), 1e-6)
+            assert err <= 1e-6, (name, err)
+    if isotropic:
+        S = P.cpu().numpy()[3:6]
+        assert np.all(S == S[0, 0])
