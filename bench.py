@@ -51,7 +51,12 @@ WORKLOADS = {
                                     "8 orbit views 1920x1080, loss 0.8 L1 + 0.2 D-SSIM, Adam"),
     "c1": dict(config=1, G=128, J=3, wavelet="haar", K=100_000, views=16, W=800, H=800, tile=16, loss="l1",
                desc="128^3 blobs + k^-2 noise, Haar J=3, top-100k Gaussians, 16 orbit views 800x800, L1, Adam"),
+    "c2": dict(config=2, G=256, J=4, wavelet="bior4.4", K=500_000, views=8, W=1024, H=1024, tile=16,
+               loss="l1_dssim", desc="256^3 blobs + k^-2 noise, bior4.4 J=4, top-500k Gaussians, 8 orbit views "
+                                     "1024x1024, loss 0.8 L1 + 0.2 D-SSIM, Adam"),
 }
+# checkpoints (steps) of the --convergence ablation runs
+CONVERGENCE_AT = (1, 10, 25, 50, 100, 200, 400, 800)
 
 
 def log(msg: str) -> None:
@@ -299,7 +304,67 @@ def run_gpu(args, wl):
         out["plain_wall_s"] = wall_p
         log(f"plain: {args.steps / wall_p:.2f} it/s")
         del fp
+
+    if args.convergence > 0:
+        out["convergence"] = run_convergence(args, wl, vol_d, tfn, cams, targets, loss_kind)
     return out
+
+
+def run_convergence(args, wl, vol_d, tfn, cams, targets, loss_kind):
+    """PSNR against the DVR targets over training for the method and its ablation variants (Sec. 5):
+    without the transition bank's covariances, without the energy projection, with Haar instead of
+    bior4.4, and from random parameters.  The PSNR after checkpoint step t is that of the image
+    rendered in step t (the parameters after t - 1 updates), averaged over the views."""
+    import torch
+
+    import vbm_inputs as vi
+    from paper_2601_09417_amd import api, trainer
+
+    dev = vol_d.device
+    npx = [c.width * c.height for c in cams]
+    offs = np.concatenate([[0], np.cumsum(npx)]) * 3
+
+    def psnr(img):
+        vals = []
+        for v in range(len(cams)):
+            mse = torch.mean((img[offs[v]:offs[v + 1]] - targets[offs[v]:offs[v + 1]]) ** 2).item()
+            vals.append(10.0 * np.log10(1.0 / max(mse, 1e-12)))
+        return float(np.mean(vals))
+
+    def built(wavelet, **flags):
+        coeffs = api.dwt3d(vol_d, wl["J"], wavelet, (tfn.xs, tfn.rgba))
+        _, packed = api.bank_build(wavelet, wl["J"])
+        P, _ = api.build_gaussians(coeffs, wl["G"], wl["J"], packed, wl["K"], s_mode="none", **flags)
+        return P
+
+    variants = {"vbm": lambda: built(wl["wavelet"]),
+                "no_transition_bank": lambda: built(wl["wavelet"], isotropic=True),
+                "no_energy_projection": lambda: built(wl["wavelet"], unit_weight=True),
+                "haar": lambda: built("haar")}
+    # random initialisation: seeded uniform centres in the volume, isotropic log-normal scales around
+    # the method's mean extent, random rotations, opacity U(0.05, 0.5), colour U(0, 1)
+    sigma = float(built(wl["wavelet"], isotropic=True)[3, 0].item())
+    rnd = vi.random_gaussians(wl["K"], 7 + wl["config"], extent=0.95, log_scale_mean=float(np.log(sigma)),
+                              log_scale_std=0.3, opacity_range=(0.05, 0.5))
+    variants["random_init"] = lambda: api.pack_params(rnd.means, rnd.scales, rnd.quats, rnd.opacity, rnd.rgb, dev)
+    at = [t for t in CONVERGENCE_AT if t <= args.convergence]
+    res = {}
+    for name, make in variants.items():
+        P = make()
+        ft = trainer.FineTuner(P, cams, targets, loss=loss_kind, lam=0.2, tile=wl["tile"], schedule="graph")
+        curve = []
+        for t in range(1, args.convergence + 1):
+            ft.step()
+            if t in at:
+                torch.cuda.synchronize()
+                curve.append(round(psnr(ft.image), 3))
+            if t % 10 == 0:
+                ft.check_capacity()   # parameters move: re-plan when the pair lists outgrow the plan
+        res[name] = curve
+        log(f"convergence {name}: " + ", ".join(f"{t}:{p:.2f}" for t, p in zip(at, curve)) +
+            f"  (pairs at the end {ft.pair_count()}, re-plans {ft.overflows})")
+        del ft, P
+    return dict(steps=at, psnr_db=res, workload=wl["desc"])
 
 
 def main() -> int:
@@ -316,6 +381,8 @@ def main() -> int:
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--cpu-tiles", type=int, default=256, help="tiles in the CPU oracle sample")
     ap.add_argument("--cpu-threads", type=int, default=8)
+    ap.add_argument("--convergence", type=int, default=0,
+                    help="also train each ablation variant (Sec. 5) for this many steps and report PSNR")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (scales HBM counters)")
     args = ap.parse_args()
@@ -378,6 +445,7 @@ def main() -> int:
         "pairs_per_step": gpu["pairs_per_step"],
         "init_ms": round(gpu["init_ms"], 2),
         "adaptive_select": gpu.get("adaptive_select"),
+        "convergence": gpu.get("convergence"),
         "kernels_ms": {n: round(d["ms"], 3) for n, d in gpu["kernels"].items()},
         "composite_evals": {n: [int(d["evals"]), int(d["contrib"])] for n, d in gpu["kernels"].items()},
         "roofline": {

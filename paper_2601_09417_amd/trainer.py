@@ -141,6 +141,16 @@ class FineTuner:
         """True if any forward since the last check dropped pairs (reads the device flag)."""
         return any(int(o.status[0].item()) != 0 for o in self.outs)
 
+    def check_capacity(self) -> bool:
+        """Reads the overflow flags (one host sync).  If a forward dropped pairs, re-plans with the
+        exact counts of the current parameters, so the next step renders complete lists (its graph is
+        captured again); returns True when it re-planned."""
+        if not self.overflowed():
+            return False
+        self.overflows += 1
+        self._plan(None)
+        return True
+
     def pair_count(self) -> int:
         return sum(int(o.status[1].item()) for o in self.outs)
 
