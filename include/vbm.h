@@ -282,7 +282,9 @@ vbm_status vbm_plan_make(const vbm_view* views_host, int32_t n_views, const int6
 /* ------------------------------------------------------------------------------------------
  * vbm_render_fwd -- project (all views), bin, depth-sort, tile-sort and composite.
  *   status    device int32 [4]: [0] set to 1 if the pair list overflowed pair_capacity (the images
- *             are then incomplete; re-plan with a larger capacity), [1] pair count, [2] visible items
+ *             are then incomplete; re-plan with a larger capacity), [1] pair count, [2] visible items,
+ *             [3] incremented when this forward overflowed (a count over the forwards that share the
+ *             buffer, so that a loop without host syncs can check once; the caller resets it)
  *   ws        plan->ws_bytes; holds the state vbm_render_bwd needs, keep it unchanged between
  * ------------------------------------------------------------------------------------------ */
 vbm_status vbm_render_fwd(const vbm_plan* plan_host, const void* view_table_dev, vbm_gaussians_c g, float* image,

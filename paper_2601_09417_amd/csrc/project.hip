@@ -454,7 +454,7 @@ __global__ void k_status(const uint32_t* __restrict__ counters, int32_t* __restr
     status[0] = static_cast<int32_t>(counters[2]);
     status[1] = static_cast<int32_t>(counters[1]);
     status[2] = static_cast<int32_t>(counters[0]);
-    status[3] = 0;
+    status[3] += counters[2] ? 1 : 0;
   }
 }
 

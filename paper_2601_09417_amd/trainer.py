@@ -138,8 +138,12 @@ class FineTuner:
             self._step_body()
 
     def overflowed(self) -> bool:
-        """True if any forward since the last check dropped pairs (reads the device flag)."""
-        return any(int(o.status[0].item()) != 0 for o in self.outs)
+        """True if any forward since the last check dropped pairs (reads the device counts, one host
+        sync, and clears them)."""
+        hit = any(int(o.status[0].item()) != 0 or int(o.status[3].item()) != 0 for o in self.outs)
+        for o in self.outs:
+            o.status[3].zero_()
+        return hit
 
     def check_capacity(self) -> bool:
         """Reads the overflow flags (one host sync).  If a forward dropped pairs, re-plans with the

@@ -174,6 +174,9 @@ def test_capacity_overflow_is_flagged():
     out = api.render_fwd(rp, P)
     torch.cuda.synchronize()
     assert int(out.status[0]) == 1 and int(out.status[1]) > 100
+    api.render_fwd(rp, P, out)                      # a second overflowing forward into the same status
+    torch.cuda.synchronize()
+    assert int(out.status[3]) == 2
     rp2 = api.plan_batch(cams, [0, gs.n], tile=16, pair_capacity=int(out.status[1]))
     out2 = api.render_fwd(rp2, P)
     torch.cuda.synchronize()
