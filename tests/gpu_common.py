@@ -56,20 +56,24 @@ def flat(arrs) -> torch.Tensor:
 
 
 def adaptive_check(coeffs_np, G, J, kept_gpu, stats_gpu, K_tot, **kw):
-    """Stage-isolated parity of one vbm_adaptive_select result with the oracle (see test_gpu_adaptive)."""
+    """Parity of one vbm_adaptive_select result with the oracle run on the same float32 coefficients
+    (made by the oracle or by the seeded generators, never by the HIP path).  Budgets are float64
+    quotients floored to integers, summed in different orders on the two sides; the fixtures keep
+    every quotient at least 1e-3 away from an integer unless it is one exactly (with alpha = 0 and
+    power-of-two band sizes every operation is exact), so the budgets are unique and compared exactly.
+    Everything after the budgets is float32 decided in the same order on both sides and must match
+    bit for bit."""
     from oracle import adaptive as A
     from paper_2601_09417_amd import _lib as L
     S = {name: stats_gpu[:, i] for i, name in enumerate(L.ADAPTIVE_STATS)}
-    budgets = S["K_band"].astype(np.int64)
-    kept_o, so = A.select(coeffs_np, G, J, K_tot, band_budgets=budgets, **kw)
+    kept_o, so = A.select(coeffs_np, G, J, K_tot, **kw)
     E = np.array([s["E"] for s in so])
-    alpha, beta = kw.get("alpha", A.DEFAULTS["alpha"]), kw.get("beta", A.DEFAULTS["beta"])
-    q = A.budget_quotients(E, np.array([s["N"] for s in so]), K_tot, alpha, beta)
+    N = np.array([s["N"] for s in so])
+    q = np.array([s["quotient"] for s in so])
     assert np.allclose(S["E"], E, rtol=1e-12, atol=0.0)
+    assert np.array_equal(S["N"].astype(np.int64), N)
     assert np.allclose(S["quotient"], q, rtol=1e-11, atol=1e-300)
-    own = A.budgets(E, np.array([s["N"] for s in so]), K_tot, alpha, beta, kw.get("min_band", A.DEFAULTS["min_band"]))
-    near = np.abs(q - np.round(q)) <= 1e-9 * np.maximum(1.0, q)
-    assert np.array_equal(budgets[~near], own[~near])
+    assert np.array_equal(S["K_band"].astype(np.int64), np.array([s["K_band"] for s in so]))
     for b, s in enumerate(so):
         for name in ("median", "mad", "sigma", "T", "vK"):
             assert np.float32(S[name][b]) == s[name], (b, name, S[name][b], s[name])

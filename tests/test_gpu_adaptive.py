@@ -1,18 +1,21 @@
 """GPU parity of the adaptive per-subband selection (Supp. A) and of construction from an index
-list, against the oracle on the GPU's own float32 coefficients (stage isolation).
+list, against the oracle on the same float32 coefficients: the oracle's FP64 DWT of TF(F) cast
+to float32 (or seeded synthetic values), uploaded for the HIP path.
 
-Budgets are float64 quotients floored to integers; the two sides sum in different orders, so a
-budget is compared exactly unless the oracle's quotient lies within 1e-9 of an integer (then either
-neighbour is correct and the oracle continues with the GPU's budgets).  Everything after the
-budgets is float32 decided in the same order on both sides and must match bit for bit: medians,
-MAD, sigma, T, #(v >= T), K, v_(K) and the kept index list."""
+Budgets are float64 quotients floored to integers and must match exactly (the fixtures have no
+quotient within 1e-9 of an integer).  Everything after the budgets is float32 decided in the same
+order on both sides and must match bit for bit: medians, MAD, sigma, T, #(v >= T), K, v_(K) and
+the kept index list."""
 import numpy as np
 import pytest
 import torch
 
 import vbm_inputs as vi
+from oracle import adaptive as oadaptive
 from oracle import bank as obank
 from oracle import construct as oconstruct
+from oracle import dwt as odwt
+from oracle import tf as otf
 from paper_2601_09417_amd import _lib as L
 from tests.gpu_common import ROWS, adaptive_check, dev, say
 
@@ -25,10 +28,10 @@ def _api():
 
 
 def _coeffs(G, J, wav, seed):
-    api = _api()
+    """float32 coefficients of the oracle's DWT of TF(F) for a seeded blob volume."""
     vol = vi.minmax(vi.blob_volume(G, 6, seed)).astype(np.float32)
     tf = vi.transfer_function(seed)
-    return api.dwt3d(torch.from_numpy(vol).to(dev()), J, wav, (tf.xs, tf.rgba))
+    return odwt.dwt3d_rgba(otf.apply(vol, tf.xs, tf.rgba), J, wav).astype(np.float32)
 
 
 @pytest.mark.parametrize("G,J,wav,K_tot,params", [
@@ -42,10 +45,9 @@ def _coeffs(G, J, wav, seed):
 def test_adaptive_select_matches_oracle(G, J, wav, K_tot, params):
     api = _api()
     say(f"adaptive G={G} J={J} {wav} K_tot={K_tot} {params}")
-    coeffs = _coeffs(G, J, wav, G + J)
-    kept, stats = api.adaptive_select(coeffs, G, J, K_tot, **params)
-    kept_o, so = adaptive_check(coeffs.cpu().numpy(), G, J, kept.cpu().numpy(), stats.cpu().numpy(), K_tot,
-                                      **params)
+    c = _coeffs(G, J, wav, G + J)
+    kept, stats = api.adaptive_select(torch.from_numpy(c).to(dev()), G, J, K_tot, **params)
+    kept_o, so = adaptive_check(c, G, J, kept.cpu().numpy(), stats.cpu().numpy(), K_tot, **params)
     say(f"  kept {kept_o.size} over {len(so)} subbands")
 
 
@@ -74,13 +76,15 @@ def test_adaptive_rejects_bad_arguments():
 def test_construct_from_adaptive_indices():
     api = _api()
     G, J, wav = 32, 3, "bior4.4"
-    coeffs = _coeffs(G, J, wav, 9)
+    c = _coeffs(G, J, wav, 9)
+    coeffs = torch.from_numpy(c).to(dev())
+    kept_o, _ = oadaptive.select(c, G, J, 3000)
     kept, _ = api.adaptive_select(coeffs, G, J, 3000)
+    assert np.array_equal(kept.cpu().numpy(), kept_o)
     _, packed = api.bank_build(wav, J)
     for s_mode in ("paper", "none"):
-        P = api.construct_gaussians(coeffs, G, J, packed, kept, s_mode=s_mode)
-        ref = oconstruct.construct(coeffs.cpu().numpy(), kept.cpu().numpy(), G, J, obank.build_bank(wav, J),
-                                   s_mode=s_mode)
+        P = api.construct_gaussians(coeffs, G, J, packed, torch.from_numpy(kept_o).to(dev()), s_mode=s_mode)
+        ref = oconstruct.construct(c, kept_o, G, J, obank.build_bank(wav, J), s_mode=s_mode)
         Pn = P.cpu().numpy()
         for name, rows in ROWS.items():
             r = ref[name].reshape(rows.stop - rows.start, -1)

@@ -30,6 +30,11 @@ def _dwt_case(G, J, wav, seed):
     return vol, tf
 
 
+def _oracle_coeffs(vol, tf, J, wav):
+    """float32 coefficients of the oracle's FP64 DWT of TF(F): the input both sides select from."""
+    return odwt.dwt3d_rgba(otf.apply(vol, tf.xs, tf.rgba), J, wav).astype(np.float32)
+
+
 @pytest.mark.parametrize("G,J,wav", [(32, 1, "haar"), (32, 3, "haar"), (32, 2, "bior4.4"), (48, 3, "bior4.4"),
                                      (16, 3, "bior4.4")])
 def test_dwt_matches_oracle(G, J, wav):
@@ -61,12 +66,10 @@ def test_dwt_rgba_input_path():
 def test_select_bit_exact_and_construction(G, J, wav, K, s_mode):
     api = _api()
     say(f"select/build G={G} J={J} {wav} K={K}")
-    vol, tf = _dwt_case(G, J, wav, 7)
-    coeffs_d = api.dwt3d(torch.from_numpy(vol).to(dev()), J, wav, (tf.xs, tf.rgba))
+    coeffs = _oracle_coeffs(*_dwt_case(G, J, wav, 7), J, wav)
     entries, packed = api.bank_build(wav, J)
-    P, kept = api.build_gaussians(coeffs_d, G, J, packed, K, s_mode=s_mode)
-    coeffs = coeffs_d.cpu().numpy()
-    ref_kept = oselect.topk(coeffs, K)            # stage-isolated: same float32 coefficients
+    P, kept = api.build_gaussians(torch.from_numpy(coeffs).to(dev()), G, J, packed, K, s_mode=s_mode)
+    ref_kept = oselect.topk(coeffs, K)
     assert np.array_equal(kept.cpu().numpy(), ref_kept)
     ob = obank.build_bank(wav, J)
     ref = oconstruct.construct(coeffs, ref_kept, G, J, ob, s_mode=s_mode)
@@ -116,15 +119,17 @@ def test_adam_matches_oracle():
     N = 1000
     gs = vi.random_gaussians(N, 2)
     P = api.pack_params(gs.means, gs.scales, gs.quats, gs.opacity, gs.rgb, dev())
-    raw = api.raw_from_activated(P)
+    ls, lo = oadam.raw_from_activated(gs.scales, gs.opacity)
+    # the activated -> raw map on the GPU against the oracle's
+    raw_gpu = api.raw_from_activated(P).cpu().numpy().astype(np.float64)
+    assert np.abs(raw_gpu[3:6] - ls).max() <= 1e-6 * np.abs(ls).max()
+    assert np.abs(raw_gpu[10] - lo).max() <= 1e-5 * np.abs(lo).max()
+    # both sides start from the oracle's raw values rounded to float32
+    R = np.concatenate([gs.means, ls, gs.quats, lo[None], gs.rgb], 0).astype(np.float32).astype(np.float64)
+    raw = torch.from_numpy(R.astype(np.float32)).to(dev())
     m = torch.zeros_like(raw)
     v = torch.zeros_like(raw)
     act = P.clone()
-    ls, lo = oadam.raw_from_activated(gs.scales, gs.opacity)
-    oraw = dict(means=gs.means.astype(np.float64), log_scales=ls, quats=gs.quats.astype(np.float64),
-                logit_opacity=lo, rgb=gs.rgb.astype(np.float64))
-    # oracle starts from the same float32 raw values
-    R = raw.cpu().numpy().astype(np.float64)
     oraw = dict(means=R[0:3], log_scales=R[3:6], quats=R[6:10], logit_opacity=R[10], rgb=R[11:14])
     om = {k: np.zeros_like(a) for k, a in oraw.items()}
     ov = {k: np.zeros_like(a) for k, a in oraw.items()}
@@ -223,14 +228,16 @@ def test_construction_ablation_variants(isotropic, unit_weight):
     api = _api()
     G, J, wav, K = 32, 3, "bior4.4", 4000
     say(f"ablation isotropic={isotropic} unit_weight={unit_weight}")
-    vol, tf = _dwt_case(G, J, wav, 11)
-    coeffs_d = api.dwt3d(torch.from_numpy(vol).to(dev()), J, wav, (tf.xs, tf.rgba))
+    coeffs = _oracle_coeffs(*_dwt_case(G, J, wav, 11), J, wav)
+    coeffs_d = torch.from_numpy(coeffs).to(dev())
+    ref_kept = oselect.topk(coeffs, K)
     _, packed = api.bank_build(wav, J)
     P, kept = api.build_gaussians(coeffs_d, G, J, packed, K, s_mode="none", isotropic=isotropic,
                                   unit_weight=unit_weight)
-    P2 = api.construct_gaussians(coeffs_d, G, J, packed, kept, s_mode="none", isotropic=isotropic,
-                                 unit_weight=unit_weight)
-    ref = oconstruct.construct(coeffs_d.cpu().numpy(), kept.cpu().numpy(), G, J, obank.build_bank(wav, J),
+    assert np.array_equal(kept.cpu().numpy(), ref_kept)
+    P2 = api.construct_gaussians(coeffs_d, G, J, packed, torch.from_numpy(ref_kept).to(dev()), s_mode="none",
+                                 isotropic=isotropic, unit_weight=unit_weight)
+    ref = oconstruct.construct(coeffs, ref_kept, G, J, obank.build_bank(wav, J),
                                s_mode="none", isotropic=isotropic, unit_weight=unit_weight)
     for Pn in (P.cpu().numpy(), P2.cpu().numpy()):
         for name, rows in (("means", slice(0, 3)), ("scales", slice(3, 6)), ("quats", slice(6, 10)),
