@@ -307,7 +307,80 @@ def run_gpu(args, wl):
 
     if args.convergence > 0:
         out["convergence"] = run_convergence(args, wl, vol_d, tfn, cams, targets, loss_kind)
+    if args.modes > 0:
+        del targets
+        out["modes"] = run_modes(args, wl, vol_d, loss_kind)
     return out
+
+
+def run_modes(args, wl, vol_d, loss_kind):
+    """Visual modes (Sec. 4.4): n transfer functions, each zero outside its own interval of the
+    field's values, one Gaussian set per mode (the workload's K split evenly), every set fine-tuned
+    against the DVR of its own radiance field from the same orbit cameras, all modes as the scenes
+    of one batched step (one HIP graph).  Reports the step rate and PSNR over training of every
+    mode rendered separately against its own DVR, and of all sets rendered concatenated against
+    the DVR of the union of the transfer functions."""
+    import torch
+
+    import vbm_inputs as vi
+    from paper_2601_09417_amd import api, trainer
+
+    n, V, R = args.n_modes, args.mode_views, args.mode_size
+    vol = vol_d.cpu().numpy()
+    tfs = vi.mode_transfer_functions(vol, wl["config"], n)
+    edges = vi.mode_intervals(vol, n)
+    union = vi.union_transfer_function(tfs)
+    del vol
+    pairs = [(t.xs, t.rgba) for t in tfs]
+    Kh = wl["K"] // n
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P, offs, _ = api.build_mode_sets(vol_d, pairs, wl["J"], wl["wavelet"], Kh, s_mode="none")
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    cams = vi.orbit_cameras(V, R, R)
+    cams_all, view_scene = api.mode_views(cams, n)
+    targets = api.dvr_render_modes(vol_d, pairs, cams)
+    union_targets = api.dvr_render(vol_d, (union.xs, union.rgba), cams)
+    torch.cuda.synchronize()
+    log(f"modes: {n} sets of {Kh} Gaussians built in {build_ms:.1f} ms; {n} x {V} targets {R}x{R} ready")
+    per = targets.numel() // n
+    npx = 3 * R * R
+
+    def psnr(img, tgt):
+        vals = [10.0 * np.log10(1.0 / max(torch.mean((img[v * npx:(v + 1) * npx] - tgt[v * npx:(v + 1) * npx]) ** 2)
+                                          .item(), 1e-12)) for v in range(tgt.numel() // npx)]
+        return float(np.mean(vals))
+
+    ft = trainer.FineTuner(P, cams_all, targets, offs, view_scene, loss=loss_kind, lam=0.2, tile=wl["tile"],
+                           schedule="graph")
+    at = [t for t in CONVERGENCE_AT if t <= args.modes]
+    sep = {h: [] for h in range(n)}
+    concat = []
+    t_train = 0.0
+    for t in range(1, args.modes + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ft.step()
+        torch.cuda.synchronize()
+        if t > 1:                  # the first step includes the graph capture
+            t_train += time.perf_counter() - t0
+        if t in at:
+            for h in range(n):
+                sep[h].append(round(psnr(ft.image[h * per:(h + 1) * per], targets[h * per:(h + 1) * per]), 3))
+            # the parameters after t updates, all sets in one scene
+            concat.append(round(psnr(trainer.render_images(ft.act, cams, tile=wl["tile"]), union_targets), 3))
+            log(f"modes step {t}: separate " + " ".join(f"{sep[h][-1]:.2f}" for h in range(n)) +
+                f" dB, concatenated {concat[-1]:.2f} dB")
+        if t % 10 == 0:
+            ft.check_capacity()
+    return dict(n_modes=n, intervals=[round(float(e), 5) for e in edges], gaussians_per_mode=Kh,
+                views_per_mode=V, size=[R, R], build_ms=round(build_ms, 1),
+                step_ms=round(1e3 * t_train / max(args.modes - 1, 1), 3), pairs_at_end=ft.pair_count(), re_plans=ft.overflows,
+                steps=at, psnr_db_separate=sep, psnr_db_concatenated=concat,
+                note="separate: each mode's views against the DVR of its own transfer function (the image of "
+                     "step t, i.e. after t - 1 updates); concatenated: all sets in one scene after t updates "
+                     "against the DVR of the union of the transfer functions")
 
 
 def run_convergence(args, wl, vol_d, tfn, cams, targets, loss_kind):
@@ -383,6 +456,11 @@ def main() -> int:
     ap.add_argument("--cpu-threads", type=int, default=8)
     ap.add_argument("--convergence", type=int, default=0,
                     help="also train each ablation variant (Sec. 5) for this many steps and report PSNR")
+    ap.add_argument("--modes", type=int, default=0,
+                    help="also fine-tune the visual-mode sets (Sec. 4.4) together for this many steps and report PSNR")
+    ap.add_argument("--n-modes", type=int, default=5, help="transfer functions (visual modes) per volume")
+    ap.add_argument("--mode-views", type=int, default=64, help="supervision views per mode")
+    ap.add_argument("--mode-size", type=int, default=512, help="edge of the square mode views")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (scales HBM counters)")
     args = ap.parse_args()
@@ -446,6 +524,7 @@ def main() -> int:
         "init_ms": round(gpu["init_ms"], 2),
         "adaptive_select": gpu.get("adaptive_select"),
         "convergence": gpu.get("convergence"),
+        "modes": gpu.get("modes"),
         "kernels_ms": {n: round(d["ms"], 3) for n, d in gpu["kernels"].items()},
         "composite_evals": {n: [int(d["evals"]), int(d["contrib"])] for n, d in gpu["kernels"].items()},
         "roofline": {

@@ -33,10 +33,11 @@ def _require_cuda(*ts):
             raise ValueError("libvbm operates on GPU tensors only")
 
 
-def gaussians_struct(P: torch.Tensor) -> L.vbm_gaussians:
-    """SoA pointer struct over a [14, stride] float32 tensor."""
+def gaussians_struct(P: torch.Tensor, offset: int = 0) -> L.vbm_gaussians:
+    """SoA pointer struct over a [14, stride] float32 tensor, starting at column ``offset``."""
     assert P.dtype == torch.float32 and P.dim() == 2 and P.shape[0] == N_ROWS and P.is_contiguous()
-    base, stride = P.data_ptr(), P.shape[1]
+    assert 0 <= offset <= P.shape[1]
+    base, stride = P.data_ptr() + 4 * int(offset), P.shape[1]
     row = lambda r: base + 4 * r * stride  # noqa: E731
     return L.vbm_gaussians(row(0), row(3), row(6), row(10), row(11), stride)
 
@@ -92,20 +93,28 @@ def bank_build(wavelet: str, J: int, tau: float = 0.1, lam: float = 1e-8):
 
 def build_gaussians(coeffs: torch.Tensor, G: int, J: int, bank_packed, K: int, s_mode: str = "paper",
                     delta: float = 0.5, opacity_min: float = 1e-3, opacity_max: float = 0.99, stride: int | None = None,
-                    isotropic: bool = False, unit_weight: bool = False):
-    """Top-K + construction.  Returns (P [14, stride] activated parameters, kept int64 [K])."""
+                    isotropic: bool = False, unit_weight: bool = False, out: torch.Tensor | None = None,
+                    offset: int = 0):
+    """Top-K + construction.  Returns (P [14, stride] activated parameters, kept int64 [K]).
+    With ``out`` given, the K Gaussians are written into its columns [offset, offset + K) and
+    ``out`` is returned as P (the other columns are left as they are)."""
     lib = L.load()
     _require_cuda(coeffs)
     dev = coeffs.device
     bank = torch.as_tensor(np.ascontiguousarray(bank_packed, dtype=np.float32)).to(dev)
-    stride = stride or K
-    P = torch.zeros(N_ROWS, stride, dtype=torch.float32, device=dev)
+    if out is None:
+        P = torch.zeros(N_ROWS, stride or K, dtype=torch.float32, device=dev)
+    else:
+        _require_cuda(out)
+        if not 0 <= offset or offset + K > out.shape[1]:
+            raise ValueError(f"columns [{offset}, {offset + K}) do not fit an output of {out.shape[1]}")
+        P = out
     kept = torch.empty(K, dtype=torch.int64, device=dev)
     ws = torch.empty(lib.vbm_build_workspace_size(G, J), dtype=torch.uint8, device=dev)
     opts = L.vbm_build_opts(0 if s_mode == "paper" else 1, delta, opacity_min, opacity_max, int(isotropic),
                             int(unit_weight))
-    st = lib.vbm_build_gaussians(coeffs.data_ptr(), G, J, bank.data_ptr(), K, C.byref(opts), gaussians_struct(P),
-                                 kept.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev))
+    st = lib.vbm_build_gaussians(coeffs.data_ptr(), G, J, bank.data_ptr(), K, C.byref(opts),
+                                 gaussians_struct(P, offset), kept.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev))
     L.check(st, "vbm_build_gaussians")
     return P, kept
 
@@ -314,16 +323,65 @@ def adam_step(raw, m, v, grads, act, lr=LR_DEFAULT, step: int = 1, step_dev: tor
     L.check(st, "vbm_adam_step")
 
 
-def dvr_render(vol: torch.Tensor, tf, cams, step_vox: float = 0.5) -> torch.Tensor:
-    """Ray-marched images of vol [G, G, G] for each camera, concatenated planar [3][H][W] per view."""
+def dvr_render(vol: torch.Tensor, tf, cams, step_vox: float = 0.5, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Ray-marched images of vol [G, G, G] for each camera, concatenated planar [3][H][W] per view
+    (written into ``out`` when given)."""
     lib = L.load()
     _require_cuda(vol)
     G = vol.shape[0]
     views = (L.vbm_view * len(cams))(*[make_view(c) for c in cams])
     n = sum(3 * c.width * c.height for c in cams)
-    out = torch.empty(n, dtype=torch.float32, device=vol.device)
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=vol.device)
+    elif out.numel() != n or out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError(f"dvr_render: out must be {n} contiguous float32 values")
     t = make_tf(*tf)
     st = lib.vbm_dvr_render(vol.contiguous().data_ptr(), G, C.byref(t), views, len(cams), step_vox, out.data_ptr(),
                             _stream(vol.device))
     L.check(st, "vbm_dvr_render")
+    return out
+
+
+# ----------------------------------------------------------------------------------- visual modes
+# Sec. 4.4: a series of transfer functions TF_h, each non-zero only on its own value interval of F,
+# gives one radiance field RF_h = TF_h(F) per visual mode and one Gaussian set G_h per field.  The
+# sets live side by side in one parameter buffer as the scenes of one batch, so all modes are
+# fine-tuned in the same launches; afterwards they are rendered separately (one scene per mode) or
+# concatenated (one scene holding every column).
+
+def build_mode_sets(vol: torch.Tensor, tfs, J: int, wavelet: str, K, s_mode: str = "paper", **build_kw):
+    """One Gaussian set per transfer function (each given as (xs, rgba)), built from the wavelet
+    coefficients of TF_h(vol) and written into consecutive columns of one buffer.  K is one count
+    for every mode or one per mode.  Returns (P [14, sum K], scene_offsets int64 [n_modes + 1],
+    kept: list of int64 [K_h] packed indices)."""
+    _require_cuda(vol)
+    G = vol.shape[-1]
+    Ks = [int(K)] * len(tfs) if np.ndim(K) == 0 else [int(k) for k in K]
+    if len(Ks) != len(tfs) or not tfs:
+        raise ValueError("one count per transfer function")
+    offsets = np.concatenate([[0], np.cumsum(Ks)]).astype(np.int64)
+    _, packed = bank_build(wavelet, J)
+    P = torch.zeros(N_ROWS, int(offsets[-1]), dtype=torch.float32, device=vol.device)
+    kept = []
+    for h, tf in enumerate(tfs):
+        coeffs = dwt3d(vol, J, wavelet, tf)
+        _, kh = build_gaussians(coeffs, G, J, packed, Ks[h], s_mode=s_mode, out=P, offset=int(offsets[h]),
+                                **build_kw)
+        kept.append(kh)
+        del coeffs
+    return P, offsets, kept
+
+
+def mode_views(cams, n_modes: int):
+    """Views of a mode batch: every camera once per mode, mode-major.  Returns (cams, view_scene)."""
+    return [c for _ in range(n_modes) for c in cams], [h for h in range(n_modes) for _ in cams]
+
+
+def dvr_render_modes(vol: torch.Tensor, tfs, cams, step_vox: float = 0.5) -> torch.Tensor:
+    """Supervision images of a mode batch: the DVR of every RF_h from every camera, mode-major (the
+    view order of mode_views)."""
+    n = sum(3 * c.width * c.height for c in cams)
+    out = torch.empty(len(tfs) * n, dtype=torch.float32, device=vol.device)
+    for h, tf in enumerate(tfs):
+        dvr_render(vol, tf, cams, step_vox, out=out[h * n:(h + 1) * n])
     return out

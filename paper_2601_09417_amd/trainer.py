@@ -8,6 +8,8 @@
     batched  every view (and scene) in one launch per phase, counts kept on the device
     graph    the batched step captured once in a HIP graph and replayed
   All three produce identical pair lists and images; gradients agree up to float atomics order.
+* ``render_images`` -- a forward-only batch render with exactly counted pair lists (used to render
+  the visual-mode sets concatenated or separately after fine-tuning).
 * ``autotune``   -- times the batched step for each (tile, radix digit) candidate and picks the
   fastest; run before capture, on a copy of the parameters.
 """
@@ -160,6 +162,28 @@ class FineTuner:
 
     def loss(self) -> float:
         return float(self.loss_fn.loss.item())
+
+
+def render_images(P: torch.Tensor, cams, scene_offsets=None, view_scene=None, tile: int = 16,
+                  sort_bits: int = 8) -> torch.Tensor:
+    """Forward render of a batch with complete pair lists: counts every view's pairs exactly (one
+    exact-mode forward per view), then renders all views in one batched forward planned for that
+    count.  Returns the images, planar [3][H][W] per view, concatenated."""
+    N = P.shape[1]
+    so = np.asarray(scene_offsets if scene_offsets is not None else [0, N], np.int64)
+    vs = list(view_scene) if view_scene is not None else [0] * len(cams)
+    total = 0
+    for v, cam in enumerate(cams):
+        rp = api.plan_batch([cam], so, [vs[v]], tile, sort_bits, 1, "exact", P.device)
+        out = api.render_fwd(rp, P)
+        torch.cuda.synchronize(P.device)
+        total += int(out.status[1].item())
+    rp = api.plan_batch(cams, so, vs, tile, sort_bits, max(total, 1), "batched", P.device)
+    out = api.render_fwd(rp, P)
+    torch.cuda.synchronize(P.device)
+    if int(out.status[0].item()) != 0:
+        raise RuntimeError("render_images: the batched forward dropped pairs")
+    return out.image
 
 
 TUNE_CANDIDATES = ((16, 8), (8, 8), (32, 8), (16, 4))

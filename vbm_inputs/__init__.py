@@ -7,7 +7,7 @@ path can both consume its outputs without sharing method code.
 
 Every generator is seeded with ``numpy.random.SeedSequence([config_index, stream])``
 with the streams: 0 volume, 1 noise, 2 transfer function, 3 cameras, 4 FD subset,
-5 random Gaussian sets.
+5 random Gaussian sets, 6 visual-mode transfer functions.
 """
 from __future__ import annotations
 
@@ -16,7 +16,7 @@ import math
 
 import numpy as np
 
-STREAM_VOLUME, STREAM_NOISE, STREAM_TF, STREAM_CAMERAS, STREAM_FD, STREAM_GAUSS = range(6)
+STREAM_VOLUME, STREAM_NOISE, STREAM_TF, STREAM_CAMERAS, STREAM_FD, STREAM_GAUSS, STREAM_MODES = range(7)
 
 
 def rng(config_index: int, stream: int) -> np.random.Generator:
@@ -140,6 +140,58 @@ def transfer_function(config_index: int, n_points: int = 6) -> TransferFunction:
     a[0] = 0.0
     rgba = np.concatenate([rgb, a[:, None]], axis=1).astype(np.float32)
     return TransferFunction(xs=xs, rgba=rgba)
+
+
+def mode_intervals(vol: np.ndarray, n_modes: int = 5, q_lo: float = 0.5) -> np.ndarray:
+    """Value intervals of the visual modes: edges at n_modes + 1 equally spaced quantiles of the
+    volume's values from q_lo to 1, so each mode covers the same number of voxels of the upper
+    part of the value distribution.  float32 [n_modes + 1], strictly increasing."""
+    e = np.quantile(np.asarray(vol, np.float64).reshape(-1), np.linspace(q_lo, 1.0, n_modes + 1))
+    e = e.astype(np.float32)
+    if not np.all(np.diff(e) > 0):
+        raise ValueError("mode intervals collapse: the volume has too few distinct values")
+    return e
+
+
+def mode_transfer_functions(vol: np.ndarray, config_index: int, n_modes: int = 5,
+                            q_lo: float = 0.5) -> list:
+    """One transfer function per visual mode, each zero outside its own value interval [a, b].
+
+    Four control points per mode: (a, 0), two seeded interior points at a + (b - a) u with sorted
+    u ~ U(0.15, 0.85), RGB ~ U(0.2, 1), alpha ~ U(0.1, 0.5), and (b, 0); the map is constant (zero)
+    beyond the end points.
+    """
+    edges = mode_intervals(vol, n_modes, q_lo)
+    r = rng(config_index, STREAM_MODES)
+    out = []
+    for h in range(n_modes):
+        a, b = float(edges[h]), float(edges[h + 1])
+        u = np.sort(r.uniform(0.15, 0.85, size=2))
+        xs = np.array([a, a + (b - a) * u[0], a + (b - a) * u[1], b], dtype=np.float32)
+        rgba = np.zeros((4, 4), dtype=np.float32)
+        rgba[1:3, :3] = r.uniform(0.2, 1.0, size=(2, 3))
+        rgba[1:3, 3] = r.uniform(0.1, 0.5, size=2)
+        if not np.all(np.diff(xs) > 0):
+            raise ValueError("mode interval too narrow for float32 control points")
+        out.append(TransferFunction(xs=xs, rgba=rgba))
+    return out
+
+
+def union_transfer_function(tfs: list) -> TransferFunction:
+    """The sum of transfer functions with disjoint supports, each zero at its end points: the control
+    points of all of them in order, a shared end point (zero in both) taken once."""
+    xs, rgba = [], []
+    for tf in sorted(tfs, key=lambda t: float(t.xs[0])):
+        if float(tf.rgba[0].max()) != 0.0 or float(tf.rgba[-1].max()) != 0.0:
+            raise ValueError("a mode transfer function must be zero at its end points")
+        for x, c in zip(tf.xs, tf.rgba):
+            if xs and float(x) < xs[-1]:
+                raise ValueError("mode transfer functions overlap")
+            if xs and float(x) == xs[-1]:
+                continue                     # shared end point, zero on both sides
+            xs.append(float(x))
+            rgba.append(np.asarray(c, np.float32))
+    return TransferFunction(xs=np.array(xs, np.float32), rgba=np.array(rgba, np.float32))
 
 
 # ----------------------------------------------------------------------------- cameras
