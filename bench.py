@@ -374,13 +374,30 @@ def run_modes(args, wl, vol_d, loss_kind):
                 f" dB, concatenated {concat[-1]:.2f} dB")
         if t % 10 == 0:
             ft.check_capacity()
+    pairs_end, replans = ft.pair_count(), ft.overflows
+    del ft
+    # reference point, not the paper's procedure: the same initial sets concatenated into one scene
+    # and fine-tuned against the union's DVR directly
+    fj = trainer.FineTuner(P, cams, union_targets, loss=loss_kind, lam=0.2, tile=wl["tile"], schedule="graph")
+    joint = []
+    for t in range(1, args.modes + 1):
+        fj.step()
+        if t in at:
+            torch.cuda.synchronize()
+            joint.append(round(psnr(fj.image, union_targets), 3))
+        if t % 10 == 0:
+            fj.check_capacity()
+    log("modes joint (concatenated sets fitted to the union's DVR): " +
+        ", ".join(f"{t}:{p:.2f}" for t, p in zip(at, joint)))
+    del fj
     return dict(n_modes=n, intervals=[round(float(e), 5) for e in edges], gaussians_per_mode=Kh,
                 views_per_mode=V, size=[R, R], build_ms=round(build_ms, 1),
-                step_ms=round(1e3 * t_train / max(args.modes - 1, 1), 3), pairs_at_end=ft.pair_count(), re_plans=ft.overflows,
-                steps=at, psnr_db_separate=sep, psnr_db_concatenated=concat,
+                step_ms=round(1e3 * t_train / max(args.modes - 1, 1), 3), pairs_at_end=pairs_end, re_plans=replans,
+                steps=at, psnr_db_separate=sep, psnr_db_concatenated=concat, psnr_db_joint=joint,
                 note="separate: each mode's views against the DVR of its own transfer function (the image of "
                      "step t, i.e. after t - 1 updates); concatenated: all sets in one scene after t updates "
-                     "against the DVR of the union of the transfer functions")
+                     "against the DVR of the union of the transfer functions; joint: the initial sets "
+                     "concatenated and fine-tuned against the union's DVR (a reference point)")
 
 
 def run_convergence(args, wl, vol_d, tfn, cams, targets, loss_kind):
