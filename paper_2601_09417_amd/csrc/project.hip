@@ -314,15 +314,27 @@ __global__ __launch_bounds__(256) void k_compact_visible(const DevView* __restri
                                                          const uint32_t* __restrict__ ntiles,
                                                          const float* __restrict__ depth,
                                                          const uint32_t* __restrict__ pos,
-                                                         uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                                                         uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   const DevView& v = views[blockIdx.y];
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= v.n_gauss) return;
   const int64_t item = v.item_offset + i;
   if (ntiles[item] == 0) return;
   const uint32_t p = pos[item];
-  keys[p] = (static_cast<uint64_t>(blockIdx.y) << 32) | __float_as_uint(depth[item]);
+  keys[p] = __float_as_uint(depth[item]);   // depth > near plane > 0: sign bit 0
   vals[p] = static_cast<uint32_t>(item);
+}
+
+// The view an item belongs to: the last view whose first item is at or below it (views hold
+// consecutive item ranges in view order; a view with no items shares its start with the next).
+__device__ __forceinline__ int view_of_item(const DevView* __restrict__ views, int n_views, uint32_t item) {
+  int lo = 0, hi = n_views - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (static_cast<uint32_t>(views[mid].item_offset) <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 __global__ __launch_bounds__(256) void k_gather_ntiles(const uint32_t* __restrict__ vals,
@@ -335,11 +347,11 @@ __global__ __launch_bounds__(256) void k_gather_ntiles(const uint32_t* __restric
     out[p] = ntiles[vals[p]];
 }
 
-// Writes each visible item's tiles in (view, depth, item) order.  Pairs past the capacity are
-// dropped and flagged.  Rectangles of at most 32 tiles walk the projection's reach mask per thread;
+// Writes each visible item's tiles in the items' depth order (views interleaved; the stable tile
+// sort that follows yields (tile, depth, item)).  Pairs past the capacity are dropped and flagged.  Rectangles of at most 32 tiles walk the projection's reach mask per thread;
 // larger ones are queued in the block and emitted by whole waves afterwards (64 tiles per round,
 // positions from the ballot of reached tiles).
-__global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views, const uint64_t* __restrict__ keys,
+__global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views, int n_views,
                                               const uint32_t* __restrict__ vals, const uint32_t* __restrict__ offs,
                                               const uint4* __restrict__ bin, const float4* __restrict__ rec,
                                               int tile, uint32_t* __restrict__ counters, int64_t n_max,
@@ -355,7 +367,7 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
     const int64_t p = base + threadIdx.x;
     if (p < n) {
       const uint32_t item = vals[p];
-      const DevView& v = views[keys[p] >> 32];
+      const DevView& v = views[view_of_item(views, n_views, item)];
       const uint4 b = bin[item];
       const uint32_t x0 = b.x & 0xFFFFu, x1 = b.x >> 16, y0 = b.y & 0xFFFFu, y1 = b.y >> 16;
       const uint32_t w = x1 - x0;
@@ -389,7 +401,7 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
     for (uint32_t d = threadIdx.x >> 6; d < n_q; d += 4) {
       const int64_t q = base + s_q[d];
       const uint32_t item = vals[q];
-      const DevView& v = views[keys[q] >> 32];
+      const DevView& v = views[view_of_item(views, n_views, item)];
       const uint4 b = bin[item];
       const uint32_t x0 = b.x & 0xFFFFu, x1 = b.x >> 16, y0 = b.y & 0xFFFFu, y1 = b.y >> 16;
       const uint32_t w = x1 - x0, area = w * (y1 - y0);

@@ -20,10 +20,10 @@ namespace vbm {
 
 __global__ void k_project(const DevView*, int, vbm_gaussians_c, float*, uint32_t*, uint32_t*, float4*, float4*,
                           float*, uint32_t*, uint4*, int64_t);
-__global__ void k_compact_visible(const DevView*, const uint32_t*, const float*, const uint32_t*, uint64_t*,
+__global__ void k_compact_visible(const DevView*, const uint32_t*, const float*, const uint32_t*, uint32_t*,
                                   uint32_t*);
 __global__ void k_gather_ntiles(const uint32_t*, const uint32_t*, const uint32_t*, int64_t, uint32_t*);
-__global__ void k_emit(const DevView*, const uint64_t*, const uint32_t*, const uint32_t*, const uint4*,
+__global__ void k_emit(const DevView*, int, const uint32_t*, const uint32_t*, const uint4*,
                        const float4*, int, uint32_t*, int64_t, int64_t, uint32_t*, uint32_t*);
 __global__ void k_ranges(const uint32_t*, const uint32_t*, int64_t, uint2*);
 __global__ void k_status(const uint32_t*, int32_t*);
@@ -91,8 +91,8 @@ void layout(vbm_plan* p) {
   sz[R_PITEM] = P * 4;
   sz[R_RANGES] = NT * 8;
   sz[R_GRAD2D] = 16 * I * 4;
-  sz[R_VKEYS] = I * 8;
-  sz[R_VKEYS_ALT] = I * 8;
+  sz[R_VKEYS] = I * 4;
+  sz[R_VKEYS_ALT] = I * 4;
   sz[R_VVALS] = I * 4;
   sz[R_VVALS_ALT] = I * 4;
   sz[R_POFFS] = I * 4;
@@ -315,7 +315,7 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
   float4* coef = region<float4>(p, ws, R_COEF);
   float* blue = region<float>(p, ws, R_BLUE);
   uint32_t* visflag = region<uint32_t>(p, ws, R_VISFLAG);
-  uint64_t* vk[2] = {region<uint64_t>(p, ws, R_VKEYS), region<uint64_t>(p, ws, R_VKEYS_ALT)};
+  uint32_t* vk[2] = {region<uint32_t>(p, ws, R_VKEYS), region<uint32_t>(p, ws, R_VKEYS_ALT)};
   uint32_t* vv[2] = {region<uint32_t>(p, ws, R_VVALS), region<uint32_t>(p, ws, R_VVALS_ALT)};
   uint32_t* poffs = region<uint32_t>(p, ws, R_POFFS);
   uint32_t* pt[2] = {region<uint32_t>(p, ws, R_PTILE), region<uint32_t>(p, ws, R_PTILE_ALT)};
@@ -331,15 +331,19 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
                        coef, blue, visflag, region<uint4>(p, ws, R_BIN), I);
     VBM_LAUNCH_CHECK("project");
     VBM_TRY(scan_exclusive_u32(visflag, visflag, I, nullptr, &counters[0], scratch, s));
-    const int view_bits = ceil_log2(p->n_views);
-    const int item_passes = static_cast<int>(ceil_div(32 + view_bits, 8));
-    const int first = item_passes % 2;  // emit into the buffer that leaves the sorted data in slot 0
+    // Visible items sorted by depth alone, all views together: a visible item's depth is positive,
+    // so its float32 bits order like the depths and the sign bit is 0 (31 key bits, 4 passes).
+    // Items of different views interleave, but every tile belongs to one view and the stable tile
+    // sort that follows keeps this order inside each tile: (tile, depth, item).
+    constexpr int kDepthKeyBits = 31;
+    const int item_passes = static_cast<int>(ceil_div(kDepthKeyBits, 8));
+    const int first = item_passes % 2;  // compact into the buffer that leaves the sorted data in slot 0
     hipLaunchKernelGGL(k_compact_visible, dim3(gx, p->n_views), dim3(256), 0, s, views, ntiles, depth, visflag,
                        vk[first], vv[first]);
     VBM_LAUNCH_CHECK("compact_visible");
     bool in_alt = false;
-    VBM_TRY(radix_sort_pairs<uint64_t>(vk[first], vv[first], vk[1 - first], vv[1 - first], I, &counters[0],
-                                       32 + view_bits, 8, scratch, s, &in_alt));
+    VBM_TRY(radix_sort_pairs<uint32_t>(vk[first], vv[first], vk[1 - first], vv[1 - first], I, &counters[0],
+                                       kDepthKeyBits, 8, scratch, s, &in_alt));
     hipLaunchKernelGGL(k_gather_ntiles, dim3(grid_cap(I, 8192)), dim3(256), 0, s, vv[0], ntiles, counters, I, poffs);
     VBM_LAUNCH_CHECK("gather_ntiles");
     VBM_TRY(scan_exclusive_u32(poffs, poffs, I, &counters[0], &counters[1], scratch, s));
@@ -360,7 +364,7 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
   const int tile_passes = static_cast<int>(ceil_div(p->tile_key_bits, p->sort_bits));
   const int pfirst = tile_passes % 2;
   if (I > 0 && emit_grid_n > 0) {
-    hipLaunchKernelGGL(k_emit, dim3(grid_cap(emit_grid_n, 16384)), dim3(256), 0, s, views, vk[0], vv[0], poffs,
+    hipLaunchKernelGGL(k_emit, dim3(grid_cap(emit_grid_n, 16384)), dim3(256), 0, s, views, p->n_views, vv[0], poffs,
                        region<uint4>(p, ws, R_BIN), rec, p->tile, counters, I, cap, pt[pfirst], pi[pfirst]);
     VBM_LAUNCH_CHECK("emit");
   }

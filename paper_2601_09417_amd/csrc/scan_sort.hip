@@ -1,8 +1,9 @@
 // Device-wide exclusive scan and stable LSD radix sort (gfx950, wave64, 256-thread blocks).
 //
 // Scan: reduce -> single-workgroup scan of the block sums -> per-block scan with the block
-// offset added.  Sort: per pass a digit histogram per 4096-key tile, an exclusive scan of the
-// digit-major histogram (digit * n_tiles + tile), then a stable scatter that ranks equal digits
+// offset added.  Sort: per pass a digit histogram per 4096-key tile, an exclusive scan of every
+// digit's row of the digit-major histogram (one block per digit, which also yields the digit
+// totals), then a stable scatter that ranks equal digits
 // inside each wave with ballots (a lane's rank = set bits of its digit-match mask below it) and
 // across a wave's rounds through per-wave LDS counters, partitions the tile in LDS, and writes it
 // out in digit order (coalesced runs).
@@ -21,6 +22,10 @@ constexpr int kChunk = kThreads * kItems;  // elements per block
 constexpr int kWaves = kThreads / 64;
 static_assert(kThreads == 256, "one thread per 8-bit digit in the scatter's LDS bookkeeping");
 
+__device__ __forceinline__ bool aligned16(const void* p) {
+  return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+}
+
 __device__ __forceinline__ int64_t active_count(int64_t n_max, const uint32_t* n_dev) {
   if (!n_dev) return n_max;
   int64_t n = static_cast<int64_t>(*n_dev);
@@ -33,7 +38,15 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const T* __restrict__ 
   const int64_t n = active_count(n_max, n_dev);
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kChunk;
   T acc = 0;
-  if (base < n) {
+  if (sizeof(T) == 4 && base + kChunk <= n && aligned16(in)) {
+    // a full block of 32-bit values: four 16-byte loads per thread, consecutive across the wave
+    const uint4* src = reinterpret_cast<const uint4*>(in + base);
+#pragma unroll
+    for (int r = 0; r < kItems / 4; ++r) {
+      const uint4 q = src[r * kThreads + threadIdx.x];
+      acc += static_cast<T>(q.x) + static_cast<T>(q.y) + static_cast<T>(q.z) + static_cast<T>(q.w);
+    }
+  } else if (base < n) {
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       int64_t i = base + r * kThreads + threadIdx.x;
@@ -78,21 +91,54 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const T* __restrict__ in
   const int64_t n = active_count(n_max, n_dev);
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kChunk;
   if (base >= n) return;  // uniform per block
+  // A full block of 32-bit values moves as four 16-byte vectors per thread (thread t owns
+  // elements [16 t, 16 t + 16) of the block, as in the general path).
+  const bool vec = sizeof(T) == 4 && base + kChunk <= n && aligned16(in) && aligned16(out);
   T items[kItems];
   T acc = 0;
+  if (vec) {
+    const uint4* src = reinterpret_cast<const uint4*>(in + base) + threadIdx.x * (kItems / 4);
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    int64_t i = base + static_cast<int64_t>(threadIdx.x) * kItems + r;
-    items[r] = i < n ? in[i] : T(0);
-    acc += items[r];
+    for (int r = 0; r < kItems / 4; ++r) {
+      const uint4 q = src[r];
+      items[4 * r] = static_cast<T>(q.x);
+      items[4 * r + 1] = static_cast<T>(q.y);
+      items[4 * r + 2] = static_cast<T>(q.z);
+      items[4 * r + 3] = static_cast<T>(q.w);
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      int64_t i = base + static_cast<int64_t>(threadIdx.x) * kItems + r;
+      items[r] = i < n ? in[i] : T(0);
+    }
   }
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) acc += items[r];
   T tot;
   T ex = block_excl_scan(acc, &tot) + block_offsets[blockIdx.x];
+  if (vec) {
+    uint4* dst = reinterpret_cast<uint4*>(out + base) + threadIdx.x * (kItems / 4);
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    int64_t i = base + static_cast<int64_t>(threadIdx.x) * kItems + r;
-    if (i < n) out[i] = ex;
-    ex += items[r];
+    for (int r = 0; r < kItems / 4; ++r) {
+      uint4 q;
+      q.x = static_cast<uint32_t>(ex);
+      ex += items[4 * r];
+      q.y = static_cast<uint32_t>(ex);
+      ex += items[4 * r + 1];
+      q.z = static_cast<uint32_t>(ex);
+      ex += items[4 * r + 2];
+      q.w = static_cast<uint32_t>(ex);
+      ex += items[4 * r + 3];
+      dst[r] = q;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      int64_t i = base + static_cast<int64_t>(threadIdx.x) * kItems + r;
+      if (i < n) out[i] = ex;
+      ex += items[r];
+    }
   }
 }
 
@@ -128,6 +174,35 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const K* __restrict__ k
   for (int d = threadIdx.x; d < radix; d += kThreads) hist[static_cast<int64_t>(d) * n_blocks + blockIdx.x] = s_hist[d];
 }
 
+// Exclusive scan of one digit's row of the digit-major histogram (the digit's count in every
+// tile, in tile order), in place; block d handles digit d and writes the digit's total.  The
+// scatter adds the exclusive scan of the totals, so one launch replaces a device-wide scan.
+__global__ __launch_bounds__(kThreads) void k_radix_digit_scan(uint32_t* __restrict__ hist, int64_t n_blocks,
+                                                               uint32_t* __restrict__ totals) {
+  uint32_t* row = hist + static_cast<int64_t>(blockIdx.x) * n_blocks;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < n_blocks; base += kChunk) {
+    uint32_t items[kItems];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const int64_t i = base + static_cast<int64_t>(threadIdx.x) * kItems + r;
+      items[r] = i < n_blocks ? row[i] : 0u;
+      acc += items[r];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(acc, &tot) + carry;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const int64_t i = base + static_cast<int64_t>(threadIdx.x) * kItems + r;
+      if (i < n_blocks) row[i] = ex;
+      ex += items[r];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
 // Stable scatter of one 4096-key tile.  Wave w owns keys [1024 w, 1024 w + 1024) and ranks them
 // in 16 rounds of 64 against its own LDS digit counters: a lane's rank among the round's equal
 // digits comes from ballots, and the wave's LDS operations complete in issue order, so a round
@@ -138,7 +213,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const K* __restrict__ k
 template <class K>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                             K* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                            const uint32_t* __restrict__ offsets, int64_t n_max,
+                                                            const uint32_t* __restrict__ offsets,
+                                                            const uint32_t* __restrict__ digit_totals, int64_t n_max,
                                                             const uint32_t* n_dev, int shift, int bits,
                                                             int64_t n_blocks) {
   constexpr int kPerWave = kChunk / kWaves;
@@ -156,8 +232,14 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const K* __restrict_
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   for (int x = threadIdx.x; x < kWaves * 256; x += kThreads) (&s_cnt[0][0])[x] = 0;
-  if (static_cast<int>(threadIdx.x) < radix)
-    s_glob[threadIdx.x] = offsets[static_cast<int64_t>(threadIdx.x) * n_blocks + blockIdx.x];
+  {
+    // global start of digit d's run from this tile: all keys of lower digits, plus digit d's keys
+    // in the lower tiles
+    const bool has = static_cast<int>(threadIdx.x) < radix;
+    uint32_t all;
+    const uint32_t below = block_excl_scan(has ? digit_totals[threadIdx.x] : 0u, &all);
+    if (has) s_glob[threadIdx.x] = below + offsets[static_cast<int64_t>(threadIdx.x) * n_blocks + blockIdx.x];
+  }
   K keys[kItems];
   uint32_t vals[kItems];
 #pragma unroll
@@ -268,7 +350,7 @@ vbm_status fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s) {
 size_t radix_scratch_bytes(int64_t n_max, int digit_bits) {
   const int64_t nb = ceil_div(n_max > 0 ? n_max : 1, kChunk);
   const int64_t hist = static_cast<int64_t>(1 << digit_bits) * nb;
-  return align_up(static_cast<size_t>(hist) * 4, 256) + scan_scratch_bytes(hist);
+  return align_up(static_cast<size_t>(hist) * 4, 256) + 256 * 4;
 }
 
 template <class K>
@@ -283,7 +365,8 @@ vbm_status radix_sort_pairs(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t n_
   const int64_t nb = ceil_div(n_max, kChunk);
   const int64_t hist_n = static_cast<int64_t>(1 << digit_bits) * nb;
   uint32_t* hist = static_cast<uint32_t*>(scratch);
-  void* scan_scratch = static_cast<char*>(scratch) + align_up(static_cast<size_t>(hist_n) * 4, 256);
+  uint32_t* totals = reinterpret_cast<uint32_t*>(static_cast<char*>(scratch) +
+                                                 align_up(static_cast<size_t>(hist_n) * 4, 256));
   K* kin = k0;
   uint32_t* vin = v0;
   K* kout = k1;
@@ -292,10 +375,10 @@ vbm_status radix_sort_pairs(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t n_
     const int bits = (end_bit - shift) < digit_bits ? (end_bit - shift) : digit_bits;
     hipLaunchKernelGGL(k_radix_hist<K>, dim3(nb), dim3(kThreads), 0, s, kin, hist, n_max, n_dev, shift, bits, nb);
     VBM_LAUNCH_CHECK("radix_hist");
-    const int64_t hn = static_cast<int64_t>(1 << bits) * nb;
-    VBM_TRY(scan_exclusive_u32(hist, hist, hn, nullptr, nullptr, scan_scratch, s));
-    hipLaunchKernelGGL(k_radix_scatter<K>, dim3(nb), dim3(kThreads), 0, s, kin, vin, kout, vout, hist, n_max, n_dev,
-                       shift, bits, nb);
+    hipLaunchKernelGGL(k_radix_digit_scan, dim3(1 << bits), dim3(kThreads), 0, s, hist, nb, totals);
+    VBM_LAUNCH_CHECK("radix_digit_scan");
+    hipLaunchKernelGGL(k_radix_scatter<K>, dim3(nb), dim3(kThreads), 0, s, kin, vin, kout, vout, hist, totals, n_max,
+                       n_dev, shift, bits, nb);
     VBM_LAUNCH_CHECK("radix_scatter");
     K* tk = kin;
     kin = kout;
