@@ -142,10 +142,19 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const T* __restrict__ in
   }
 }
 
+// Fills n values; a 16-byte aligned buffer is written as 16-byte vectors plus a scalar tail.
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
-  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t first = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (; i < n; i += stride) p[i] = v;
+  if (aligned16(p)) {
+    const int64_t n4 = n >> 2;
+    uint4* q = reinterpret_cast<uint4*>(p);
+    const uint4 vv = make_uint4(v, v, v, v);
+    for (int64_t i = first; i < n4; i += stride) q[i] = vv;
+    for (int64_t i = 4 * n4 + first; i < n; i += stride) p[i] = v;
+  } else {
+    for (int64_t i = first; i < n; i += stride) p[i] = v;
+  }
 }
 
 // ------------------------------------------------------------------ radix sort
@@ -340,7 +349,7 @@ vbm_status scan_exclusive_u64(const uint64_t* in, uint64_t* out, int64_t n_max, 
 
 vbm_status fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s) {
   if (n <= 0) return VBM_OK;
-  int64_t blocks = ceil_div(n, 256);
+  int64_t blocks = ceil_div(ceil_div(n, 4), 256);
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, p, value, n);
   VBM_LAUNCH_CHECK("fill_u32");
