@@ -80,3 +80,117 @@ def adaptive_check(coeffs_np, G, J, kept_gpu, stats_gpu, K_tot, **kw):
         assert int(S["C"][b]) == s["C"] and int(S["K"][b]) == s["K"] and int(S["kept"][b]) == s["kept"], b
     assert np.array_equal(kept_gpu, kept_o)
     return kept_o, so
+
+
+def oracle_gaussians(vol, tf, J, wav, K):
+    """The oracle's Gaussian set for a volume: its FP64 DWT of TF(F) per channel, rounded to float32
+    (the coefficients both sides select from), its top-K and its construction (s_mode none), as a
+    float32 GaussianSet.  Returns (coefficients float32 [4][G^3], kept, construction dict, set)."""
+    from oracle import bank as obank
+    from oracle import construct as oconstruct
+    from oracle import dwt as odwt
+    from oracle import select as oselect
+    from oracle import tf as otf
+    G = vol.shape[0]
+    rf = otf.apply(vol, tf.xs, tf.rgba)                       # [4][z][y][x] FP64
+    coeffs = np.empty((4, G ** 3), np.float32)
+    for c in range(4):
+        coeffs[c] = odwt.pack(odwt.dwt3d(rf[c], J, wav), G, J)
+    del rf
+    Ks = [K] if np.ndim(K) == 0 else list(K)
+    out = []
+    for k in Ks:
+        kept = oselect.topk(coeffs, k)
+        ref = oconstruct.construct(coeffs, kept, G, J, obank.build_bank(wav, J), s_mode="none")
+        f = np.float32
+        gs = vi.GaussianSet(ref["means"].astype(f), ref["scales"].astype(f), ref["quats"].astype(f),
+                            ref["opacity"].astype(f), ref["rgb"].astype(f))
+        out.append((kept, ref, gs))
+    return coeffs, out
+
+
+def sampled_tile_parity(rp, P, gs, cams, view_scene, scene_offsets, tile, sample_views, n_random, seed):
+    """Forward and backward of one planned batch against the oracle on sampled tiles.
+
+    For every sampled view: the oracle's pair lists of the view's scene (float32 decisions), the
+    GPU lists of n_random random non-empty tiles and of the view's longest tile compared bit for bit,
+    and their images compared with the oracle's FP64 compositing.  Then dL/dI is random on those
+    tiles and zero elsewhere, so every Gaussian's gradient is the oracle's autodiff over the same
+    tiles (and exactly zero for Gaussians in none of them).  Returns the sampled tiles, the GPU
+    gradient [14][N], the involved Gaussians and the oracle's gradient of those ({group: [rows][n]})."""
+    from oracle import binning, render
+    from paper_2601_09417_amd import api
+    out = api.render_fwd(rp, P)
+    torch.cuda.synchronize()
+    assert int(out.status[0]) == 0, "pair capacity overflow"
+    N = P.shape[1]
+    so = np.asarray(scene_offsets, np.int64)
+    toff = binning.tile_grid(cams, tile)
+    ioff = binning.item_offsets(view_scene, so)
+    ptile = rp.region("pair_tile", torch.int32).cpu().numpy()
+    pitem = rp.region("pair_item", torch.int32).cpu().numpy() & ITEM_MASK
+    ranges = rp.region("ranges", torch.int32).cpu().numpy().reshape(-1, 2)
+    imgs = [t.cpu().numpy() for t in api.split_views(out.image, cams)]
+    rng = np.random.default_rng(seed)
+    dL = [np.zeros((3, c.height, c.width), np.float32) for c in cams]
+    tiles = []                  # (view, scene-global Gaussian indices of the list, pixel xs, ys, dL values)
+    err_img, img_max = 0.0, 0.0
+    for v in sample_views:
+        cam, s = cams[v], view_scene[v]
+        s0, s1 = int(so[s]), int(so[s + 1])
+        sub = gs.subset(np.arange(s0, s1))
+        ref = binning.pair_lists(sub, [cam], tile)
+        TX = -(-cam.width // tile)
+        lens = ref["ranges"][:, 1] - ref["ranges"][:, 0]
+        nonempty = np.nonzero(lens > 0)[0]
+        pick = rng.choice(nonempty, min(n_random, nonempty.size), replace=False)
+        for lt in np.unique(np.concatenate([pick, [int(np.argmax(lens))]])):
+            a, b = ref["ranges"][lt]
+            ga, gb = ranges[toff[v] + lt]
+            assert gb - ga == b - a, (v, lt, gb - ga, b - a)
+            assert np.array_equal(ptile[ga:gb], np.full(b - a, toff[v] + lt))
+            local = ref["item"][a:b]
+            assert np.array_equal(pitem[ga:gb] - ioff[v], local), (v, lt)
+            glob = s0 + local
+            xs, ys = render._tile_pixels(cam, tile, int(lt % TX), int(lt // TX))
+            it = torch.as_tensor(glob, dtype=torch.int64)
+            m2d, con, _ = render.project_fp64(render._t(gs.means)[:, it], render._t(gs.scales)[:, it],
+                                              render._t(gs.quats)[:, it], cam)
+            pix = torch.stack([render._t(xs + 0.5), render._t(ys + 0.5)], 1)
+            col, _, _, fl, _ = render.composite_tile(pix, m2d, con, render._t(gs.opacity)[it],
+                                                     render._t(gs.rgb)[:, it].T, render._t(cam.bg))
+            col, fl = col.numpy(), fl.numpy()
+            err_img = max(err_img, float(np.abs(imgs[v][:, ys, xs].T - col)[~fl].max(initial=0.0)))
+            img_max = max(img_max, float(np.abs(col).max()))
+            d = rng.normal(size=(3, xs.size)).astype(np.float32)
+            d[:, fl] = 0.0
+            dL[v][:, ys, xs] = d
+            tiles.append((v, glob, xs, ys, d))
+    assert err_img <= IMG_TOL * max(img_max, 1e-6), (err_img, img_max)
+    say(f"  {len(tiles)} sampled tiles in {len(sample_views)} views: image error {err_img / max(img_max, 1e-6):.2e}")
+
+    g = api.render_bwd(rp, P, flat(dL), out).cpu().numpy()
+    involved = np.unique(np.concatenate([t[1] for t in tiles]))
+    assert np.all(np.delete(g, involved, axis=1) == 0.0)
+    inv = torch.as_tensor(involved, dtype=torch.int64)
+    leaf = {k: render._t(np.asarray(getattr(gs, k), np.float64))[..., inv].clone().requires_grad_(True)
+            for k in ("means", "scales", "quats", "opacity", "rgb")}
+    pos = {int(gi): i for i, gi in enumerate(involved)}
+    total = 0.0
+    for v, glob, xs, ys, d in tiles:
+        loc = torch.as_tensor([pos[int(i)] for i in glob], dtype=torch.int64)
+        m2d, con, _ = render.project_fp64(leaf["means"][:, loc], leaf["scales"][:, loc], leaf["quats"][:, loc],
+                                          cams[v])
+        pix = torch.stack([render._t(xs + 0.5), render._t(ys + 0.5)], 1)
+        col, _, _, _, _ = render.composite_tile(pix, m2d, con, leaf["opacity"][loc], leaf["rgb"][:, loc].T,
+                                                render._t(cams[v].bg))
+        total = total + (col * render._t(d.T.astype(np.float64))).sum()
+    total.backward()
+    oracle_grad = {}
+    for name, rows in ROWS.items():
+        r = leaf[name].grad.numpy().reshape(rows.stop - rows.start, -1)
+        e = group_error(g[rows][:, involved], r)
+        say(f"  grad {name}: {e:.2e} over {involved.size} Gaussians")
+        assert e <= GRAD_TOL, name
+        oracle_grad[name] = r
+    return tiles, g, involved, oracle_grad

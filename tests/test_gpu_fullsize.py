@@ -1,65 +1,49 @@
-"""GPU parity at the benchmark's full size.
+"""GPU parity at the benchmark's full size and at the large-batch size.
 
-Workload: the 512^3 turbulence volume and its transfer function, bior4.4 J=5, the top 1,000,000
-Gaussians, 8 orbit views at 1920x1080, 16x16 tiles, one batched launch over all views (the launch
-configuration bench.py times).  The oracle computes the whole FP64 DWT of TF(F) (about a minute on
-the host); its float32 rounding is the input both sides select from, and the oracle's own top-K
-and construction give the Gaussian set both sides render.  Checked against the oracle:
+Workloads: the 512^3 turbulence volume and its transfer function, bior4.4 J=5; the benchmark's top
+1,000,000 Gaussians with 8 orbit views at 1920x1080, and the large batch's top 2,000,000 with 16
+views at 1920x1080; 16x16 tiles, one batched launch over all views (the launch configuration
+bench.py times).  The oracle computes the whole FP64 DWT of TF(F) once (about a minute on the
+host); its float32 rounding is the input both sides select from, and the oracle's own top-K and
+construction give the Gaussian sets both sides render.  Checked against the oracle:
 
 * DWT: every coefficient of the GPU's transform of the same volume (per subband, relative to the
   subband maximum);
-* selection: the complete top-K set (bit-exact) and every constructed Gaussian, and the adaptive
+* selection: the complete top-K sets (bit-exact) and every constructed Gaussian, and the adaptive
   per-subband selection with all its statistics;
-* rendering: two views' pair lists (bit-exact) and the images of sampled tiles; for the backward,
-  dL/dI is nonzero only on those tiles, so the oracle's autodiff over the same tiles gives every
-  Gaussian's exact gradient.
+* rendering: sampled views' pair lists of sampled tiles (bit-exact) and their images; for the
+  backward, dL/dI is nonzero only on those tiles, so the oracle's autodiff over the same tiles gives
+  every Gaussian's exact gradient.
 """
 import numpy as np
 import pytest
 import torch
 
 import vbm_inputs as vi
-from oracle import bank as obank
-from oracle import binning, render
-from oracle import construct as oconstruct
 from oracle import dwt as odwt
-from oracle import select as oselect
-from oracle import tf as otf
-from tests.gpu_common import GRAD_TOL, IMG_TOL, ITEM_MASK, ROWS, adaptive_check, dev, group_error, say
+from tests.gpu_common import ROWS, adaptive_check, dev, oracle_gaussians, sampled_tile_parity, say
 
 # the module fixture runs the oracle's full-size DWT once: allow for it in the first test's limit
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
-G, J, WAV, K = 512, 5, "bior4.4", 1_000_000
-VIEWS, W, H, TILE = 8, 1920, 1080, 16
+G, J, WAV = 512, 5, "bior4.4"
+W, H, TILE = 1920, 1080, 16
+CASES = {"1M-8views": dict(K=1_000_000, views=8, sample=(1, 6)),
+         "2M-16views": dict(K=2_000_000, views=16, sample=(3, 12))}
 
 
 @pytest.fixture(scope="module")
 def h_case():
     from paper_2601_09417_amd import api
-    say("full size: the 512^3 volume and the oracle's FP64 DWT of TF(F)")
+    say("full size: the 512^3 volume, the oracle's FP64 DWT of TF(F), its top-1M and top-2M sets")
     vol = vi.volume_for_config(3)
     tfn = vi.transfer_function(3)
-    rf = otf.apply(vol, tfn.xs, tfn.rgba)                       # [4][z][y][x] FP64
-    coeffs = np.empty((4, G ** 3), np.float32)
-    for c in range(4):
-        coeffs[c] = odwt.pack(odwt.dwt3d(rf[c], J, WAV), G, J)
-        say(f"  oracle DWT channel {c} done")
-    del rf
-    kept_o = oselect.topk(coeffs, K)
-    ref = oconstruct.construct(coeffs, kept_o, G, J, obank.build_bank(WAV, J), s_mode="none")
-    f = np.float32
-    gs = vi.GaussianSet(ref["means"].astype(f), ref["scales"].astype(f), ref["quats"].astype(f),
-                        ref["opacity"].astype(f), ref["rgb"].astype(f))
-    say("  oracle top-K and construction done")
+    coeffs, sets = oracle_gaussians(vol, tfn, J, WAV, [c["K"] for c in CASES.values()])
+    say("  oracle DWT, top-K and construction done")
     gpu_coeffs = api.dwt3d(torch.from_numpy(vol).to(dev()), J, WAV, (tfn.xs, tfn.rgba))
-    coeffs_d = torch.from_numpy(coeffs).to(dev())
-    _, packed = api.bank_build(WAV, J)
-    P_built, kept = api.build_gaussians(coeffs_d, G, J, packed, K, s_mode="none")
-    P = api.pack_params(gs.means, gs.scales, gs.quats, gs.opacity, gs.rgb, dev())
     torch.cuda.synchronize()
-    return dict(api=api, coeffs=coeffs, coeffs_d=coeffs_d, gpu_coeffs=gpu_coeffs, kept_o=kept_o, ref=ref,
-                P_built=P_built, kept=kept, gs=gs, P=P, cams=vi.orbit_cameras(VIEWS, W, H))
+    return dict(api=api, coeffs=coeffs, coeffs_d=torch.from_numpy(coeffs).to(dev()), gpu_coeffs=gpu_coeffs,
+                sets=dict(zip(CASES, sets)))
 
 
 def test_fullsize_dwt_every_coefficient(h_case):
@@ -75,11 +59,16 @@ def test_fullsize_dwt_every_coefficient(h_case):
     say(f"  {G ** 3} coefficients x 4 channels within {worst:.1e} of their subband maximum")
 
 
-def test_fullsize_selection_and_construction(h_case):
-    assert np.array_equal(h_case["kept"].cpu().numpy(), h_case["kept_o"])
-    Pn = h_case["P_built"].cpu().numpy()
+@pytest.mark.parametrize("case", list(CASES))
+def test_fullsize_selection_and_construction(h_case, case):
+    api = h_case["api"]
+    kept_o, ref, _ = h_case["sets"][case]
+    _, packed = api.bank_build(WAV, J)
+    P, kept = api.build_gaussians(h_case["coeffs_d"], G, J, packed, CASES[case]["K"], s_mode="none")
+    assert np.array_equal(kept.cpu().numpy(), kept_o)
+    Pn = P.cpu().numpy()
     for name, rows in ROWS.items():
-        r = h_case["ref"][name].reshape(rows.stop - rows.start, -1)
+        r = ref[name].reshape(rows.stop - rows.start, -1)
         err = np.abs(Pn[rows] - r).max() / max(np.abs(r).max(), 1e-6)
         assert err <= 1e-6, (name, err)
 
@@ -88,79 +77,22 @@ def test_fullsize_adaptive_selection(h_case):
     """The adaptive per-subband selection on the full coefficient set (36 subbands, 134M locations)
     against the oracle on the same float32 coefficients, budget 1M."""
     api = h_case["api"]
+    K = CASES["1M-8views"]["K"]
     kept, stats = api.adaptive_select(h_case["coeffs_d"], G, J, K)
     kept_o, so = adaptive_check(h_case["coeffs"], G, J, kept.cpu().numpy(), stats.cpu().numpy(), K)
     say(f"  adaptive: kept {kept_o.size} (budget {K}), T of the finest subbands "
         f"{[round(float(s['T']), 5) for s in so[-7:]]}")
 
 
-def test_fullsize_render_sampled_tiles(h_case):
-    api, P, cams, gs = h_case["api"], h_case["P"], h_case["cams"], h_case["gs"]
+@pytest.mark.parametrize("case", list(CASES))
+def test_fullsize_render_sampled_tiles(h_case, case):
+    api = h_case["api"]
+    _, _, gs = h_case["sets"][case]
+    cfg = CASES[case]
+    cams = vi.orbit_cameras(cfg["views"], W, H)
+    P = api.pack_params(gs.means, gs.scales, gs.quats, gs.opacity, gs.rgb, dev())
     N = P.shape[1]
-    rp = api.plan_batch(cams, [0, N], tile=TILE, sort_bits=8, pair_capacity=32_000_000, mode="batched")
-    out = api.render_fwd(rp, P)
-    torch.cuda.synchronize()
-    assert int(out.status[0]) == 0
-    toff = binning.tile_grid(cams, TILE)
-    ptile = rp.region("pair_tile", torch.int32).cpu().numpy()
-    pitem = rp.region("pair_item", torch.int32).cpu().numpy() & ITEM_MASK        # marks above bit 26
-    ranges = rp.region("ranges", torch.int32).cpu().numpy().reshape(-1, 2)
-    imgs = [t.cpu().numpy() for t in api.split_views(out.image, cams)]
-    rng = np.random.default_rng(33)
-    dL = [np.zeros((3, H, W), np.float32) for _ in cams]
-    tiles = []                                              # (view, tx, ty, items, pixel xs, ys, flagged)
-    err_img, img_max = 0.0, 0.0
-    for v in (1, 6):
-        ref = binning.pair_lists(gs, [cams[v]], TILE)
-        TX = -(-W // TILE)
-        nonempty = np.nonzero(ref["ranges"][:, 1] > ref["ranges"][:, 0])[0]
-        longest = int(np.argmax(ref["ranges"][:, 1] - ref["ranges"][:, 0]))
-        for lt in np.unique(np.concatenate([rng.choice(nonempty, 10, replace=False), [longest]])):
-            s, e = ref["ranges"][lt]
-            gs_, ge_ = ranges[toff[v] + lt]
-            assert np.array_equal(ptile[gs_:ge_], np.full(e - s, toff[v] + lt))
-            items = ref["item"][s:e]
-            assert np.array_equal(pitem[gs_:ge_] - v * N, items)            # view v's items start at v*N
-            tx, ty = int(lt % TX), int(lt // TX)
-            xs, ys = render._tile_pixels(cams[v], TILE, tx, ty)
-            it = torch.as_tensor(items, dtype=torch.int64)
-            m2d, con, _ = render.project_fp64(render._t(gs.means)[:, it], render._t(gs.scales)[:, it],
-                                              render._t(gs.quats)[:, it], cams[v])
-            pix = torch.stack([render._t(xs + 0.5), render._t(ys + 0.5)], 1)
-            col, _, _, fl, _ = render.composite_tile(pix, m2d, con, render._t(gs.opacity)[it],
-                                                     render._t(gs.rgb)[:, it].T, render._t(cams[v].bg))
-            col, fl = col.numpy(), fl.numpy()
-            ok = ~fl
-            err_img = max(err_img, float(np.abs(imgs[v][:, ys, xs].T - col)[ok].max(initial=0.0)))
-            img_max = max(img_max, float(np.abs(col).max()))
-            d = rng.normal(size=(3, xs.size)).astype(np.float32)
-            d[:, fl] = 0.0
-            dL[v][:, ys, xs] = d
-            tiles.append((v, items, xs, ys, d))
-    assert err_img <= IMG_TOL * max(img_max, 1e-6), (err_img, img_max)
-    say(f"  {len(tiles)} sampled tiles: image error {err_img / max(img_max, 1e-6):.2e}")
-
-    flat = torch.from_numpy(np.concatenate([d.reshape(-1) for d in dL])).to(dev())
-    g = api.render_bwd(rp, P, flat, out).cpu().numpy()
-    involved = np.unique(np.concatenate([t[1] for t in tiles]))
-    outside = np.setdiff1d(np.arange(N), involved)
-    assert np.all(g[:, outside] == 0.0)
-    inv = torch.as_tensor(involved, dtype=torch.int64)
-    leaf = {k: render._t(np.asarray(getattr(gs, k), np.float64))[..., inv].clone().requires_grad_(True)
-            for k in ("means", "scales", "quats", "opacity", "rgb")}
-    pos = {int(gi): i for i, gi in enumerate(involved)}
-    total = 0.0
-    for v, items, xs, ys, d in tiles:
-        loc = torch.as_tensor([pos[int(i)] for i in items], dtype=torch.int64)
-        m2d, con, _ = render.project_fp64(leaf["means"][:, loc], leaf["scales"][:, loc], leaf["quats"][:, loc],
-                                          cams[v])
-        pix = torch.stack([render._t(xs + 0.5), render._t(ys + 0.5)], 1)
-        col, _, _, _, _ = render.composite_tile(pix, m2d, con, leaf["opacity"][loc], leaf["rgb"][:, loc].T,
-                                                render._t(cams[v].bg))
-        total = total + (col * render._t(d.T.astype(np.float64))).sum()
-    total.backward()
-    for name, rows in ROWS.items():
-        r = leaf[name].grad.numpy().reshape(rows.stop - rows.start, -1)
-        e = group_error(g[rows][:, involved], r)
-        say(f"  grad {name}: {e:.2e}")
-        assert e <= GRAD_TOL, name
+    say(f"  {case}: {N} Gaussians, {cfg['views']} views {W}x{H}")
+    rp = api.plan_batch(cams, [0, N], tile=TILE, sort_bits=8, pair_capacity=8_000_000 * cfg["views"],
+                        mode="batched")
+    sampled_tile_parity(rp, P, gs, cams, [0] * len(cams), [0, N], TILE, cfg["sample"], 10, 33)
