@@ -46,6 +46,17 @@ BYTES_PER_PAIR_BWD, BYTES_PER_PIXEL_BWD = 76, 20
 ADAPTIVE_BYTES_PER_COEF = 16 + 4 + 12 * 4 + 3 * 4
 
 WORKLOADS = {
+    "c0": dict(config=0, G=32, J=1, wavelet="haar", K=2048, views=1, W=64, H=64, tile=16, loss="l1",
+               desc="32^3 blobs, Haar J=1, top-2048 Gaussians, one 64x64 view, L1, Adam"),
+    "c3": dict(config=3, G=512, J=5, wavelet="bior4.4", K=2_000_000, views=16, W=1920, H=1080, tile=16,
+               loss="l1_dssim", desc="512^3 turbulence (E(k)~k^-5/3, kmax 64), bior4.4 J=5, top-2M Gaussians, "
+                                     "16 orbit views 1920x1080, loss 0.8 L1 + 0.2 D-SSIM, Adam"),
+    "c4": dict(config=4, wavelet="bior4.4", tile=16, loss="l1_dssim", views_per_scene=4,
+               scenes=[dict(G=64, J=3, K=50_000, W=512, H=512), dict(G=128, J=3, K=200_000, W=800, H=800),
+                       dict(G=256, J=4, K=800_000, W=1280, H=720), dict(G=384, J=5, K=1_500_000, W=1920, H=1080)],
+               desc="4 scenes (64^3/128^3/256^3/384^3 blobs + k^-2 noise, one transfer function, bior4.4 "
+                    "J=3/3/4/5, top 50k/200k/800k/1.5M Gaussians), 4 orbit views each at 512x512/800x800/"
+                    "1280x720/1920x1080, all 16 in one batch, loss 0.8 L1 + 0.2 D-SSIM, Adam"),
     "H": dict(config=3, G=512, J=5, wavelet="bior4.4", K=1_000_000, views=8, W=1920, H=1080, tile=16,
               loss="l1_dssim", desc="512^3 turbulence (E(k)~k^-5/3, kmax 64), bior4.4 J=5, top-1M Gaussians, "
                                     "8 orbit views 1920x1080, loss 0.8 L1 + 0.2 D-SSIM, Adam"),
@@ -56,7 +67,22 @@ WORKLOADS = {
                                      "1024x1024, loss 0.8 L1 + 0.2 D-SSIM, Adam"),
 }
 # checkpoints (steps) of the --convergence ablation runs
-CONVERGENCE_AT = (1, 10, 25, 50, 100, 200, 400, 800)
+CONVERGENCE_AT = (1, 10, 25, 50, 100, 200, 400, 800, 1000)
+
+
+def workload_shape(wl) -> str:
+    if "scenes" in wl:
+        sc = wl["scenes"]
+        return (f"{sum(x['K'] for x in sc)} Gaussians in {len(sc)} scenes, {wl['views_per_scene'] * len(sc)} views "
+                + "/".join(f"{x['W']}x{x['H']}" for x in sc))
+    return f"{wl['K']} Gaussians, {wl['W']}x{wl['H']}, {wl['views']} views"
+
+
+def workload_config(wl) -> dict:
+    if "scenes" in wl:
+        return {"gaussians": [x["K"] for x in wl["scenes"]], "views": [wl["views_per_scene"]] * len(wl["scenes"]),
+                "width": [x["W"] for x in wl["scenes"]], "height": [x["H"] for x in wl["scenes"]]}
+    return {"gaussians": wl["K"], "views": wl["views"], "width": wl["W"], "height": wl["H"]}
 
 
 def log(msg: str) -> None:
@@ -187,6 +213,8 @@ def run_gpu(args, wl):
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if "scenes" in wl:
+        return run_gpu_scenes(args, wl, out, timed_step_runs)
     t0 = time.perf_counter()
     vol = vi.volume_for_config(wl["config"])
     tfn = vi.transfer_function(wl["config"])
@@ -222,89 +250,7 @@ def run_gpu(args, wl):
     torch.cuda.synchronize()
     log(f"init {out['init_ms']:.1f} ms; targets ready")
 
-    def timed(ft, steps, warmup):
-        for _ in range(warmup):
-            ft.step()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t = time.perf_counter()
-        e0.record()
-        for _ in range(steps):
-            ft.step()
-        e1.record()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t
-        return wall, e0.elapsed_time(e1) / 1e3
-
-    # schedule knobs: the autotuner times each (tile, radix digit) candidate on the eager batched
-    # step before anything is captured or timed
-    loss_kind = wl["loss"] if args.loss == "default" else args.loss
-    if args.tile == "auto":
-        tune = trainer.autotune(P, cams, targets, loss=loss_kind, lam=0.2)
-        tile, bits = tune["tile"], tune["sort_bits"]
-        out["autotune"] = [dict(tile=d["tile"], sort_bits=d["sort_bits"], ms=round(d["ms"], 3)) for d in tune["table"]]
-        log("autotune: " + ", ".join(f"tile {d['tile']}/{d['sort_bits']}b {d['ms']:.2f} ms" for d in tune["table"])
-            + f" -> tile {tile}, {bits}-bit digits")
-    else:
-        tile, bits = int(args.tile), 8
-    out["tile"], out["sort_bits"], out["loss_kind"] = tile, bits, loss_kind
-
-    # batched schedule, captured as a graph: the reported value
-    ft = trainer.FineTuner(P, cams, targets, loss=loss_kind, lam=0.2, tile=tile, sort_bits=bits, schedule="graph")
-    wall, ev = timed(ft, args.steps, args.warmup)
-    if ft.overflowed():
-        raise RuntimeError("pair capacity overflow during the timed region")
-    out["batched_wall_s"], out["batched_event_s"] = wall, ev
-    out["pairs_per_step"] = ft.pair_count()
-    out["loss"] = ft.loss()
-    log(f"batched(graph): {args.steps / wall:.2f} it/s, pairs {out['pairs_per_step']}")
-    del ft
-
-    # kernel-level timing of the compositing kernels on the eager batched schedule
-    fb = trainer.FineTuner(P, cams, targets, loss=loss_kind, lam=0.2, tile=tile, sort_bits=bits, schedule="batched")
-    for _ in range(args.warmup):
-        fb.step()
-    # one untimed step with the counting kernel variants (evaluations and contributions) ...
-    counters = torch.zeros(4, dtype=torch.int64, device=dev)
-    lib.vbm_profile_counters(counters.data_ptr())
-    fb.step()
-    lib.vbm_profile_counters(None)
-    # ... then K steps of the timing variants, each compositing launch bracketed by HIP events
-    evs = []
-    torch.cuda.synchronize()
-    for i in range(args.steps):
-        quad = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        for e in quad:
-            e.record()  # creates the underlying event
-        lib.vbm_profile_events(*[e.cuda_event for e in quad])
-        fb.step()
-        evs.append(quad)
-    lib.vbm_profile_events(None, None, None, None)
-    torch.cuda.synchronize()
-    fwd_ms = float(np.mean([q[0].elapsed_time(q[1]) for q in evs]))
-    bwd_ms = float(np.mean([q[2].elapsed_time(q[3]) for q in evs]))
-    c = counters.cpu().numpy().astype(np.float64)
-    npx = sum(cc.width * cc.height for cc in cams)
-    P_pairs = out["pairs_per_step"]
-    out["kernels"] = {
-        "composite_fwd": dict(ms=fwd_ms, evals=c[0], contrib=c[1],
-                              tflops=(FLOPS_FWD_EVAL * c[0] + FLOPS_FWD_USED * c[1]) / (fwd_ms * 1e-3) / 1e12,
-                              gbs=(BYTES_PER_PAIR_FWD * P_pairs + BYTES_PER_PIXEL_FWD * npx) / (fwd_ms * 1e-3) / 1e9),
-        "composite_bwd": dict(ms=bwd_ms, evals=c[2], contrib=c[3],
-                              tflops=(FLOPS_BWD_EVAL * c[2] + FLOPS_BWD_USED * c[3]) / (bwd_ms * 1e-3) / 1e12,
-                              gbs=(BYTES_PER_PAIR_BWD * P_pairs + BYTES_PER_PIXEL_BWD * npx) / (bwd_ms * 1e-3) / 1e9),
-    }
-    log(f"composite fwd {fwd_ms:.2f} ms, bwd {bwd_ms:.2f} ms per launch")
-    del fb
-
-    # plain schedule: one view per launch, one host sync per view forward
-    if not args.skip_plain:
-        fp = trainer.FineTuner(P, cams, targets, loss=loss_kind, lam=0.2, tile=tile, sort_bits=bits, schedule="plain")
-        wall_p, _ = timed(fp, args.steps, args.warmup)
-        out["plain_wall_s"] = wall_p
-        log(f"plain: {args.steps / wall_p:.2f} it/s")
-        del fp
-
+    loss_kind = timed_step_runs(args, out, P, cams, targets, wl, None, None)
     if args.convergence > 0:
         out["convergence"] = run_convergence(args, wl, vol_d, tfn, cams, targets, loss_kind)
     if args.modes > 0:
@@ -400,6 +346,148 @@ def run_modes(args, wl, vol_d, loss_kind):
                      "concatenated and fine-tuned against the union's DVR (a reference point)")
 
 
+def timed_step_runs(args, out, P, cams, targets, wl, scene_offsets, view_scene):
+    """Autotune (optional), the graph-captured batched step (the reported value), the compositing
+    kernels' event times and counts on the eager batched step, and the plain schedule."""
+    import torch
+
+    from paper_2601_09417_amd import _lib as L
+    from paper_2601_09417_amd import trainer
+
+    dev = P.device
+    lib = L.load()
+    so, vs = scene_offsets, view_scene
+
+    def timed(ft, steps, warmup):
+        for _ in range(warmup):
+            ft.step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            ft.step()
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        return wall, e0.elapsed_time(e1) / 1e3
+
+    # schedule knobs: the autotuner times each (tile, radix digit) candidate on the eager batched
+    # step before anything is captured or timed
+    loss_kind = wl["loss"] if args.loss == "default" else args.loss
+    if args.tile == "auto":
+        tune = trainer.autotune(P, cams, targets, so, vs, loss=loss_kind, lam=0.2)
+        tile, bits = tune["tile"], tune["sort_bits"]
+        out["autotune"] = [dict(tile=d["tile"], sort_bits=d["sort_bits"], ms=round(d["ms"], 3)) for d in tune["table"]]
+        log("autotune: " + ", ".join(f"tile {d['tile']}/{d['sort_bits']}b {d['ms']:.2f} ms" for d in tune["table"])
+            + f" -> tile {tile}, {bits}-bit digits")
+    else:
+        tile, bits = int(args.tile), 8
+    out["tile"], out["sort_bits"], out["loss_kind"] = tile, bits, loss_kind
+
+    # batched schedule, captured as a graph: the reported value
+    ft = trainer.FineTuner(P, cams, targets, so, vs, loss=loss_kind, lam=0.2,
+                           tile=tile, sort_bits=bits, schedule="graph")
+    wall, ev = timed(ft, args.steps, args.warmup)
+    if ft.overflowed():
+        raise RuntimeError("pair capacity overflow during the timed region")
+    out["batched_wall_s"], out["batched_event_s"] = wall, ev
+    out["pairs_per_step"] = ft.pair_count()
+    out["loss"] = ft.loss()
+    log(f"batched(graph): {args.steps / wall:.2f} it/s, pairs {out['pairs_per_step']}")
+    del ft
+
+    # kernel-level timing of the compositing kernels on the eager batched schedule
+    fb = trainer.FineTuner(P, cams, targets, so, vs, loss=loss_kind, lam=0.2,
+                           tile=tile, sort_bits=bits, schedule="batched")
+    for _ in range(args.warmup):
+        fb.step()
+    # one untimed step with the counting kernel variants (evaluations and contributions) ...
+    counters = torch.zeros(4, dtype=torch.int64, device=dev)
+    lib.vbm_profile_counters(counters.data_ptr())
+    fb.step()
+    lib.vbm_profile_counters(None)
+    # ... then K steps of the timing variants, each compositing launch bracketed by HIP events
+    evs = []
+    torch.cuda.synchronize()
+    for i in range(args.steps):
+        quad = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        for e in quad:
+            e.record()  # creates the underlying event
+        lib.vbm_profile_events(*[e.cuda_event for e in quad])
+        fb.step()
+        evs.append(quad)
+    lib.vbm_profile_events(None, None, None, None)
+    torch.cuda.synchronize()
+    fwd_ms = float(np.mean([q[0].elapsed_time(q[1]) for q in evs]))
+    bwd_ms = float(np.mean([q[2].elapsed_time(q[3]) for q in evs]))
+    c = counters.cpu().numpy().astype(np.float64)
+    npx = sum(cc.width * cc.height for cc in cams)
+    P_pairs = out["pairs_per_step"]
+    out["kernels"] = {
+        "composite_fwd": dict(ms=fwd_ms, evals=c[0], contrib=c[1],
+                              tflops=(FLOPS_FWD_EVAL * c[0] + FLOPS_FWD_USED * c[1]) / (fwd_ms * 1e-3) / 1e12,
+                              gbs=(BYTES_PER_PAIR_FWD * P_pairs + BYTES_PER_PIXEL_FWD * npx) / (fwd_ms * 1e-3) / 1e9),
+        "composite_bwd": dict(ms=bwd_ms, evals=c[2], contrib=c[3],
+                              tflops=(FLOPS_BWD_EVAL * c[2] + FLOPS_BWD_USED * c[3]) / (bwd_ms * 1e-3) / 1e12,
+                              gbs=(BYTES_PER_PAIR_BWD * P_pairs + BYTES_PER_PIXEL_BWD * npx) / (bwd_ms * 1e-3) / 1e9),
+    }
+    log(f"composite fwd {fwd_ms:.2f} ms, bwd {bwd_ms:.2f} ms per launch")
+    del fb
+
+    # plain schedule: one view per launch, one host sync per view forward
+    if not args.skip_plain:
+        fp = trainer.FineTuner(P, cams, targets, so, vs, loss=loss_kind, lam=0.2,
+                               tile=tile, sort_bits=bits, schedule="plain")
+        wall_p, _ = timed(fp, args.steps, args.warmup)
+        out["plain_wall_s"] = wall_p
+        log(f"plain: {args.steps / wall_p:.2f} it/s")
+        del fp
+
+    return loss_kind
+
+
+def run_gpu_scenes(args, wl, out, step_runs):
+    """The uneven multi-scene batch: every scene's volume, DWT and top-K build written into one
+    parameter buffer, each scene seen by its own orbit views at its own resolution, DVR targets per
+    view, all views in one batch."""
+    import torch
+
+    import vbm_inputs as vi
+    from paper_2601_09417_amd import api
+
+    if args.convergence or args.modes:
+        raise SystemExit("--convergence and --modes take a single-scene workload")
+    dev = torch.device("cuda:0")
+    tfn = vi.transfer_function(wl["config"])
+    Ks = [sc["K"] for sc in wl["scenes"]]
+    so = np.concatenate([[0], np.cumsum(Ks)]).astype(np.int64)
+    P = torch.zeros(api.N_ROWS, int(so[-1]), dtype=torch.float32, device=dev)
+    cams, view_scene, targets = [], [], []
+    init_ms = 0.0
+    for s_, sc in enumerate(wl["scenes"]):
+        vol_d = torch.from_numpy(vi.scene_volume(wl["config"], s_, sc["G"])).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        coeffs = api.dwt3d(vol_d, sc["J"], wl["wavelet"], (tfn.xs, tfn.rgba))
+        _, packed = api.bank_build(wl["wavelet"], sc["J"])
+        api.build_gaussians(coeffs, sc["G"], sc["J"], packed, sc["K"], s_mode="none", out=P, offset=int(so[s_]))
+        torch.cuda.synchronize()
+        init_ms += (time.perf_counter() - t0) * 1e3
+        del coeffs
+        c = vi.orbit_cameras(wl["views_per_scene"], sc["W"], sc["H"], azimuth0=0.4 * s_)
+        targets.append(api.dvr_render(vol_d, (tfn.xs, tfn.rgba), c))
+        cams += c
+        view_scene += [s_] * len(c)
+        del vol_d
+    targets = torch.cat(targets)
+    torch.cuda.synchronize()
+    out["init_ms"] = init_ms
+    log(f"init {init_ms:.1f} ms for {len(Ks)} scenes; targets ready")
+    step_runs(args, out, P, cams, targets, wl, so, view_scene)
+    return out
+
+
 def run_convergence(args, wl, vol_d, tfn, cams, targets, loss_kind):
     """PSNR against the DVR targets over training for the method and its ablation variants (Sec. 5):
     without the transition bank's covariances, without the energy projection, with Haar instead of
@@ -491,7 +579,7 @@ def main() -> int:
 
     # start the CPU oracle before anything touches the GPU in this process
     proc = queue = None
-    if rank0 and not args.no_cpu_baseline:
+    if rank0 and not args.no_cpu_baseline and "scenes" not in wl:
         ctx = mp.get_context("spawn")
         queue = ctx.Queue()
         proc = ctx.Process(target=cpu_baseline_worker, args=(queue, args.workload, args.cpu_tiles, args.cpu_threads),
@@ -518,8 +606,7 @@ def main() -> int:
                if args.workload == "H" and gpu["tile"] == 16 and gpu["loss_kind"] == wl["loss"] else None)
     result = {
         "metric": (METRIC if args.workload == "H" else
-                   f"fine-tune iters/sec (fwd+bwd, {wl['K']} Gaussians, {wl['W']}x{wl['H']}, {wl['views']} views) "
-                   "batched vs plain"),
+                   "fine-tune iters/sec (fwd+bwd, " + workload_shape(wl) + ") batched vs plain"),
         "value": round(value, 4),
         "unit": "iters/sec",
         "n_gpus": 1,
@@ -531,9 +618,8 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {wl['desc']}", "gaussians": wl["K"], "views": wl["views"],
-                   "width": wl["W"], "height": wl["H"], "tile": gpu["tile"], "sort_bits": gpu["sort_bits"],
-                   "loss": gpu["loss_kind"], "schedule": "batched, HIP graph"},
+        "config": {"workload": f"{args.workload}: {wl['desc']}", **workload_config(wl), "tile": gpu["tile"],
+                   "sort_bits": gpu["sort_bits"], "loss": gpu["loss_kind"], "schedule": "batched, HIP graph"},
         "autotune": gpu.get("autotune"),
         "plain_value": None if plain is None else round(plain, 4),
         "batched_over_plain": None if plain is None else round(value / plain, 3),
