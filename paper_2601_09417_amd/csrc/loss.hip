@@ -66,6 +66,30 @@ __device__ __forceinline__ float block_sum(float v, float* s_red) {
   return t;
 }
 
+// Block order of the SSIM passes.  A run of equal-size views has n_blocks = tiles x 3 channels x
+// views logical blocks (tile fastest).  Consecutive dispatches go to the 8 XCDs in turn and each XCD
+// has its own L2, so dispatch L takes logical block (L mod 8) * ceil(n_blocks / 8) + L / 8: every
+// XCD works through a contiguous run of tiles, and the halo rows and columns that neighbouring
+// tiles share are fetched once into that XCD's L2 instead of once per XCD.  Returns false for the
+// few padding dispatches past the end.
+constexpr int kXcds = 8;
+
+struct SsimBlock {
+  int tile, c, z, bid;
+};
+
+__device__ __forceinline__ bool ssim_block(int tiles, int n_blocks, SsimBlock& b) {
+  const int per = (n_blocks + kXcds - 1) / kXcds;
+  const int d = static_cast<int>(blockIdx.x);
+  const int logical = (d % kXcds) * per + d / kXcds;
+  if (logical >= n_blocks) return false;
+  b.tile = logical % tiles;
+  b.c = (logical / tiles) % 3;
+  b.z = logical / (3 * tiles);
+  b.bid = logical;
+  return true;
+}
+
 // L1 only: dL/dx = scale * sign(x - y); per-block partial of |x - y|.
 __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ x, const float* __restrict__ y, int64_t n,
                                             float scale, float* __restrict__ grad, float* __restrict__ partial) {
@@ -106,13 +130,14 @@ __device__ __forceinline__ void load_halo(const float* const (&src)[NF], int W, 
   }
 }
 
-// Pass 1 of SSIM over a run of views of equal size: grid (tiles per view, 3 channels, views),
-// 256 threads, 32x32 outputs per block.  SSIM needs E[x^2] and E[y^2] only through their sum (in
+// Pass 1 of SSIM over a run of views of equal size: one block per (tile, channel, view) in the
+// order of ssim_block, 256 threads, 32x32 outputs per block.  SSIM needs E[x^2] and E[y^2] only through their sum (in
 // sigma_x^2 + sigma_y^2, and d/dx of the sum is that of E[x^2]), so four signals are filtered:
 // x, y, x^2 + y^2 and x y.  Their horizontally filtered maps over the (TY + 10) x TX halo rows are
 // staged in LDS; each thread then filters a 4-row strip of one column vertically.
 __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, const float* __restrict__ y, int W,
-                                                   int H, int tiles_x, Window win, float* __restrict__ p1,
+                                                   int H, int tiles_x, int tiles, int n_blocks, Window win,
+                                                   float* __restrict__ p1,
                                                    float* __restrict__ p2, float* __restrict__ p3,
                                                    float* __restrict__ partial_s, float* __restrict__ partial_l1) {
   // The filtered maps 2 and 3 overlay the input halo: the horizontal pass holds them in registers
@@ -124,10 +149,12 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
   auto hb = reinterpret_cast<float(*)[EY][TX]>(lds);
   auto sx = sxy[0];
   auto sy = sxy[1];
-  const int c = blockIdx.y;
-  const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
+  SsimBlock blk;
+  if (!ssim_block(tiles, n_blocks, blk)) return;
+  const int c = blk.c;
+  const int bx = blk.tile % tiles_x, by = blk.tile / tiles_x;
   const int64_t HW = static_cast<int64_t>(W) * H;
-  const int64_t chan = (3 * static_cast<int64_t>(blockIdx.z) + c) * HW;
+  const int64_t chan = (3 * static_cast<int64_t>(blk.z) + c) * HW;
   const int ox = bx * TX - RAD, oy = by * TY - RAD;
   {
     const float* const src[2] = {x + chan, y + chan};
@@ -228,7 +255,7 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
       sval += sv;
     }
   }
-  const int64_t bid = (static_cast<int64_t>(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const int64_t bid = blk.bid;
   const float ts = block_sum(sval, s_red);
   if (threadIdx.x == 0) partial_s[bid] = ts;
   __syncthreads();
@@ -239,7 +266,8 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
 // Pass 2: dL/dx = w_l1 sign(x - y) - w_ssim [w*p1 + 2 x (w*p2) + y (w*p3)], same tiling; the
 // horizontal pass filters four adjacent columns per task, reading each input once for all four.
 __global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ x, const float* __restrict__ y, int W,
-                                                   int H, int tiles_x, Window win, const float* __restrict__ p1,
+                                                   int H, int tiles_x, int tiles, int n_blocks, Window win,
+                                                   const float* __restrict__ p1,
                                                    const float* __restrict__ p2, const float* __restrict__ p3,
                                                    float w_l1, float w_ssim, float* __restrict__ grad) {
   // Filtered maps 1 and 2 overlay the input halo (held in registers until it has been read).
@@ -247,10 +275,12 @@ __global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ x, 
   __shared__ float lds[kMap + 3 * kHalo];
   auto sp = reinterpret_cast<float(*)[EY][EX + 1]>(lds + kMap);
   auto hb = reinterpret_cast<float(*)[EY][TX]>(lds);
-  const int c = blockIdx.y;
-  const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
+  SsimBlock blk;
+  if (!ssim_block(tiles, n_blocks, blk)) return;
+  const int c = blk.c;
+  const int bx = blk.tile % tiles_x, by = blk.tile / tiles_x;
   const int64_t HW = static_cast<int64_t>(W) * H;
-  const int64_t chan = (3 * static_cast<int64_t>(blockIdx.z) + c) * HW;
+  const int64_t chan = (3 * static_cast<int64_t>(blk.z) + c) * HW;
   const int ox = bx * TX - RAD, oy = by * TY - RAD;
   {
     const float* const src[3] = {p1 + chan, p2 + chan, p3 + chan};
@@ -444,20 +474,26 @@ extern "C" vbm_status vbm_image_loss(const float* image, const float* target, co
   const Window win = make_window();
   const float w_l1 = (1.0f - lambda) / static_cast<float>(n);
   const float w_ss = lambda / static_cast<float>(n);
-  // One launch of each pass per run of consecutive views of equal size (grid.z = the run's views;
-  // their images are consecutive); the partial slots keep the view, channel, tile order.
+  // One launch of each pass per run of consecutive views of equal size (their images are
+  // consecutive); the partial slots keep the view, channel, tile order.
   int64_t off = 0, boff = 0;
   for (int v = 0; v < n_views;) {
     const int W = dims[2 * v], H = dims[2 * v + 1];
     int nv = 1;
     while (v + nv < n_views && nv < 65535 && dims[2 * (v + nv)] == W && dims[2 * (v + nv) + 1] == H) ++nv;
     const int tx = static_cast<int>(ceil_div(W, TX)), ty = static_cast<int>(ceil_div(H, TY));
-    const dim3 grid(static_cast<unsigned>(tx * ty), 3, static_cast<unsigned>(nv));
-    hipLaunchKernelGGL(k_ssim_maps, grid, dim3(256), 0, s, image + off, target + off, W, H, tx, win, p1 + off,
-                       p2 + off, p3 + off, ps + boff, pl + boff);
+    const int64_t nb64 = static_cast<int64_t>(tx) * ty * 3 * nv;
+    if (nb64 > (int64_t{1} << 30)) {
+      set_error("vbm_image_loss: %lld SSIM tiles in one run of views", static_cast<long long>(nb64));
+      return VBM_ERR_UNSUPPORTED;
+    }
+    const int nb = static_cast<int>(nb64);
+    const dim3 grid(static_cast<unsigned>(kXcds * ceil_div(nb, kXcds)));
+    hipLaunchKernelGGL(k_ssim_maps, grid, dim3(256), 0, s, image + off, target + off, W, H, tx, tx * ty, nb, win,
+                       p1 + off, p2 + off, p3 + off, ps + boff, pl + boff);
     VBM_LAUNCH_CHECK("ssim_maps");
-    hipLaunchKernelGGL(k_ssim_grad, grid, dim3(256), 0, s, image + off, target + off, W, H, tx, win, p1 + off,
-                       p2 + off, p3 + off, w_l1, w_ss, grad + off);
+    hipLaunchKernelGGL(k_ssim_grad, grid, dim3(256), 0, s, image + off, target + off, W, H, tx, tx * ty, nb, win,
+                       p1 + off, p2 + off, p3 + off, w_l1, w_ss, grad + off);
     VBM_LAUNCH_CHECK("ssim_grad");
     off += 3 * static_cast<int64_t>(W) * H * nv;
     boff += static_cast<int64_t>(tx) * ty * 3 * nv;
