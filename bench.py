@@ -399,15 +399,18 @@ def timed_step_runs(args, out, P, cams, targets, wl, scene_offsets, view_scene):
     out["pairs_per_step"] = ft.pair_count()
     out["loss"] = ft.loss()
     log(f"batched(graph): {args.steps / wall:.2f} it/s, pairs {out['pairs_per_step']}")
-    # spread: further windows of K replayed steps after the reported one (not part of `value`)
+    del ft
+    # spread: the same measurement repeated (fresh step runner from the same initial parameters, W
+    # warm-up steps, K timed steps); not part of `value`
     reps = [args.steps / wall]
     for _ in range(max(args.repeats - 1, 0)):
-        ft.check_capacity()        # training moves the parameters: re-plan between windows when needed
-        w2, _ = timed(ft, args.steps, 1)
-        if not ft.overflowed():    # a window whose pair lists outgrew the plan is not counted
+        fr = trainer.FineTuner(P, cams, targets, so, vs, loss=loss_kind, lam=0.2,
+                               tile=tile, sort_bits=bits, schedule="graph")
+        w2, _ = timed(fr, args.steps, args.warmup)
+        if not fr.overflowed():
             reps.append(args.steps / w2)
+        del fr
     out["repeats"] = reps
-    del ft
 
     # kernel-level timing of the compositing kernels on the eager batched schedule
     fb = trainer.FineTuner(P, cams, targets, so, vs, loss=loss_kind, lam=0.2,
@@ -579,7 +582,8 @@ def main() -> int:
     ap.add_argument("--mode-views", type=int, default=64, help="supervision views per mode")
     ap.add_argument("--mode-size", type=int, default=512, help="edge of the square mode views")
     ap.add_argument("--repeats", type=int, default=5,
-                    help="windows of K graph steps timed in all (the first gives `value`; all give the spread)")
+                    help="times the graph measurement is made in all, each from the initial parameters (the "
+                         "first gives `value`; all give the spread)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (scales HBM counters)")
     args = ap.parse_args()
