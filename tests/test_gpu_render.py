@@ -227,3 +227,26 @@ def test_forward_is_deterministic_and_accumulate_adds():
     g1 = api.render_bwd(rp, P, dL, b)
     g2 = api.render_bwd(rp, P, dL, b, grads=g1.clone(), accumulate=True)
     assert torch.allclose(g2, 2 * g1, rtol=1e-5, atol=1e-7 * float(g1.abs().max()))
+
+
+def test_autograd_function_matches_oracle():
+    """The torch.autograd.Function around the forward and backward: image = render(P) for a planned
+    batch, a torch loss on it, and P.grad against the oracle's gradient of the same loss."""
+    from paper_2601_09417_amd import trainer
+    api = _api()
+    gs, cams = _scene(1200, 41, 2, 72, 56)
+    say("autograd Function, 2 views 72x56")
+    P = to_dev(gs).requires_grad_(True)
+    rp = api.plan_batch(cams, [0, gs.n], tile=16, pair_capacity=1 << 18)
+    img = trainer.VBMRender.apply(P, rp)
+    batch = render.Batch(gs, cams, 16)
+    ref = render.render_forward(batch)
+    for v, got in enumerate(api.split_views(img.detach(), cams)):
+        assert image_error(got.cpu().numpy(), ref[v]["image"], ref[v]["flagged"]) <= IMG_TOL, v
+    dL = masked_dL(cams, [r["flagged"] for r in ref], seed=42)
+    w = flat(dL)
+    (img * w).sum().backward()
+    g_ref, _ = render.render_backward(batch, dL)
+    G = P.grad.cpu().numpy()
+    for name, rows in ROWS.items():
+        assert group_error(G[rows], g_ref[name].reshape(rows.stop - rows.start, -1)) <= GRAD_TOL, name
