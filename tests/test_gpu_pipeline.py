@@ -248,3 +248,27 @@ def test_construction_ablation_variants(isotropic, unit_weight):
     if isotropic:
         S = P.cpu().numpy()[3:6]
         assert np.all(S == S[0, 0])
+
+
+def test_trainer_replans_after_overflow():
+    """A step whose pair lists outgrow the plan is flagged; check_capacity re-plans from exact counts
+    (and captures the graph again), after which the step renders complete lists: its image equals
+    that of a step runner planned with enough room from the start, given the same parameters."""
+    from paper_2601_09417_amd import trainer
+    gs, cams, tgt = _tuner_inputs(7)
+    api = _api()
+    P = api.pack_params(gs.means, gs.scales, gs.quats, gs.opacity, gs.rgb, dev())
+    say("trainer re-plan after a pair overflow")
+    ft = trainer.FineTuner(P, cams, tgt, schedule="graph", pair_capacity=64)
+    ft.step()
+    torch.cuda.synchronize()
+    assert ft.check_capacity() and ft.overflows == 1
+    assert not ft.check_capacity()          # flags were read and cleared
+    act = ft.act.clone()
+    ft.step()
+    torch.cuda.synchronize()
+    assert not ft.overflowed()
+    ref = trainer.FineTuner(act, cams, tgt, schedule="batched")
+    ref.step()
+    torch.cuda.synchronize()
+    assert torch.equal(ft.image, ref.image)
