@@ -1,13 +1,14 @@
 // Host side of the renderer: batch planning, workspace layout and the launch sequence of
 // vbm_render_fwd / vbm_render_bwd.
 //
-// Forward: project every (view, Gaussian) item -> stable compaction of visible items into
-// (view, depth-bits) keys -> radix sort of those keys (so each view's items are in depth order with
-// item index as the tie-break) -> exclusive scan of tile counts in that order -> emit (tile, item)
-// pairs in view/depth/item order -> stable radix sort by global tile id alone, which leaves every
-// tile's list in (depth, item) order -> tile ranges -> compositing.  Sorting items by depth once and
-// then pairs by tile only needs ceil(tile_bits / digit) passes over the pairs instead of a full
-// 64-bit (tile, depth) key sort.
+// Forward: project every (view, Gaussian) item -> stable compaction of visible items with their
+// float32 depth bits as keys -> radix sort of those 31-bit keys (items in depth order, all views
+// together, item index as the tie-break) -> exclusive scan of tile counts in that order -> emit
+// (tile, item) pairs in depth/item order -> stable radix sort by global tile id alone, which leaves
+// every tile's list (a tile belongs to one view) in (depth, item) order -> tile ranges -> tile
+// launch order, longest lists first -> compositing.  Sorting items by depth once and then pairs by
+// tile only needs ceil(tile_bits / digit) passes over the pairs instead of a full 64-bit
+// (tile, depth) key sort.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
