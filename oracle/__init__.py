@@ -13,6 +13,8 @@ Modules and the passages they follow:
   bank       canonical wavelets, dominant-lobe moments, ridge weight   (Sec. 4.2: eq. canonical_wavelet,
              eq. roi, eq. moment, eq. canonical_gaussian, eq. ridge_regression)
   select     joint-norm global top-K                                   (Supp. A, joint magnitude)
+  adaptive   adaptive per-subband selection: budgets, MAD threshold,   (Supp. A: budget allocation,
+             capped top-K per subband                                   joint sparsification, MAD, top-K)
   construct  per-coefficient Gaussians                                 (Sec. 4.3: eq. per_location_weight,
              eq. wavelet_gaussian_kernel, eq. translation_operator)
   binning    FP32 projection decisions (depth keys, tile rects) and the sorted pair lists
