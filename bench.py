@@ -204,10 +204,10 @@ def run_gpu(args, wl):
 
     import vbm_inputs as vi
     from paper_2601_09417_amd import _lib as L
-    from paper_2601_09417_amd import api, trainer
+    from paper_2601_09417_amd import api
 
     dev = torch.device("cuda:0")
-    lib = L.load()
+    L.load()          # fails loudly when the HIP library is not built
     out = {}
     if args.copy_calibration_mib:
         n = args.copy_calibration_mib * (1 << 20) // 4
