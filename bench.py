@@ -41,9 +41,9 @@ FLOPS_FWD_EVAL, FLOPS_FWD_USED = 17, 8
 FLOPS_BWD_EVAL, FLOPS_BWD_USED = 17, 40
 BYTES_PER_PAIR_FWD, BYTES_PER_PIXEL_FWD = 40, 20   # algorithmic (the lane-group marks written back are not counted)
 BYTES_PER_PAIR_BWD, BYTES_PER_PIXEL_BWD = 76, 20
-# adaptive selection: 16 B read + 4 B key written, twelve select passes and three flag/count
-# passes over the 4-byte keys, per coefficient
-ADAPTIVE_BYTES_PER_COEF = 16 + 4 + 12 * 4 + 3 * 4
+# adaptive selection: 16 B read + 4 B key written, eight select passes (the median and the
+# K_band-th largest share four) and three count/flag/write passes over the 4-byte keys, per coefficient
+ADAPTIVE_BYTES_PER_COEF = 16 + 4 + 8 * 4 + 3 * 4
 
 WORKLOADS = {
     "c0": dict(config=0, G=32, J=1, wavelet="haar", K=2048, views=1, W=64, H=64, tile=16, loss="l1",

@@ -7,7 +7,10 @@
 // block per chunk.  The order statistics (the two medians and the K-th largest joint norm) come
 // from four-pass 8-bit radix selects on float32 bit patterns (non-negative floats order like their
 // bits), run for all subbands at once with per-subband histograms; the two middle ranks of a median
-// are selected side by side.  Every keep/drop decision uses float32 values computed in a fixed
+// are selected side by side, and the K_band-th largest joint norm alongside the median of the
+// joint norms (it does not depend on the threshold: when fewer than K_band values pass T, the
+// K-th largest is the smallest value >= T, which the count pass finds).  Every keep/drop decision
+// uses float32 values computed in a fixed
 // order; energies and budgets are float64.  Per-subband counts are summed from per-chunk counts
 // (no same-address atomics across blocks).  Nothing is read back to the host.
 #include <hip/hip_runtime.h>
@@ -32,9 +35,15 @@ struct BandTable {
   int64_t chunk0[kMaxBands + 1];   // first chunk of each subband; chunk0[nb] = number of chunks
 };
 
+// Select targets: 0 and 1 the two middle ranks (of v, then of |v - median|), 2 the K_band-th
+// largest v (selected alongside the median; active when 1 <= K_band <= N).
+constexpr int kTargets = 3;
+
 struct BandState {
-  uint32_t prefix[2];   // key bits fixed so far, per select target
-  uint32_t rank[2];     // ascending 0-based rank still to find inside the prefix's bucket
+  uint32_t prefix[kTargets];   // key bits fixed so far, per select target
+  uint32_t rank[kTargets];     // ascending 0-based rank still to find inside the prefix's bucket
+  uint32_t use2;               // target 2 active
+  uint32_t vmin;               // smallest v >= T (bit pattern; +inf when none)
   double E, quotient;   // reference energy, K_tot S / sum S
   int64_t K_band;       // max(min_band, floor(quotient))
   float med, mad, sigma, T, vK, thr;
@@ -71,6 +80,16 @@ __device__ __forceinline__ double block_sum_f64(double v, double* s_red) {
   __syncthreads();
   double t = 0.0;
   for (int w = 0; w < kT / 64; ++w) t += s_red[w];
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ uint32_t block_min_u32(uint32_t v, uint32_t* s_red) {
+  for (int d = 32; d >= 1; d >>= 1) v = min(v, static_cast<uint32_t>(__shfl_xor(v, d, 64)));
+  if (lane_id() == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint32_t t = 0xFFFFFFFFu;
+  for (int w = 0; w < kT / 64; ++w) t = min(t, s_red[w]);
   __syncthreads();
   return t;
 }
@@ -150,9 +169,12 @@ __global__ void k_af_budget(BandTable bt, BandState* __restrict__ st, int64_t K_
     const double f = floor(q);
     st[b].quotient = q;
     st[b].K_band = f > static_cast<double>(min_band) ? static_cast<int64_t>(f) : min_band;
-    st[b].prefix[0] = st[b].prefix[1] = 0u;
+    st[b].prefix[0] = st[b].prefix[1] = st[b].prefix[2] = 0u;
     st[b].rank[0] = static_cast<uint32_t>((bt.n[b] - 1) / 2);
     st[b].rank[1] = static_cast<uint32_t>(bt.n[b] / 2);
+    const bool use2 = st[b].K_band >= 1 && st[b].K_band <= bt.n[b];
+    st[b].use2 = use2 ? 1u : 0u;
+    st[b].rank[2] = use2 ? static_cast<uint32_t>(bt.n[b] - st[b].K_band) : 0u;
   }
 }
 
@@ -162,20 +184,23 @@ __device__ __forceinline__ uint32_t select_key(uint32_t v, int mode, float med) 
   return mode == 0 ? v : __float_as_uint(fabsf(__uint_as_float(v) - med));
 }
 
-// Histogram of digit `shift` over the keys whose higher digits match each target's prefix.
+// Histogram of digit `shift` over the keys whose higher digits match each target's prefix (target 2
+// only in the first select, mode 0).  Targets whose prefixes coincide share one histogram.
 __global__ __launch_bounds__(kT) void k_af_hist(const uint32_t* __restrict__ keys, BandTable bt,
                                                const BandState* __restrict__ st, int mode, int shift,
                                                uint32_t* __restrict__ ghist) {
-  __shared__ uint32_t h[kT / 64][2][256];   // one histogram pair per wave: less contention
+  __shared__ uint32_t h[kT / 64][kTargets][256];   // one set per wave: less contention
   const int b = band_of(bt, blockIdx.x);
   int64_t begin, end;
   chunk_range(bt, b, blockIdx.x, begin, end);
-  for (int x = threadIdx.x; x < (kT / 64) * 512; x += kT) (&h[0][0][0])[x] = 0;
+  for (int x = threadIdx.x; x < (kT / 64) * kTargets * 256; x += kT) (&h[0][0][0])[x] = 0;
   __syncthreads();
   const int w = threadIdx.x >> 6;
   const uint32_t hi_mask = shift >= 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
-  const uint32_t p0 = st[b].prefix[0] & hi_mask, p1 = st[b].prefix[1] & hi_mask;
-  const bool same = p0 == p1;   // both targets in one bucket: one histogram serves both
+  const uint32_t p0 = st[b].prefix[0] & hi_mask, p1 = st[b].prefix[1] & hi_mask, p2 = st[b].prefix[2] & hi_mask;
+  const bool same01 = p0 == p1;
+  const bool use2 = mode == 0 && st[b].use2 != 0u;
+  const bool own2 = use2 && p2 != p0 && p2 != p1;   // target 2 needs its own histogram
   const float med = st[b].med;
   for (int r0 = 0; r0 < kPer; r0 += 16) {
     uint32_t kk[16];
@@ -185,44 +210,51 @@ __global__ __launch_bounds__(kT) void k_af_hist(const uint32_t* __restrict__ key
       if (begin + static_cast<int64_t>(r0 + q) * kT + threadIdx.x >= end) continue;
       const uint32_t k = select_key(kk[q], mode, med);
       const uint32_t d = (k >> shift) & 255u;
-      if ((k & hi_mask) == p0) atomicAdd(&h[w][0][d], 1u);
-      else if (!same && (k & hi_mask) == p1) atomicAdd(&h[w][1][d], 1u);
+      const uint32_t hk = k & hi_mask;
+      if (hk == p0) atomicAdd(&h[w][0][d], 1u);
+      else if (!same01 && hk == p1) atomicAdd(&h[w][1][d], 1u);
+      else if (own2 && hk == p2) atomicAdd(&h[w][2][d], 1u);
     }
   }
   __syncthreads();
-  uint32_t c0 = 0, c1 = 0;
+  uint32_t c0 = 0, c1 = 0, c2 = 0;
 #pragma unroll
   for (int ww = 0; ww < kT / 64; ++ww) {
     c0 += h[ww][0][threadIdx.x];
     c1 += h[ww][1][threadIdx.x];
+    c2 += h[ww][2][threadIdx.x];
   }
-  if (same) c1 = c0;
-  uint32_t* g = ghist + static_cast<int64_t>(b) * 512;
+  if (same01) c1 = c0;
+  if (use2 && !own2) c2 = p2 == p0 ? c0 : c1;
+  uint32_t* g = ghist + static_cast<int64_t>(b) * (kTargets * 256);
   if (c0) atomicAdd(&g[threadIdx.x], c0);
   if (c1) atomicAdd(&g[256 + threadIdx.x], c1);
+  if (c2) atomicAdd(&g[512 + threadIdx.x], c2);
 }
 
 // Picks, per subband and target, the digit whose bucket holds the target rank; clears the
 // histograms for the next pass.
 __global__ __launch_bounds__(kT) void k_af_pick(BandState* __restrict__ st, uint32_t* __restrict__ ghist, int shift) {
   const int b = blockIdx.x, d = threadIdx.x;
-  uint32_t* g = ghist + static_cast<int64_t>(b) * 512;
-  const uint32_t h0 = g[d], h1 = g[256 + d];
-  uint32_t tot;
-  const uint32_t below0 = block_excl_scan(h0, &tot);
-  const uint32_t below1 = block_excl_scan(h1, &tot);
-  const uint32_t r0 = st[b].rank[0], r1 = st[b].rank[1];
+  uint32_t* g = ghist + static_cast<int64_t>(b) * (kTargets * 256);
+  uint32_t hv[kTargets], below[kTargets], tot;
+#pragma unroll
+  for (int t = 0; t < kTargets; ++t) {
+    hv[t] = g[256 * t + d];
+    below[t] = block_excl_scan(hv[t], &tot);
+  }
+  uint32_t r[kTargets];
+#pragma unroll
+  for (int t = 0; t < kTargets; ++t) r[t] = st[b].rank[t];
   __syncthreads();
-  if (below0 <= r0 && r0 < below0 + h0) {
-    st[b].prefix[0] |= static_cast<uint32_t>(d) << shift;
-    st[b].rank[0] = r0 - below0;
+#pragma unroll
+  for (int t = 0; t < kTargets; ++t) {
+    if (below[t] <= r[t] && r[t] < below[t] + hv[t]) {
+      st[b].prefix[t] |= static_cast<uint32_t>(d) << shift;
+      st[b].rank[t] = r[t] - below[t];
+    }
+    g[256 * t + d] = 0;
   }
-  if (below1 <= r1 && r1 < below1 + h1) {
-    st[b].prefix[1] |= static_cast<uint32_t>(d) << shift;
-    st[b].rank[1] = r1 - below1;
-  }
-  g[d] = 0;
-  g[256 + d] = 0;
 }
 
 __device__ __forceinline__ float mid_mean(const BandState& s) {
@@ -250,59 +282,73 @@ __global__ void k_af_thresh(BandTable bt, BandState* __restrict__ st, float lamb
   st[b].T = lambda * sigma;
 }
 
-// #(v >= T) per chunk (summed per subband by k_af_band_sum).
+// #(v >= T) and the smallest such v per chunk (combined per subband by k_af_band_sum); keys are
+// non-negative float bit patterns, so their unsigned order is the float order.
 __global__ __launch_bounds__(kT) void k_af_count(const uint32_t* __restrict__ keys, BandTable bt,
-                                                const BandState* __restrict__ st, uint32_t* __restrict__ cnt) {
+                                                const BandState* __restrict__ st, uint32_t* __restrict__ cnt,
+                                                uint32_t* __restrict__ cmin) {
   __shared__ uint32_t s_red[kT / 64];
   const int b = band_of(bt, blockIdx.x);
   int64_t begin, end;
   chunk_range(bt, b, blockIdx.x, begin, end);
   const float T = st[b].T;
-  uint32_t c = 0;
+  uint32_t c = 0, mn = 0xFFFFFFFFu;
   for (int r0 = 0; r0 < kPer; r0 += 16) {
     uint32_t kk[16];
     load16(keys, begin, end, r0, kk);
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
-      c += begin + static_cast<int64_t>(r0 + q) * kT + threadIdx.x < end && __uint_as_float(kk[q]) >= T ? 1u : 0u;
+    for (int q = 0; q < 16; ++q) {
+      const bool in = begin + static_cast<int64_t>(r0 + q) * kT + threadIdx.x < end && __uint_as_float(kk[q]) >= T;
+      c += in ? 1u : 0u;
+      mn = in ? min(mn, kk[q]) : mn;
+    }
   }
   c = block_sum_u32(c, s_red);
-  if (threadIdx.x == 0) cnt[blockIdx.x] = c;
+  mn = block_min_u32(mn, s_red);
+  if (threadIdx.x == 0) {
+    cnt[blockIdx.x] = c;
+    cmin[blockIdx.x] = mn;
+  }
 }
 
-// Sum of the per-chunk counts of each subband (one block per subband) into C (which = 0) or the
-// kept count (which = 1).
-__global__ __launch_bounds__(kT) void k_af_band_sum(BandTable bt, const uint32_t* __restrict__ cnt, int which,
+// Sum of the per-chunk counts of each subband (one block per subband) into C and the smallest
+// v >= T into vmin (which = 0, from k_af_count), or into the kept count (which = 1).
+__global__ __launch_bounds__(kT) void k_af_band_sum(BandTable bt, const uint32_t* __restrict__ cnt,
+                                                   const uint32_t* __restrict__ cmin, int which,
                                                    BandState* __restrict__ st) {
   __shared__ uint32_t s_red[kT / 64];
   const int b = blockIdx.x;
-  uint32_t c = 0;
-  for (int64_t k = bt.chunk0[b] + threadIdx.x; k < bt.chunk0[b + 1]; k += kT) c += cnt[k];
+  uint32_t c = 0, mn = 0xFFFFFFFFu;
+  for (int64_t k = bt.chunk0[b] + threadIdx.x; k < bt.chunk0[b + 1]; k += kT) {
+    c += cnt[k];
+    if (which == 0) mn = min(mn, cmin[k]);
+  }
   c = block_sum_u32(c, s_red);
+  if (which == 0) mn = block_min_u32(mn, s_red);
   if (threadIdx.x == 0) {
-    if (which == 0) st[b].C = c;
-    else st[b].kept = c;
+    if (which == 0) {
+      st[b].C = c;
+      st[b].vmin = mn;
+    } else {
+      st[b].kept = c;
+    }
   }
 }
 
-// K = min(K_band, C); the last select finds the K-th largest joint norm (ascending rank N - K).
-__global__ void k_af_kinit(BandTable bt, BandState* __restrict__ st) {
-  const int b = threadIdx.x;
-  if (b >= bt.nb) return;
-  const int64_t K = st[b].K_band < static_cast<int64_t>(st[b].C) ? st[b].K_band : static_cast<int64_t>(st[b].C);
-  st[b].K = static_cast<uint32_t>(K);
-  st[b].prefix[0] = st[b].prefix[1] = 0u;
-  const uint32_t r = K >= 1 ? static_cast<uint32_t>(bt.n[b] - K) : 0u;
-  st[b].rank[0] = st[b].rank[1] = r;
-}
-
-// Keep threshold max(T, v_(K)), or +inf when K = 0.
+// K = min(K_band, C) and v_(K), the K-th largest joint norm: when K_band <= C it is the K_band-th
+// largest, found by target 2 of the first select; otherwise K = C and the C largest values are
+// exactly those >= T, so v_(C) is the smallest v >= T.  Keep threshold max(T, v_(K)), or +inf when
+// K = 0.
 __global__ void k_af_thr(BandTable bt, BandState* __restrict__ st) {
   const int b = threadIdx.x;
   if (b >= bt.nb) return;
-  const float vK = __uint_as_float(st[b].prefix[0]);
-  st[b].vK = st[b].K >= 1 ? vK : __builtin_inff();
-  st[b].thr = st[b].K >= 1 ? fmaxf(st[b].T, vK) : __builtin_inff();
+  const int64_t C = static_cast<int64_t>(st[b].C);
+  const int64_t K = st[b].K_band < C ? st[b].K_band : C;
+  st[b].K = static_cast<uint32_t>(K);
+  const float vK = K < 1 ? __builtin_inff()
+                         : __uint_as_float(st[b].K_band <= C ? st[b].prefix[2] : st[b].vmin);
+  st[b].vK = vK;
+  st[b].thr = K >= 1 ? fmaxf(st[b].T, vK) : __builtin_inff();
 }
 
 // Kept coefficients per chunk.
@@ -327,20 +373,37 @@ __global__ __launch_bounds__(kT) void k_af_flags(const uint32_t* __restrict__ ke
 
 __global__ __launch_bounds__(kT) void k_af_write(const uint32_t* __restrict__ keys, BandTable bt,
                                                 const BandState* __restrict__ st, const uint32_t* __restrict__ offs,
-                                                int64_t capacity, int64_t* __restrict__ kept) {
+                                                const uint32_t* __restrict__ cnt, int64_t capacity,
+                                                int64_t* __restrict__ kept) {
+  if (cnt[blockIdx.x] == 0) return;   // nothing kept in this chunk (uniform for the block)
   const int b = band_of(bt, blockIdx.x);
   int64_t begin, end;
   chunk_range(bt, b, blockIdx.x, begin, end);
   // Sub-rounds of 4096 coefficients in which each thread owns 16 consecutive ones, so the block's
-  // scan of the per-thread counts numbers the kept ones in ascending index order.
+  // scan of the per-thread counts numbers the kept ones in ascending index order.  A full sub-round
+  // that starts on a 16-byte boundary (subband sizes are cubes of even numbers except for an odd
+  // coarsest side) is read as four 16-byte vectors per thread.
   constexpr int kSub = 16;
   const float thr = st[b].thr;
   int64_t pos0 = static_cast<int64_t>(offs[blockIdx.x]);
   for (int64_t base = begin; base < end; base += kSub * kT) {
     uint32_t f = 0;
-    for (int r = 0; r < kSub; ++r) {
-      const int64_t i = base + static_cast<int64_t>(threadIdx.x) * kSub + r;
-      if (i < end && __uint_as_float(keys[i]) >= thr) f |= 1u << r;
+    const int64_t first = base + static_cast<int64_t>(threadIdx.x) * kSub;
+    if (base + kSub * kT <= end && (reinterpret_cast<uintptr_t>(keys + base) & 15u) == 0) {
+      const uint4* src = reinterpret_cast<const uint4*>(keys + first);
+#pragma unroll
+      for (int q = 0; q < kSub / 4; ++q) {
+        const uint4 k4 = src[q];
+        f |= (__uint_as_float(k4.x) >= thr ? 1u : 0u) << (4 * q);
+        f |= (__uint_as_float(k4.y) >= thr ? 1u : 0u) << (4 * q + 1);
+        f |= (__uint_as_float(k4.z) >= thr ? 1u : 0u) << (4 * q + 2);
+        f |= (__uint_as_float(k4.w) >= thr ? 1u : 0u) << (4 * q + 3);
+      }
+    } else {
+      for (int r = 0; r < kSub; ++r) {
+        const int64_t i = first + r;
+        if (i < end && __uint_as_float(keys[i]) >= thr) f |= 1u << r;
+      }
     }
     uint32_t tot;
     int64_t pos = pos0 + block_excl_scan(static_cast<uint32_t>(__popc(f)), &tot);
@@ -396,6 +459,7 @@ struct AdaptiveWs {
   uint32_t* keys;
   double* epart;
   uint32_t* cnt;
+  uint32_t* cmin;
   uint32_t* offs;
   uint32_t* total;
   BandState* st;
@@ -408,10 +472,11 @@ AdaptiveWs carve(Carver& c, int64_t M, int64_t chunks) {
   w.keys = c.take<uint32_t>(M);
   w.epart = c.take<double>(chunks);
   w.cnt = c.take<uint32_t>(chunks);
+  w.cmin = c.take<uint32_t>(chunks);
   w.offs = c.take<uint32_t>(chunks);
   w.total = c.take<uint32_t>(1);
   w.st = c.take<BandState>(kMaxBands);
-  w.ghist = c.take<uint32_t>(static_cast<size_t>(kMaxBands) * 512);
+  w.ghist = c.take<uint32_t>(static_cast<size_t>(kMaxBands) * kTargets * 256);
   w.scan = c.take<char>(scan_scratch_bytes(chunks));
   return w;
 }
@@ -467,17 +532,16 @@ extern "C" vbm_status vbm_adaptive_select(const float* coeffs, int32_t G, int32_
 
   hipLaunchKernelGGL(k_af_norm, cg, blk, 0, s, coeffs, M, bt, opts->ref_channel, w.keys, w.epart);
   VBM_LAUNCH_CHECK("adaptive_norm");
-  VBM_TRY(fill_u32(w.ghist, 0u, static_cast<int64_t>(kMaxBands) * 512, s));
+  VBM_TRY(fill_u32(w.ghist, 0u, static_cast<int64_t>(kMaxBands) * kTargets * 256, s));
   hipLaunchKernelGGL(k_af_energy, nbg, blk, 0, s, bt, w.epart, w.st);
   VBM_LAUNCH_CHECK("adaptive_energy");
   hipLaunchKernelGGL(k_af_budget, dim3(1), dim3(128), 0, s, bt, w.st, opts->K_tot, opts->alpha, opts->beta,
                      static_cast<int64_t>(opts->min_band));
   VBM_LAUNCH_CHECK("adaptive_budget");
-  // three radix selects: median(v), median(|v - median|), then the K-th largest v
-  for (int sel = 0; sel < 3; ++sel) {
-    const int mode = sel == 1 ? 1 : 0;
+  // two radix selects: median(v) together with the K_band-th largest v, then median(|v - median|)
+  for (int sel = 0; sel < 2; ++sel) {
     for (int shift = 24; shift >= 0; shift -= 8) {
-      hipLaunchKernelGGL(k_af_hist, cg, blk, 0, s, w.keys, bt, w.st, mode, shift, w.ghist);
+      hipLaunchKernelGGL(k_af_hist, cg, blk, 0, s, w.keys, bt, w.st, sel, shift, w.ghist);
       VBM_LAUNCH_CHECK("adaptive_hist");
       hipLaunchKernelGGL(k_af_pick, nbg, blk, 0, s, w.st, w.ghist, shift);
       VBM_LAUNCH_CHECK("adaptive_pick");
@@ -485,26 +549,22 @@ extern "C" vbm_status vbm_adaptive_select(const float* coeffs, int32_t G, int32_
     if (sel == 0) {
       hipLaunchKernelGGL(k_af_median, dim3(1), dim3(128), 0, s, bt, w.st);
       VBM_LAUNCH_CHECK("adaptive_median");
-    } else if (sel == 1) {
-      hipLaunchKernelGGL(k_af_thresh, dim3(1), dim3(128), 0, s, bt, w.st, opts->lambda);
-      VBM_LAUNCH_CHECK("adaptive_thresh");
-      hipLaunchKernelGGL(k_af_count, cg, blk, 0, s, w.keys, bt, w.st, w.cnt);
-      VBM_LAUNCH_CHECK("adaptive_count");
-      hipLaunchKernelGGL(k_af_band_sum, nbg, blk, 0, s, bt, w.cnt, 0, w.st);
-      VBM_LAUNCH_CHECK("adaptive_band_sum");
-      hipLaunchKernelGGL(k_af_kinit, dim3(1), dim3(128), 0, s, bt, w.st);
-      VBM_LAUNCH_CHECK("adaptive_kinit");
-    } else {
-      hipLaunchKernelGGL(k_af_thr, dim3(1), dim3(128), 0, s, bt, w.st);
-      VBM_LAUNCH_CHECK("adaptive_thr");
     }
   }
+  hipLaunchKernelGGL(k_af_thresh, dim3(1), dim3(128), 0, s, bt, w.st, opts->lambda);
+  VBM_LAUNCH_CHECK("adaptive_thresh");
+  hipLaunchKernelGGL(k_af_count, cg, blk, 0, s, w.keys, bt, w.st, w.cnt, w.cmin);
+  VBM_LAUNCH_CHECK("adaptive_count");
+  hipLaunchKernelGGL(k_af_band_sum, nbg, blk, 0, s, bt, w.cnt, w.cmin, 0, w.st);
+  VBM_LAUNCH_CHECK("adaptive_band_sum");
+  hipLaunchKernelGGL(k_af_thr, dim3(1), dim3(128), 0, s, bt, w.st);
+  VBM_LAUNCH_CHECK("adaptive_thr");
   hipLaunchKernelGGL(k_af_flags, cg, blk, 0, s, w.keys, bt, w.st, w.cnt);
   VBM_LAUNCH_CHECK("adaptive_flags");
-  hipLaunchKernelGGL(k_af_band_sum, nbg, blk, 0, s, bt, w.cnt, 1, w.st);
+  hipLaunchKernelGGL(k_af_band_sum, nbg, blk, 0, s, bt, w.cnt, static_cast<const uint32_t*>(nullptr), 1, w.st);
   VBM_LAUNCH_CHECK("adaptive_band_sum");
   VBM_TRY(scan_exclusive_u32(w.cnt, w.offs, chunks, nullptr, w.total, w.scan, s));
-  hipLaunchKernelGGL(k_af_write, cg, blk, 0, s, w.keys, bt, w.st, w.offs, capacity, kept_index);
+  hipLaunchKernelGGL(k_af_write, cg, blk, 0, s, w.keys, bt, w.st, w.offs, w.cnt, capacity, kept_index);
   VBM_LAUNCH_CHECK("adaptive_write");
   hipLaunchKernelGGL(k_af_final, dim3(1), dim3(128), 0, s, bt, w.st, w.total, count_dev, band_stats);
   VBM_LAUNCH_CHECK("adaptive_final");

@@ -41,6 +41,7 @@ def _coeffs(G, J, wav, seed):
     (48, 3, "bior4.4", 30000, dict(alpha=0.0, beta=1.0, lam=0.0)),
     (32, 3, "haar", 50, dict(lam=2.0)),            # the per-band minimum fires: total above K_tot
     (16, 1, "bior4.4", 16 ** 3, dict(ref=0, min_band=0)),
+    (40, 3, "bior4.4", 3000, dict()),              # odd coarsest side: subbands of 125 locations
 ])
 def test_adaptive_select_matches_oracle(G, J, wav, K_tot, params):
     api = _api()
