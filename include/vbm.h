@@ -251,7 +251,8 @@ typedef struct {
 } vbm_plan;
 
 /* Workspace regions a test may read back after vbm_render_fwd (offsets into ws). */
-#define VBM_REGION_COUNTERS 0    /* uint32 [16]: [0] visible items, [1] pairs, [2] overflow */
+#define VBM_REGION_COUNTERS 0    /* uint32 [16]: [0] visible items, [1] pairs, [2] overflow, [4..5]
+                                  * uint64 ballot words taken by large footprints */
 #define VBM_REGION_ITEM_DEPTH 1  /* float32 [n_items] camera depth (0 when culled) */
 #define VBM_REGION_ITEM_RECT 2   /* uint32 [2][n_items]: x0 | x1 << 16, y0 | y1 << 16 */
 #define VBM_REGION_ITEM_NTILES 3 /* uint32 [n_items] */

@@ -92,6 +92,11 @@ __device__ __forceinline__ bool tile_reached(float mx, float my, float A, float 
 // the per-thread pass of the block, so that one large footprint does not hold up 63 lanes.
 constexpr uint32_t kSmallRect = 32;
 
+// A large rectangle's reached tiles are kept as the projection's 64-tile ballots, one 64-bit word
+// per round, in a bump-allocated word buffer that the emission reads back; bin.z holds the item's
+// first word, or kNoWords when the buffer was full and the emission repeats the tests.
+constexpr uint32_t kNoWords = 0xFFFFFFFFu;
+
 // Column and row of tile t (row-major) of a rectangle w tiles wide, with inv_w = 1/w rounded: the
 // float quotient is off by at most one and corrected.
 __device__ __forceinline__ void rect_tile(uint32_t t, uint32_t w, float inv_w, uint32_t& tx, uint32_t& ty) {
@@ -196,7 +201,8 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
                                                  uint32_t* __restrict__ ntiles, float4* __restrict__ rec,
                                                  float4* __restrict__ coef, float* __restrict__ blue,
                                                  uint32_t* __restrict__ vis_flag, uint4* __restrict__ bin,
-                                                 int64_t n_items) {
+                                                 int64_t n_items, unsigned long long* __restrict__ word_count,
+                                                 unsigned long long* __restrict__ words, uint32_t word_cap) {
   __shared__ float s_par[8][256];      // per thread: mean2d.xy, conic A B C, tau, nBA, nBC
   __shared__ uint32_t s_org[256];      // rectangle origin x0 | y0 << 16
   __shared__ uint32_t s_w[256];        // rectangle width
@@ -206,8 +212,13 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
   __shared__ uint32_t s_mask[256];     // reached-tile mask of a small rectangle
   __shared__ uint8_t s_map[256 * kSmallRect];   // test number -> thread of its rectangle
   __shared__ uint32_t s_q[256];        // threads with a large rectangle
-  __shared__ uint32_t s_n;
-  if (threadIdx.x == 0) s_n = 0;
+  __shared__ uint32_t s_wofs[256];     // first ballot word of a large rectangle, within the block's
+  __shared__ uint32_t s_n, s_words;
+  __shared__ unsigned long long s_wbase;
+  if (threadIdx.x == 0) {
+    s_n = 0;
+    s_words = 0;
+  }
   s_mask[threadIdx.x] = 0u;
   __syncthreads();
   const DevView& v = views[blockIdx.y];
@@ -237,6 +248,7 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
       } else {
         deferred = true;
         s_q[atomicAdd(&s_n, 1u)] = threadIdx.x;
+        s_wofs[threadIdx.x] = atomicAdd(&s_words, (area + 63u) >> 6);
       }
     }
     depth[item] = p.visible ? p.depth : 0.0f;
@@ -259,6 +271,8 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
   s_start[threadIdx.x] = start;
   for (uint32_t k = 0; k < small_area; ++k) s_map[start + k] = static_cast<uint8_t>(threadIdx.x);
   __syncthreads();
+  // one allocation per block for the ballot words of its large rectangles (read after the next barrier)
+  if (threadIdx.x == 0) s_wbase = s_words ? atomicAdd(word_count, static_cast<unsigned long long>(s_words)) : 0ull;
   for (uint32_t t = threadIdx.x; t < n_tests; t += 256) {
     const uint32_t o = s_map[t];
     const uint32_t k = t - s_start[o];
@@ -271,15 +285,13 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
       atomicOr(&s_mask[o], 1u << k);
   }
   __syncthreads();
-  if (i < v.n_gauss) {
-    // small or invisible rectangles here; a large one gets its tile count below
+  if (i < v.n_gauss && !deferred) {
+    // small or invisible rectangles here; a large one is completed below by the wave that tests it
     const uint32_t mask = small_area ? s_mask[threadIdx.x] : 0u;
     const uint32_t nt = static_cast<uint32_t>(__popc(mask));
     bin[item] = make_uint4(rx, ry, mask, nt);
-    if (!deferred) {
-      ntiles[item] = nt;
-      vis_flag[item] = nt ? 1u : 0u;
-    }
+    ntiles[item] = nt;
+    vis_flag[item] = nt ? 1u : 0u;
   }
   const uint32_t n_def = s_n;
   const int lane = static_cast<int>(threadIdx.x) & 63;
@@ -288,9 +300,11 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
     const uint32_t org = s_org[o];
     const uint32_t x0 = org & 0xFFFFu, y0 = org >> 16;
     const int64_t it = v.item_offset + static_cast<int64_t>(blockIdx.x) * 256 + o;
-    const uint32_t w = s_w[o];
-    const uint32_t area = w * s_h[o];
+    const uint32_t w = s_w[o], h = s_h[o];
+    const uint32_t area = w * h;
     const float inv_w = s_invw[o];
+    const unsigned long long first = s_wbase + s_wofs[o];
+    const bool keep = first + ((area + 63u) >> 6) <= word_cap;
     uint32_t nt = 0;
     for (uint32_t t0 = 0; t0 < area; t0 += 64) {
       const uint32_t t = t0 + static_cast<uint32_t>(lane);
@@ -299,12 +313,15 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
       const bool hit = t < area && tile_reached(s_par[0][o], s_par[1][o], s_par[2][o], s_par[3][o], s_par[4][o],
                                                 s_par[6][o], s_par[7][o], s_par[5][o], static_cast<int>(x0 + tx),
                                                 static_cast<int>(y0 + ty), tile, v.width, v.height);
-      nt += static_cast<uint32_t>(__popcll(__ballot(hit)));
+      const uint64_t m = __ballot(hit);
+      nt += static_cast<uint32_t>(__popcll(m));
+      if (keep && lane == 0) words[first + (t0 >> 6)] = m;
     }
     if (lane == 0) {
       ntiles[it] = nt;
       vis_flag[it] = nt ? 1u : 0u;
-      bin[it].w = nt;
+      bin[it] = make_uint4(x0 | ((x0 + w) << 16), y0 | ((y0 + h) << 16),
+                           keep ? static_cast<uint32_t>(first) : kNoWords, nt);
     }
   }
 }
@@ -354,6 +371,7 @@ __global__ __launch_bounds__(256) void k_gather_ntiles(const uint32_t* __restric
 __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views, int n_views,
                                               const uint32_t* __restrict__ vals, const uint32_t* __restrict__ offs,
                                               const uint4* __restrict__ bin, const float4* __restrict__ rec,
+                                              const unsigned long long* __restrict__ words,
                                               int tile, uint32_t* __restrict__ counters, int64_t n_max,
                                               int64_t capacity, uint32_t* __restrict__ pair_tile,
                                               uint32_t* __restrict__ pair_item) {
@@ -406,12 +424,35 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
       const uint32_t x0 = b.x & 0xFFFFu, x1 = b.x >> 16, y0 = b.y & 0xFFFFu, y1 = b.y >> 16;
       const uint32_t w = x1 - x0, area = w * (y1 - y0);
       const float inv_w = 1.0f / static_cast<float>(w);
+      int64_t o = offs[q];
+      bool over = false;
+      if (b.z != kNoWords) {
+        // the projection's ballots: bit l of word k is tile 64 k + l of the rectangle (row-major)
+        const unsigned long long* wk = words + b.z;
+        for (uint32_t t0 = 0; t0 < area; t0 += 64, ++wk) {
+          const uint64_t m = *wk;
+          if (m == 0) continue;
+          if ((m >> lane) & 1u) {
+            uint32_t tx, ty;
+            rect_tile(t0 + static_cast<uint32_t>(lane), w, inv_w, tx, ty);
+            const int64_t oo = o + lanes_below(m);
+            if (oo < capacity) {
+              pair_tile[oo] = static_cast<uint32_t>(v.tile_offset) + (y0 + ty) * static_cast<uint32_t>(v.tiles_x) +
+                              x0 + tx;
+              pair_item[oo] = item;
+            } else {
+              over = true;
+            }
+          }
+          o += __popcll(m);
+        }
+        if (over) counters[2] = 1u;
+        continue;
+      }
       const float4 ra = rec[2 * static_cast<int64_t>(item)];
       const float4 rb = rec[2 * static_cast<int64_t>(item) + 1];
       const float tau = footprint_tau(rb.y);
       const float nBA = -__fdiv_rn(ra.w, ra.z), nBC = -__fdiv_rn(ra.w, rb.x);
-      int64_t o = offs[q];
-      bool over = false;
       for (uint32_t t0 = 0; t0 < area; t0 += 64) {
         const uint32_t t = t0 + static_cast<uint32_t>(lane);
         uint32_t tx, ty;

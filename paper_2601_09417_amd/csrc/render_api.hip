@@ -20,12 +20,13 @@
 namespace vbm {
 
 __global__ void k_project(const DevView*, int, vbm_gaussians_c, float*, uint32_t*, uint32_t*, float4*, float4*,
-                          float*, uint32_t*, uint4*, int64_t);
+                          float*, uint32_t*, uint4*, int64_t, unsigned long long*, unsigned long long*, uint32_t);
 __global__ void k_compact_visible(const DevView*, const uint32_t*, const float*, const uint32_t*, uint32_t*,
                                   uint32_t*);
 __global__ void k_gather_ntiles(const uint32_t*, const uint32_t*, const uint32_t*, int64_t, uint32_t*);
 __global__ void k_emit(const DevView*, int, const uint32_t*, const uint32_t*, const uint4*,
-                       const float4*, int, uint32_t*, int64_t, int64_t, uint32_t*, uint32_t*);
+                       const float4*, const unsigned long long*, int, uint32_t*, int64_t, int64_t, uint32_t*,
+                       uint32_t*);
 __global__ void k_ranges(const uint32_t*, const uint32_t*, int64_t, uint2*);
 __global__ void k_status(const uint32_t*, int32_t*);
 __global__ void k_tile_keys(const uint2*, int64_t, uint32_t*, uint32_t*);
@@ -66,10 +67,17 @@ enum Region {
   R_SCRATCH = 17,
   R_VISFLAG = 18,
   R_COEF = VBM_REGION_ITEM_COEF,
-  R_BIN = 20,      // uint4 [n_items]: x0 | x1 << 16, y0 | y1 << 16, reached-tile mask, tile count
+  R_BIN = 20,      // uint4 [n_items]: x0 | x1 << 16, y0 | y1 << 16, reached-tile mask of a small
+                   // rectangle or first ballot word of a large one, tile count
   R_TORDER = 21,   // uint32 [4][n_tiles]: sort keys, tiles, and the sorted keys and tiles (the launch order)
-  R_COUNT = 22
+  R_WORDS = 22,    // uint64 [ballot_words(n_items)]: large rectangles' reached-tile ballots
+  R_COUNT = 23
 };
+
+// Capacity of the ballot-word buffer: one word per four items (at 1M Gaussians x 8 views the large
+// rectangles need about 0.4M words of the 2M); rectangles that find it full are tested again by
+// the emission instead.
+int64_t ballot_words(int64_t n_items) { return n_items / 4 > 1024 ? n_items / 4 : 1024; }
 
 int ceil_log2(int64_t x) {
   int b = 0;
@@ -111,6 +119,7 @@ void layout(vbm_plan* p) {
   sz[R_COEF] = I * 32;
   sz[R_BIN] = I * 16;
   sz[R_TORDER] = 4 * NT * 4;
+  sz[R_WORDS] = 8 * ballot_words(I);
   size_t off = 0;
   for (int r = 0; r < VBM_WS_REGIONS; ++r) {
     p->region_offset[r] = 0;
@@ -329,7 +338,9 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
   const int gx = static_cast<int>(ceil_div(p->n_gaussians > 0 ? p->n_gaussians : 1, 256));
   if (I > 0) {
     hipLaunchKernelGGL(k_project, dim3(gx, p->n_views), dim3(256), 0, s, views, p->tile, g, depth, rect, ntiles, rec,
-                       coef, blue, visflag, region<uint4>(p, ws, R_BIN), I);
+                       coef, blue, visflag, region<uint4>(p, ws, R_BIN), I,
+                       reinterpret_cast<unsigned long long*>(counters + 4), region<unsigned long long>(p, ws, R_WORDS),
+                       static_cast<uint32_t>(ballot_words(I)));
     VBM_LAUNCH_CHECK("project");
     VBM_TRY(scan_exclusive_u32(visflag, visflag, I, nullptr, &counters[0], scratch, s));
     // Visible items sorted by depth alone, all views together: a visible item's depth is positive,
@@ -366,7 +377,8 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
   const int pfirst = tile_passes % 2;
   if (I > 0 && emit_grid_n > 0) {
     hipLaunchKernelGGL(k_emit, dim3(grid_cap(emit_grid_n, 16384)), dim3(256), 0, s, views, p->n_views, vv[0], poffs,
-                       region<uint4>(p, ws, R_BIN), rec, p->tile, counters, I, cap, pt[pfirst], pi[pfirst]);
+                       region<uint4>(p, ws, R_BIN), rec, region<unsigned long long>(p, ws, R_WORDS), p->tile,
+                       counters, I, cap, pt[pfirst], pi[pfirst]);
     VBM_LAUNCH_CHECK("emit");
   }
   if (pair_n > 0) {

@@ -93,6 +93,38 @@ def test_pair_lists_large_footprints(tile):
     assert np.array_equal(rp.region("pair_item", torch.int32).cpu().numpy()[:n] & ITEM_MASK, ref["item"])
 
 
+def test_large_footprints_beyond_the_ballot_word_buffer():
+    """Large rectangles keep the projection's 64-tile ballots in a word buffer of max(n_items / 4, 1024)
+    words that the emission reads back; rectangles that find it full are tested again by the emission.
+    Footprints large enough to overflow it exercise both in one batch: pair lists bit-exact."""
+    api = _api()
+    gs = vi.random_gaussians(1200, 14, log_scale_mean=-1.5, log_scale_std=0.3)
+    cams = vi.orbit_cameras(1, 256, 192, azimuth0=0.4)
+    P = to_dev(gs)
+    rp = api.plan_batch(cams, [0, gs.n], tile=8, pair_capacity=1 << 21)
+    out = api.render_fwd(rp, P)
+    torch.cuda.synchronize()
+    ref = binning.pair_lists(gs, cams, 8)
+    n = ref["tile"].size
+    say(f"large footprints, word buffer overflow: {n} pairs")
+    assert int(out.status[0]) == 0 and int(out.status[1]) == n
+    I = int(rp.plan.n_items)
+    cap = int(rp.plan.region_bytes[22]) // 8
+    assert cap == max(I // 4, 1024)
+    taken = int(rp.region("counters", torch.int32).cpu().numpy().view(np.uint64)[2])
+    rect = rp.region("item_rect", torch.int32).cpu().numpy().view(np.uint32)
+    area = ((rect[:I] >> 16) - (rect[:I] & 0xFFFF)) * ((rect[I:2 * I] >> 16) - (rect[I:2 * I] & 0xFFFF))
+    large = (area > 32) & (ref["proj"][0]["n_tiles"] > 0)
+    assert taken == int(((area[area > 32] + 63) // 64).sum()) and taken > cap
+    off = int(rp.plan.region_offset[20])
+    first = rp.ws[off:off + 16 * I].view(torch.int32).cpu().numpy().view(np.uint32).reshape(I, 4)[:, 2]
+    stored = large & (first != 0xFFFFFFFF)
+    assert stored.sum() > 10 and (large & ~stored).sum() > 10
+    assert np.array_equal(rp.region("item_ntiles", torch.int32).cpu().numpy()[:I], ref["proj"][0]["n_tiles"])
+    assert np.array_equal(rp.region("pair_tile", torch.int32).cpu().numpy()[:n], ref["tile"])
+    assert np.array_equal(rp.region("pair_item", torch.int32).cpu().numpy()[:n] & ITEM_MASK, ref["item"])
+
+
 @pytest.mark.parametrize("tile,W,H", [(16, 64, 64), (16, 101, 67), (8, 50, 37), (32, 96, 80)])
 def test_forward_backward_parity(tile, W, H):
     api = _api()
