@@ -271,8 +271,10 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
   s_start[threadIdx.x] = start;
   for (uint32_t k = 0; k < small_area; ++k) s_map[start + k] = static_cast<uint8_t>(threadIdx.x);
   __syncthreads();
-  // one allocation per block for the ballot words of its large rectangles (read after the next barrier)
-  if (threadIdx.x == 0) s_wbase = s_words ? atomicAdd(word_count, static_cast<unsigned long long>(s_words)) : 0ull;
+  // One allocation per block for the ballot words of its large rectangles; its result is published
+  // after this thread's tests, so that the round trip of the atomic overlaps them.
+  unsigned long long wbase = 0;
+  if (threadIdx.x == 0 && s_words) wbase = atomicAdd(word_count, static_cast<unsigned long long>(s_words));
   for (uint32_t t = threadIdx.x; t < n_tests; t += 256) {
     const uint32_t o = s_map[t];
     const uint32_t k = t - s_start[o];
@@ -284,6 +286,7 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
                      v.width, v.height))
       atomicOr(&s_mask[o], 1u << k);
   }
+  if (threadIdx.x == 0) s_wbase = wbase;
   __syncthreads();
   if (i < v.n_gauss && !deferred) {
     // small or invisible rectangles here; a large one is completed below by the wave that tests it
@@ -354,14 +357,19 @@ __device__ __forceinline__ int view_of_item(const DevView* __restrict__ views, i
   return lo;
 }
 
-__global__ __launch_bounds__(256) void k_gather_ntiles(const uint32_t* __restrict__ vals,
-                                                       const uint32_t* __restrict__ ntiles,
-                                                       const uint32_t* __restrict__ counters, int64_t n_max,
-                                                       uint32_t* __restrict__ out) {
+// The depth-sorted items' bin entries (rectangle, reach mask or first ballot word, tile count),
+// gathered once into sorted order for the emission, and their tile counts for the pair offsets.
+__global__ __launch_bounds__(256) void k_gather_bins(const uint32_t* __restrict__ vals,
+                                                     const uint4* __restrict__ bin,
+                                                     const uint32_t* __restrict__ counters, int64_t n_max,
+                                                     uint32_t* __restrict__ out, uint4* __restrict__ sorted_bin) {
   const int64_t n = min(static_cast<int64_t>(counters[0]), n_max);
   for (int64_t p = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; p < n;
-       p += static_cast<int64_t>(gridDim.x) * 256)
-    out[p] = ntiles[vals[p]];
+       p += static_cast<int64_t>(gridDim.x) * 256) {
+    const uint4 b = bin[vals[p]];
+    sorted_bin[p] = b;
+    out[p] = b.w;
+  }
 }
 
 // Writes each visible item's tiles in the items' depth order (views interleaved; the stable tile
@@ -370,7 +378,7 @@ __global__ __launch_bounds__(256) void k_gather_ntiles(const uint32_t* __restric
 // positions from the ballot of reached tiles).
 __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views, int n_views,
                                               const uint32_t* __restrict__ vals, const uint32_t* __restrict__ offs,
-                                              const uint4* __restrict__ bin, const float4* __restrict__ rec,
+                                              const uint4* __restrict__ sorted_bin, const float4* __restrict__ rec,
                                               const unsigned long long* __restrict__ words,
                                               int tile, uint32_t* __restrict__ counters, int64_t n_max,
                                               int64_t capacity, uint32_t* __restrict__ pair_tile,
@@ -386,7 +394,7 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
     if (p < n) {
       const uint32_t item = vals[p];
       const DevView& v = views[view_of_item(views, n_views, item)];
-      const uint4 b = bin[item];
+      const uint4 b = sorted_bin[p];
       const uint32_t x0 = b.x & 0xFFFFu, x1 = b.x >> 16, y0 = b.y & 0xFFFFu, y1 = b.y >> 16;
       const uint32_t w = x1 - x0;
       if (w * (y1 - y0) <= kSmallRect) {
@@ -420,7 +428,7 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
       const int64_t q = base + s_q[d];
       const uint32_t item = vals[q];
       const DevView& v = views[view_of_item(views, n_views, item)];
-      const uint4 b = bin[item];
+      const uint4 b = sorted_bin[q];
       const uint32_t x0 = b.x & 0xFFFFu, x1 = b.x >> 16, y0 = b.y & 0xFFFFu, y1 = b.y >> 16;
       const uint32_t w = x1 - x0, area = w * (y1 - y0);
       const float inv_w = 1.0f / static_cast<float>(w);

@@ -23,7 +23,7 @@ __global__ void k_project(const DevView*, int, vbm_gaussians_c, float*, uint32_t
                           float*, uint32_t*, uint4*, int64_t, unsigned long long*, unsigned long long*, uint32_t);
 __global__ void k_compact_visible(const DevView*, const uint32_t*, const float*, const uint32_t*, uint32_t*,
                                   uint32_t*);
-__global__ void k_gather_ntiles(const uint32_t*, const uint32_t*, const uint32_t*, int64_t, uint32_t*);
+__global__ void k_gather_bins(const uint32_t*, const uint4*, const uint32_t*, int64_t, uint32_t*, uint4*);
 __global__ void k_emit(const DevView*, int, const uint32_t*, const uint32_t*, const uint4*,
                        const float4*, const unsigned long long*, int, uint32_t*, int64_t, int64_t, uint32_t*,
                        uint32_t*);
@@ -71,8 +71,10 @@ enum Region {
                    // rectangle or first ballot word of a large one, tile count
   R_TORDER = 21,   // uint32 [4][n_tiles]: sort keys, tiles, and the sorted keys and tiles (the launch order)
   R_WORDS = 22,    // uint64 [ballot_words(n_items)]: large rectangles' reached-tile ballots
-  R_COUNT = 23
+  R_SBIN = 23,     // uint4 [n_items]: the visible items' bin entries in depth order
+  R_COUNT = 24
 };
+static_assert(R_COUNT <= VBM_WS_REGIONS, "plan has room for every region");
 
 // Capacity of the ballot-word buffer: one word per four items (at 1M Gaussians x 8 views the large
 // rectangles need about 0.4M words of the 2M); rectangles that find it full are tested again by
@@ -120,6 +122,7 @@ void layout(vbm_plan* p) {
   sz[R_BIN] = I * 16;
   sz[R_TORDER] = 4 * NT * 4;
   sz[R_WORDS] = 8 * ballot_words(I);
+  sz[R_SBIN] = I * 16;
   size_t off = 0;
   for (int r = 0; r < VBM_WS_REGIONS; ++r) {
     p->region_offset[r] = 0;
@@ -356,8 +359,9 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
     bool in_alt = false;
     VBM_TRY(radix_sort_pairs<uint32_t>(vk[first], vv[first], vk[1 - first], vv[1 - first], I, &counters[0],
                                        kDepthKeyBits, 8, scratch, s, &in_alt));
-    hipLaunchKernelGGL(k_gather_ntiles, dim3(grid_cap(I, 8192)), dim3(256), 0, s, vv[0], ntiles, counters, I, poffs);
-    VBM_LAUNCH_CHECK("gather_ntiles");
+    hipLaunchKernelGGL(k_gather_bins, dim3(grid_cap(I, 8192)), dim3(256), 0, s, vv[0], region<uint4>(p, ws, R_BIN),
+                       counters, I, poffs, region<uint4>(p, ws, R_SBIN));
+    VBM_LAUNCH_CHECK("gather_bins");
     VBM_TRY(scan_exclusive_u32(poffs, poffs, I, &counters[0], &counters[1], scratch, s));
   }
   int64_t emit_grid_n = I;
@@ -377,7 +381,7 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
   const int pfirst = tile_passes % 2;
   if (I > 0 && emit_grid_n > 0) {
     hipLaunchKernelGGL(k_emit, dim3(grid_cap(emit_grid_n, 16384)), dim3(256), 0, s, views, p->n_views, vv[0], poffs,
-                       region<uint4>(p, ws, R_BIN), rec, region<unsigned long long>(p, ws, R_WORDS), p->tile,
+                       region<uint4>(p, ws, R_SBIN), rec, region<unsigned long long>(p, ws, R_WORDS), p->tile,
                        counters, I, cap, pt[pfirst], pi[pfirst]);
     VBM_LAUNCH_CHECK("emit");
   }
