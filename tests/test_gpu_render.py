@@ -23,11 +23,17 @@ def _scene(n, seed, views, W, H, log_scale=-3.0, opacity=(0.05, 0.95)):
     return gs, cams
 
 
-@pytest.mark.parametrize("tile", [8, 16, 32])
-def test_projection_and_pair_lists_bit_exact(tile):
+# Opacities of (0.001, 0.007): about half of the Gaussians are below 1/255 and reach no pixel (the
+# projection marks them invisible).
+LOW_OPACITY = (0.001, 0.007)
+
+
+@pytest.mark.parametrize("tile,opacity", [(8, (0.05, 0.95)), (16, (0.05, 0.95)), (32, (0.05, 0.95)),
+                                          (16, LOW_OPACITY)])
+def test_projection_and_pair_lists_bit_exact(tile, opacity):
     api = _api()
-    gs, cams = _scene(3000, 11, 3, 131, 77)
-    say(f"pair lists tile={tile} n={gs.n} views=3 131x77")
+    gs, cams = _scene(3000, 11, 3, 131, 77, opacity=opacity)
+    say(f"pair lists tile={tile} n={gs.n} views=3 131x77 opacity {opacity}")
     P = to_dev(gs)
     rp = api.plan_batch(cams, [0, gs.n], tile=tile, pair_capacity=1 << 20)
     out = api.render_fwd(rp, P)
@@ -215,10 +221,11 @@ def test_capacity_overflow_is_flagged():
     assert int(out2.status[0]) == 0
 
 
-def test_batched_equals_plain_and_multiscene():
+@pytest.mark.parametrize("opacity", [(0.05, 0.95), LOW_OPACITY])
+def test_batched_equals_plain_and_multiscene(opacity):
     api = _api()
-    s1, _ = _scene(300, 21, 1, 60, 40)
-    s2, _ = _scene(900, 22, 1, 60, 40, log_scale=-3.5)
+    s1, _ = _scene(300, 21, 1, 60, 40, opacity=opacity)
+    s2, _ = _scene(900, 22, 1, 60, 40, log_scale=-3.5, opacity=opacity)
     gs = vi.GaussianSet.concat([s1, s2])
     cams = vi.orbit_cameras(2, 72, 56) + vi.orbit_cameras(2, 40, 33, azimuth0=1.0)
     view_scene = [0, 1, 1, 0]
