@@ -35,11 +35,21 @@ if ROOT not in sys.path:
 
 METRIC = "fine-tune iters/sec (fwd+bwd, 1M Gaussians, 1080p, 8 views) batched vs plain"
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3
+# MI355X vector ALU: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz issue 39.3e12 lane-operations/s; an FMA
+# counts 2 flops, so 78.6 TFLOP/s of float32 without packed instructions (which every device compile
+# here disables); AMD's published 157.3 TFLOP/s counts the packed (two-wide) FMA.
+CU, SIMD_PER_CU, LANES_PER_SIMD, CLOCK_GHZ = 256, 4, 16, 2.4
+FP32_ALU_PEAK_TFLOPS = round(CU * SIMD_PER_CU * LANES_PER_SIMD * 2 * CLOCK_GHZ / 1e3, 1)
+FP32_PUBLISHED_PACKED_TFLOPS = 157.3
 # Algorithmic cost per (pixel, Gaussian) evaluation of the compositing kernels.
 FLOPS_FWD_EVAL, FLOPS_FWD_USED = 17, 8
 FLOPS_BWD_EVAL, FLOPS_BWD_USED = 17, 40
-BYTES_PER_PAIR_FWD, BYTES_PER_PIXEL_FWD = 40, 20   # algorithmic (the lane-group marks written back are not counted)
+# Algorithmic HBM bytes.  Forward: per pair the 4-byte item id and the 36-byte record (32-byte
+# compositing record + blue); per pixel the image (12), final T (4) and contribution count (4)
+# written.  Backward: per pair the same 40 bytes read plus nine 4-byte gradient sums added; per
+# pixel dL/dI (12), final T (4) and the count (4) read -- it reads no image and writes nothing per
+# pixel.  (The lane-group marks the forward writes back into visited pair values are not counted.)
+BYTES_PER_PAIR_FWD, BYTES_PER_PIXEL_FWD = 40, 20
 BYTES_PER_PAIR_BWD, BYTES_PER_PIXEL_BWD = 76, 20
 # adaptive selection: 16 B read + 4 B key written, eight select passes (the median and the
 # K_band-th largest share four) and three count/flag/write passes over the 4-byte keys, per coefficient
@@ -95,8 +105,29 @@ def log(msg: str) -> None:
 
 # ----------------------------------------------------------------------------- CPU oracle baseline
 
-def cpu_baseline_worker(queue, workload: str, n_tiles: int, threads: int) -> None:
-    """Times the CPU oracle's per-iteration work on a bounded sample of the same workload."""
+def host_cpu() -> dict:
+    """The host's logical CPUs available to this process and the CPU model."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count()
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:  # pragma: no cover
+        pass
+    return dict(nproc=n, cpu_count=os.cpu_count(), model=model)
+
+
+def cpu_baseline_worker(queue, go, workload: str, n_tiles: int, threads: int) -> None:
+    """Times the CPU oracle's per-iteration work on a bounded sample of the same workload.  Waits for
+    ``go`` before doing anything, so that none of its work overlaps the GPU measurements."""
+    if not go.wait(timeout=3600):
+        queue.put(dict(ok=False, error="never released"))
+        return
     try:
         import torch
         torch.set_num_threads(threads)
@@ -442,11 +473,14 @@ def timed_step_runs(args, out, P, cams, targets, wl, scene_offsets, view_scene):
     out["kernels"] = {
         "composite_fwd": dict(ms=fwd_ms, evals=c[0], contrib=c[1],
                               tflops=(FLOPS_FWD_EVAL * c[0] + FLOPS_FWD_USED * c[1]) / (fwd_ms * 1e-3) / 1e12,
-                              gbs=(BYTES_PER_PAIR_FWD * P_pairs + BYTES_PER_PIXEL_FWD * npx) / (fwd_ms * 1e-3) / 1e9),
+                              bytes=BYTES_PER_PAIR_FWD * P_pairs + BYTES_PER_PIXEL_FWD * npx),
         "composite_bwd": dict(ms=bwd_ms, evals=c[2], contrib=c[3],
                               tflops=(FLOPS_BWD_EVAL * c[2] + FLOPS_BWD_USED * c[3]) / (bwd_ms * 1e-3) / 1e12,
-                              gbs=(BYTES_PER_PAIR_BWD * P_pairs + BYTES_PER_PIXEL_BWD * npx) / (bwd_ms * 1e-3) / 1e9),
+                              bytes=BYTES_PER_PAIR_BWD * P_pairs + BYTES_PER_PIXEL_BWD * npx),
     }
+    for d in out["kernels"].values():
+        d["gbs"] = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+    out["pixels_per_step"] = npx
     log(f"composite fwd {fwd_ms:.2f} ms, bwd {bwd_ms:.2f} ms per launch")
     del fb
 
@@ -595,21 +629,24 @@ def main() -> int:
     wl = WORKLOADS[args.workload]
     rank0 = int(os.environ.get("RANK", "0")) == 0
 
-    # start the CPU oracle before anything touches the GPU in this process
-    proc = queue = None
+    # start the CPU oracle before anything touches the GPU in this process; it waits until every GPU
+    # measurement (autotune, graph, kernel events, plain) has finished
+    proc = queue = go = None
     if rank0 and not args.no_cpu_baseline and "scenes" not in wl:
         ctx = mp.get_context("spawn")
         queue = ctx.Queue()
-        proc = ctx.Process(target=cpu_baseline_worker, args=(queue, args.workload, args.cpu_tiles, args.cpu_threads),
-                           daemon=True)
+        go = ctx.Event()
+        proc = ctx.Process(target=cpu_baseline_worker,
+                           args=(queue, go, args.workload, args.cpu_tiles, args.cpu_threads), daemon=True)
         proc.start()
-        log(f"CPU oracle baseline started (pid {proc.pid})")
+        log(f"CPU oracle baseline process started (pid {proc.pid}); it runs after the GPU measurements")
 
     gpu = run_gpu(args, wl)
 
     cpu = None
     if proc is not None:
-        log("waiting for the CPU oracle baseline")
+        go.set()
+        log("GPU measurements done; running the CPU oracle baseline")
         try:
             cpu = queue.get(timeout=900)
         except Exception as exc:
@@ -619,6 +656,7 @@ def main() -> int:
     value = args.steps / gpu["batched_wall_s"]
     plain = args.steps / gpu["plain_wall_s"] if "plain_wall_s" in gpu else None
     k = gpu["kernels"]["composite_bwd"]
+    kf = gpu["kernels"]["composite_fwd"]
     # the committed counter run covers the 16x16-tile kernel of the workload's own loss only
     traffic = (traffic_from_profiles(os.path.join(ROOT, "paper_2601_09417_amd", "csrc", "raster.hip"))
                if args.workload == "H" and gpu["tile"] == 16 and gpu["loss_kind"] == wl["loss"] else None)
@@ -645,6 +683,7 @@ def main() -> int:
         "plain_value": None if plain is None else round(plain, 4),
         "batched_over_plain": None if plain is None else round(value / plain, 3),
         "pairs_per_step": gpu["pairs_per_step"],
+        "pixels_per_step": gpu["pixels_per_step"],
         "init_ms": round(gpu["init_ms"], 2),
         "adaptive_select": gpu.get("adaptive_select"),
         "convergence": gpu.get("convergence"),
@@ -655,18 +694,24 @@ def main() -> int:
             "bound": "alu",
             "kernel": "composite_bwd",
             "achieved": round(k["tflops"], 3),
-            "peak": FP32_PEAK_TFLOPS,
+            "peak": FP32_ALU_PEAK_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": round(k["tflops"] / FP32_PEAK_TFLOPS, 4),
+            "frac": round(k["tflops"] / FP32_ALU_PEAK_TFLOPS, 4),
             "traffic": traffic,
-            "algorithmic_hbm_gbs": round(k["gbs"], 1),
-            "hbm_frac": round(k["gbs"] / HBM_PEAK_GBS, 4),
+            "traffic_over_algorithmic": None if traffic is None else round(traffic / k["bytes"], 3),
+            "peak_published_packed": FP32_PUBLISHED_PACKED_TFLOPS,
+            "frac_of_published_packed": round(k["tflops"] / FP32_PUBLISHED_PACKED_TFLOPS, 4),
+            "hbm": {name: {"algorithmic_bytes": int(d["bytes"]), "ms": round(d["ms"], 4),
+                           "gbs": round(d["gbs"], 1), "frac": round(d["gbs"] / HBM_PEAK_GBS, 4)}
+                    for name, d in (("composite_fwd", kf), ("composite_bwd", k))},
         },
     }
     if cpu is not None and cpu.get("ok"):
+        hc = host_cpu()
         result["cpu_baseline"] = {
             "value": round(1.0 / cpu["sec_per_iter"], 6), "unit": "iters/sec", "cores": cpu["threads"],
-            "kind": "oracle",
+            "kind": "oracle", "host_nproc": hc["nproc"], "host_cpu_count": hc["cpu_count"], "cpu_model": hc["model"],
+            "ran": "after the GPU measurements, alone on the host",
             "sample": (f"FP64 oracle on the same workload: projection+binning and FP64 projection fwd/bwd of all "
                        f"{wl['K']} Gaussians for view 0 (x{wl['views']} views), compositing fwd+bwd of "
                        f"{cpu['tiles']} random tiles of view 0 ({cpu['pairs_sampled']} pairs; scaled to all tiles), "

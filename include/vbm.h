@@ -339,11 +339,26 @@ vbm_status vbm_adam_step(int64_t n, int64_t stride, float* raw, float* m, float*
                          vbm_gaussians act, const vbm_adam_opts* opts_host, int32_t* step_dev, void* stream);
 
 /* ------------------------------------------------------------------------------------------
+ * vbm_adam_init -- the optimiser state at the start of fine-tuning (Sec. 5, Implementation
+ * Details: Adam; the raw parameters of vbm_adam_step).  For Gaussians 0..n-1:
+ *   raw rows 0-2 = means, 3-5 = log(scales), 6-9 = quats, 10 = log(o / (1 - o)), 11-13 = rgb
+ *   m = v = 0 on all 14 rows
+ *   act        activated parameters (stride act.stride >= n), read only
+ *   raw, m, v  float32 [14][stride], stride >= n, written (columns >= n untouched)
+ * There is no clamp: a scale <= 0 or an opacity outside (0, 1) gives a non-finite raw value, as the
+ * map itself does (the construction's opacities lie in [opacity_min, opacity_max] inside (0, 1)).
+ * Enqueues only.  Errors: VBM_ERR_INVALID for null pointers, n < 0, stride < n or act.stride < n.
+ * ------------------------------------------------------------------------------------------ */
+vbm_status vbm_adam_init(int64_t n, int64_t stride, vbm_gaussians_c act, float* raw, float* m, float* v, void* stream);
+
+/* ------------------------------------------------------------------------------------------
  * vbm_dvr_render -- supervision images by ray marching (Sec. 4.4: the method fine-tunes against
  * volume-rendered images).  One ray per pixel centre, clipped to [-1,1]^3, a sample every
  * step_vox voxels from the entry point, trilinear interpolation of the scalar field, the transfer
  * function after interpolation, opacity corrected to the step (1 - (1 - a)^step_vox),
  * front-to-back until T < 1e-4, background bg.  Output layout as vbm_render_fwd's image.
+ * The marching runs in float64 (volume and control points are float32 values); the images are
+ * rounded to float32 once at the end.
  * ------------------------------------------------------------------------------------------ */
 vbm_status vbm_dvr_render(const float* vol, int32_t G, const vbm_tf* tf_host, const vbm_view* views_host,
                           int32_t n_views, float step_vox, float* image, void* stream);

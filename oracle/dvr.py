@@ -48,9 +48,12 @@ def trilinear(vol: np.ndarray, p: np.ndarray) -> np.ndarray:
     return out
 
 
-def render(vol: np.ndarray, xs, rgba, cam, step_vox: float = 0.5, t_min: float = 1e-4, pixels=None):
+def render(vol: np.ndarray, xs, rgba, cam, step_vox: float = 0.5, t_min: float = 1e-4, pixels=None,
+           flag_rel: float | None = None):
     """Image [3][H][W] and transmittance [H][W]; with ``pixels`` = (px, py) index arrays only those
-    rays are marched and the results are [3][n] and [n]."""
+    rays are marched and the results are [3][n] and [n].  With ``flag_rel`` a third result marks the
+    rays on which some sample left T within flag_rel * t_min of the stop threshold t_min, where a
+    renderer with other rounding may legitimately stop one sample earlier or later."""
     vol = np.asarray(vol, dtype=np.float64)
     G = vol.shape[0]
     h = 2.0 / G
@@ -69,6 +72,7 @@ def render(vol: np.ndarray, xs, rgba, cam, step_vox: float = 0.5, t_min: float =
     H, W = d.shape[0], d.shape[1]
     C = np.zeros((H, W, 3))
     T = np.ones((H, W))
+    near = np.zeros((H, W), dtype=bool)
     span = np.where(hit, tf - tn, 0.0)          # rays that miss the cube have non-finite spans
     nsteps = np.where(hit, np.floor(span / dt).astype(np.int64) + 1, 0)
     for k in range(int(nsteps.max()) if nsteps.size else 0):
@@ -83,6 +87,7 @@ def render(vol: np.ndarray, xs, rgba, cam, step_vox: float = 0.5, t_min: float =
         Ta = T[act]
         C[act] += (Ta * a)[:, None] * c[:3].T
         T[act] = Ta * (1.0 - a)
-    if pixels is not None:
-        return C[0].T, T[0]
-    return C.transpose(2, 0, 1), T
+        if flag_rel is not None:
+            near[act] |= np.abs(T[act] - t_min) <= flag_rel * t_min
+    out = (C[0].T, T[0], near[0]) if pixels is not None else (C.transpose(2, 0, 1), T, near)
+    return out if flag_rel is not None else out[:2]

@@ -313,3 +313,63 @@ def composite_pixel_bruteforce(px, py, cand, m2d, con, op, rgb, bg):
         T = Tn
         n_contrib = pos + 1
     return [C[ch] + T * bg[ch] for ch in range(3)], T, n_contrib
+
+
+def composite_pixel_outcomes(px, py, cand, m2d, con, op, rgb, bg, rel_alpha=1e-4, rel_t=1e-3, max_branches=64):
+    """Every correct result of compositing one pixel when some decisions sit at a threshold.
+
+    Follows ``composite_pixel_bruteforce``, but where an evaluation lies within the flagging window
+    of ``composite_tile`` -- o G within rel_alpha of 1/255 (skip or keep), or the transmittance after
+    it within rel_t of 1e-4 (stop or add) -- the other decision is followed as well, since a float32
+    renderer may take either there.  (The 0.99 clamp needs no branch: the clamped alpha is
+    continuous.)  Returns the list of (colour [3], T, n_contrib) over all branch combinations, the
+    FP64 decisions' own among them; at most max_branches are followed.
+    """
+    results = []
+
+    def finish(T, C, n):
+        results.append(([C[ch] + T * bg[ch] for ch in range(3)], T, n))
+
+    def keep(pos, i, a, T, C, n):
+        """Adds Gaussian i at list position pos unless the stop rule ends the pixel there; returns
+        (T, C, n, ended)."""
+        Tn = T * (1.0 - a)
+        stop = Tn < T_MIN
+        if abs(Tn - T_MIN) <= rel_t * T_MIN and len(results) + 1 < max_branches:
+            if stop:
+                run(pos + 1, Tn, [C[ch] + rgb[i][ch] * a * T for ch in range(3)], pos + 1)
+            else:
+                finish(T, C, n)
+        if stop:
+            finish(T, C, n)
+            return T, C, n, True
+        return Tn, [C[ch] + rgb[i][ch] * a * T for ch in range(3)], pos + 1, False
+
+    def run(pos, T, C, n):
+        while pos < len(cand):
+            i = cand[pos]
+            dx, dy = m2d[i][0] - px, m2d[i][1] - py
+            A, B, Cc = con[i]
+            power = -0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy
+            if power > 0:
+                pos += 1
+                continue
+            og = op[i] * math.exp(power)
+            a = min(ALPHA_MAX, og)
+            valid = a >= ALPHA_MIN
+            if abs(og - ALPHA_MIN) <= rel_alpha * ALPHA_MIN and len(results) + 1 < max_branches:
+                if valid:
+                    run(pos + 1, T, list(C), n)
+                else:
+                    T2, C2, n2, ended = keep(pos, i, a, T, list(C), n)
+                    if not ended:
+                        run(pos + 1, T2, C2, n2)
+            if valid:
+                T, C, n, ended = keep(pos, i, a, T, C, n)
+                if ended:
+                    return
+            pos += 1
+        finish(T, C, n)
+
+    run(0, 1.0, [0.0, 0.0, 0.0], 0)
+    return results

@@ -104,6 +104,8 @@ _SIGS = {
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "vbm_adam_step": (C.c_int32, [C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, vbm_gaussians_c,
                                   vbm_gaussians, C.POINTER(vbm_adam_opts), C.c_void_p, C.c_void_p]),
+    "vbm_adam_init": (C.c_int32, [C.c_int64, C.c_int64, vbm_gaussians_c, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p]),
     "vbm_dvr_render": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(vbm_tf), C.POINTER(vbm_view), C.c_int32,
                                    C.c_float, C.c_void_p, C.c_void_p]),
     "vbm_profile_events": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -188,6 +188,10 @@ class RenderPlan:
     cams: list
     view_scene: list
     scene_offsets: np.ndarray
+    # Forwards enqueued on this plan so far.  The workspace holds the state of the latest one only
+    # (pair lists, lane-group marks, ranges, launch order, per-item records), so a backward must
+    # name that forward: render_bwd refuses a FwdOut whose generation is older.
+    generation: int = 0
 
     @property
     def n_pixels(self) -> int:
@@ -231,7 +235,8 @@ class FwdOut:
     image: torch.Tensor      # float32 [3 * n_pixels] (per view [3][H][W], concatenated)
     final_T: torch.Tensor    # float32 [n_pixels]
     n_contrib: torch.Tensor  # int32 [n_pixels]
-    status: torch.Tensor     # int32 [4]: overflow, pairs, visible items
+    status: torch.Tensor     # int32 [4]: overflow, pairs, visible items, overflow count
+    generation: int = -1     # the plan's forward count after the forward that wrote this output
 
 
 def render_fwd(rp: RenderPlan, P: torch.Tensor, out: FwdOut | None = None) -> FwdOut:
@@ -247,6 +252,8 @@ def render_fwd(rp: RenderPlan, P: torch.Tensor, out: FwdOut | None = None) -> Fw
                             out.final_T.data_ptr(), out.n_contrib.data_ptr(), out.status.data_ptr(), rp.ws.data_ptr(),
                             rp.ws.numel(), _stream(dev))
     L.check(st, "vbm_render_fwd")
+    rp.generation += 1
+    out.generation = rp.generation
     return out
 
 
@@ -254,6 +261,10 @@ def render_bwd(rp: RenderPlan, P: torch.Tensor, dL_dimg: torch.Tensor, fwd: FwdO
                accumulate: bool = False) -> torch.Tensor:
     lib = L.load()
     _require_cuda(P, dL_dimg)
+    if fwd.generation != rp.generation:
+        raise L.VBMError(f"render_bwd: the plan's workspace holds forward {rp.generation}, not forward "
+                         f"{fwd.generation} whose output was passed (a later forward on the same plan replaced "
+                         "its pair lists); run the forward again first")
     if grads is None:
         grads = torch.zeros_like(P)
     st = lib.vbm_render_bwd(C.byref(rp.plan), rp.table.data_ptr(), gaussians_struct(P), dL_dimg.data_ptr(),
@@ -301,13 +312,19 @@ class ImageLoss:
 LR_DEFAULT = (1e-3, 5e-3, 1e-3, 5e-3, 2.5e-3)  # means, log scales, quats, logit opacity, rgb
 
 
-def raw_from_activated(P: torch.Tensor) -> torch.Tensor:
-    """Raw optimiser parameters (log scales, logit opacity) from activated ones (setup, not on the hot path)."""
-    raw = P.clone()
-    raw[ROWS["scales"]] = torch.log(P[ROWS["scales"]])
-    op = P[ROWS["opacity"]].clamp(1e-6, 1 - 1e-6)
-    raw[ROWS["opacity"]] = torch.log(op / (1 - op))
-    return raw
+def adam_init(act: torch.Tensor, n: int | None = None):
+    """Optimiser state at the start of fine-tuning (vbm_adam_init): returns (raw, m, v), each
+    [14, stride] like ``act``; raw holds log scales and logit opacity, m = v = 0."""
+    lib = L.load()
+    _require_cuda(act)
+    raw = torch.empty_like(act)
+    m = torch.empty_like(act)
+    v = torch.empty_like(act)
+    n = act.shape[1] if n is None else int(n)
+    st = lib.vbm_adam_init(n, raw.shape[1], gaussians_struct(act), raw.data_ptr(), m.data_ptr(), v.data_ptr(),
+                           _stream(act.device))
+    L.check(st, "vbm_adam_init")
+    return raw, m, v
 
 
 def adam_step(raw, m, v, grads, act, lr=LR_DEFAULT, step: int = 1, step_dev: torch.Tensor | None = None,

@@ -24,20 +24,37 @@ from . import api
 
 
 class VBMRender(torch.autograd.Function):
-    """image = render(P) for a planned batch; P is the [14, N] activated parameter tensor."""
+    """image = render(P) for a planned batch; P is the [14, N] activated parameter tensor.
+
+    The forward reads the plan's overflow flag (one host sync) and raises when the pair lists did
+    not fit the plan's capacity, since the image would be incomplete.  The backward needs the pair
+    lists and per-item state that the forward left in the plan's workspace; when another forward
+    has run on the same plan since (a second loss, a re-render), the backward first re-runs this
+    call's forward from the saved P, which rebuilds the same lists and transmittances bit for bit
+    (every step of the forward is deterministic), so each backward gets its own forward's state.
+    """
 
     @staticmethod
     def forward(ctx, P: torch.Tensor, rp: api.RenderPlan):
         fwd = api.render_fwd(rp, P.detach().contiguous())
+        if int(fwd.status[0].item()) != 0:
+            raise api.L.VBMError(f"VBMRender: {int(fwd.status[1].item())} pairs exceed the plan's capacity of "
+                                 f"{int(rp.plan.pair_capacity)}; plan the batch with a larger pair_capacity")
         ctx.rp = rp
-        ctx.fwd = fwd
-        ctx.save_for_backward(P)
+        ctx.generation = fwd.generation
+        ctx.save_for_backward(P, fwd.final_T, fwd.n_contrib)
         return fwd.image
 
     @staticmethod
     def backward(ctx, grad_image):
-        (P,) = ctx.saved_tensors
-        g = api.render_bwd(ctx.rp, P.detach().contiguous(), grad_image.contiguous(), ctx.fwd)
+        P, final_T, n_contrib = ctx.saved_tensors
+        rp = ctx.rp
+        Pd = P.detach().contiguous()
+        if ctx.generation == rp.generation:
+            fwd = api.FwdOut(None, final_T, n_contrib, None, ctx.generation)
+        else:
+            fwd = api.render_fwd(rp, Pd)
+        g = api.render_bwd(rp, Pd, grad_image.contiguous(), fwd)
         return g, None
 
 
@@ -56,9 +73,7 @@ class FineTuner:
         self.lr = lr
         self.margin = capacity_margin
         self.act = P.contiguous().clone()
-        self.raw = api.raw_from_activated(self.act)
-        self.m = torch.zeros_like(self.raw)
-        self.v = torch.zeros_like(self.raw)
+        self.raw, self.m, self.v = api.adam_init(self.act)
         self.grads = torch.zeros_like(self.raw)
         self.step_dev = torch.zeros(1, dtype=torch.int32, device=self.dev)
         self.targets = targets

@@ -112,12 +112,14 @@ def oracle_gaussians(vol, tf, J, wav, K):
 def sampled_tile_parity(rp, P, gs, cams, view_scene, scene_offsets, tile, sample_views, n_random, seed):
     """Forward and backward of one planned batch against the oracle on sampled tiles.
 
-    For every sampled view: the oracle's pair lists of the view's scene (float32 decisions), the
-    GPU lists of n_random random non-empty tiles and of the view's longest tile compared bit for bit,
-    and their images compared with the oracle's FP64 compositing.  Then dL/dI is random on those
-    tiles and zero elsewhere, so every Gaussian's gradient is the oracle's autodiff over the same
-    tiles (and exactly zero for Gaussians in none of them).  Returns the sampled tiles, the GPU
-    gradient [14][N], the involved Gaussians and the oracle's gradient of those ({group: [rows][n]})."""
+    For every sampled view: the oracle's pair lists of the view's scene (float32 decisions) against
+    the GPU's, the view's whole list, pair count and every tile's range bit for bit; the images of
+    n_random random non-empty tiles and of the view's longest tile against the oracle's FP64
+    compositing (at pixels the oracle flags as near a threshold, against every outcome the branch
+    there allows).  Then dL/dI is random on those tiles and zero elsewhere, so every Gaussian's
+    gradient is the oracle's autodiff over the same tiles (and exactly zero for Gaussians in none of
+    them).  Returns the sampled tiles, the GPU gradient [14][N], the involved Gaussians and the
+    oracle's gradient of those ({group: [rows][n]})."""
     from oracle import binning, render
     from paper_2601_09417_amd import api
     out = api.render_fwd(rp, P)
@@ -127,14 +129,17 @@ def sampled_tile_parity(rp, P, gs, cams, view_scene, scene_offsets, tile, sample
     so = np.asarray(scene_offsets, np.int64)
     toff = binning.tile_grid(cams, tile)
     ioff = binning.item_offsets(view_scene, so)
-    ptile = rp.region("pair_tile", torch.int32).cpu().numpy()
-    pitem = rp.region("pair_item", torch.int32).cpu().numpy() & ITEM_MASK
+    n_pairs = int(out.status[1])
+    ptile = rp.region("pair_tile", torch.int32).cpu().numpy()[:n_pairs]
+    pitem = rp.region("pair_item", torch.int32).cpu().numpy()[:n_pairs] & ITEM_MASK
     ranges = rp.region("ranges", torch.int32).cpu().numpy().reshape(-1, 2)
+    assert np.all(np.diff(ptile.view(np.uint32).astype(np.int64)) >= 0)
     imgs = [t.cpu().numpy() for t in api.split_views(out.image, cams)]
     rng = np.random.default_rng(seed)
     dL = [np.zeros((3, c.height, c.width), np.float32) for c in cams]
     tiles = []                  # (view, scene-global Gaussian indices of the list, pixel xs, ys, dL values)
     err_img, img_max = 0.0, 0.0
+    flag_err, n_flagged = 0.0, 0
     for v in sample_views:
         cam, s = cams[v], view_scene[v]
         s0, s1 = int(so[s]), int(so[s + 1])
@@ -142,6 +147,16 @@ def sampled_tile_parity(rp, P, gs, cams, view_scene, scene_offsets, tile, sample
         ref = binning.pair_lists(sub, [cam], tile)
         TX = -(-cam.width // tile)
         lens = ref["ranges"][:, 1] - ref["ranges"][:, 0]
+        # the view's whole list, its pair count and every tile's range
+        va, vb = np.searchsorted(ptile, [toff[v], toff[v + 1]])
+        assert vb - va == ref["tile"].size, (v, vb - va, ref["tile"].size)
+        assert np.array_equal(ptile[va:vb], ref["tile"] + toff[v])
+        assert np.array_equal(pitem[va:vb] - ioff[v], ref["item"]), v
+        rv = ranges[toff[v]:toff[v + 1]].astype(np.int64)
+        ne = lens > 0
+        assert np.array_equal(rv[ne] - va, ref["ranges"][ne]), v
+        assert np.all(rv[~ne, 1] == rv[~ne, 0]), v
+        say(f"  view {v}: {ref['tile'].size} pairs, every tile's list and range bit-exact")
         nonempty = np.nonzero(lens > 0)[0]
         pick = rng.choice(nonempty, min(n_random, nonempty.size), replace=False)
         for lt in np.unique(np.concatenate([pick, [int(np.argmax(lens))]])):
@@ -160,14 +175,27 @@ def sampled_tile_parity(rp, P, gs, cams, view_scene, scene_offsets, tile, sample
             col, _, _, fl, _ = render.composite_tile(pix, m2d, con, render._t(gs.opacity)[it],
                                                      render._t(gs.rgb)[:, it].T, render._t(cam.bg))
             col, fl = col.numpy(), fl.numpy()
-            err_img = max(err_img, float(np.abs(imgs[v][:, ys, xs].T - col)[~fl].max(initial=0.0)))
+            gpu_px = imgs[v][:, ys, xs].T
+            err_img = max(err_img, float(np.abs(gpu_px - col)[~fl].max(initial=0.0)))
             img_max = max(img_max, float(np.abs(col).max()))
+            if fl.any():
+                # several results are correct at a flagged pixel: the GPU value must be one of them
+                m2n, cn = m2d.numpy(), con.numpy()
+                opn, rgbn = np.asarray(gs.opacity, np.float64)[glob], np.asarray(gs.rgb, np.float64)[:, glob].T
+                for p_ in np.nonzero(fl)[0]:
+                    outs = render.composite_pixel_outcomes(xs[p_] + 0.5, ys[p_] + 0.5, range(glob.size), m2n, cn, opn,
+                                                           rgbn, np.asarray(cam.bg, np.float64))
+                    e = min(float(np.abs(gpu_px[p_] - np.asarray(o[0])).max()) for o in outs)
+                    flag_err = max(flag_err, e)
+                    n_flagged += 1
             d = rng.normal(size=(3, xs.size)).astype(np.float32)
             d[:, fl] = 0.0
             dL[v][:, ys, xs] = d
             tiles.append((v, glob, xs, ys, d))
     assert err_img <= IMG_TOL * max(img_max, 1e-6), (err_img, img_max)
-    say(f"  {len(tiles)} sampled tiles in {len(sample_views)} views: image error {err_img / max(img_max, 1e-6):.2e}")
+    assert flag_err <= IMG_TOL * max(img_max, 1e-6), (flag_err, img_max)
+    say(f"  {len(tiles)} sampled tiles in {len(sample_views)} views: image error {err_img / max(img_max, 1e-6):.2e}; "
+        f"{n_flagged} flagged pixels, each within {flag_err / max(img_max, 1e-6):.2e} of a correct outcome")
 
     g = api.render_bwd(rp, P, flat(dL), out).cpu().numpy()
     involved = np.unique(np.concatenate([t[1] for t in tiles]))

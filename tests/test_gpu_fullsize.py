@@ -15,11 +15,14 @@ construction give the Gaussian sets both sides render.  Checked against the orac
   backward, dL/dI is nonzero only on those tiles, so the oracle's autodiff over the same tiles gives
   every Gaussian's exact gradient.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
 
 import vbm_inputs as vi
+from oracle import dvr as odvr
 from oracle import dwt as odwt
 from tests.gpu_common import ROWS, adaptive_check, dev, oracle_gaussians, sampled_tile_parity, say
 
@@ -27,7 +30,7 @@ from tests.gpu_common import ROWS, adaptive_check, dev, oracle_gaussians, sample
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
 G, J, WAV = 512, 5, "bior4.4"
-W, H, TILE = 1920, 1080, 16
+W, H = 1920, 1080
 CASES = {"1M-8views": dict(K=1_000_000, views=8, sample=(1, 6)),
          "2M-16views": dict(K=2_000_000, views=16, sample=(3, 12))}
 
@@ -43,7 +46,7 @@ def h_case():
     gpu_coeffs = api.dwt3d(torch.from_numpy(vol).to(dev()), J, WAV, (tfn.xs, tfn.rgba))
     torch.cuda.synchronize()
     return dict(api=api, coeffs=coeffs, coeffs_d=torch.from_numpy(coeffs).to(dev()), gpu_coeffs=gpu_coeffs,
-                sets=dict(zip(CASES, sets)))
+                sets=dict(zip(CASES, sets)), vol=vol, tf=tfn)
 
 
 def test_fullsize_dwt_every_coefficient(h_case):
@@ -84,15 +87,52 @@ def test_fullsize_adaptive_selection(h_case):
         f"{[round(float(s['T']), 5) for s in so[-7:]]}")
 
 
-@pytest.mark.parametrize("case", list(CASES))
-def test_fullsize_render_sampled_tiles(h_case, case):
+# every schedule the autotuner chooses from (tile edge, tile-sort digit width) at the benchmark's
+# size, and the autotuner's usual pick at the large batch
+SCHEDULES = [("1M-8views", 16, 4), ("1M-8views", 16, 8), ("1M-8views", 8, 8), ("1M-8views", 32, 8),
+             ("2M-16views", 16, 4)]
+
+
+@pytest.mark.parametrize("case,tile,bits", SCHEDULES)
+def test_fullsize_render_sampled_tiles(h_case, case, tile, bits):
     api = h_case["api"]
     _, _, gs = h_case["sets"][case]
     cfg = CASES[case]
     cams = vi.orbit_cameras(cfg["views"], W, H)
     P = api.pack_params(gs.means, gs.scales, gs.quats, gs.opacity, gs.rgb, dev())
     N = P.shape[1]
-    say(f"  {case}: {N} Gaussians, {cfg['views']} views {W}x{H}")
-    rp = api.plan_batch(cams, [0, N], tile=TILE, sort_bits=8, pair_capacity=8_000_000 * cfg["views"],
+    say(f"  {case}: {N} Gaussians, {cfg['views']} views {W}x{H}, tile {tile}, {bits}-bit digits")
+    rp = api.plan_batch(cams, [0, N], tile=tile, sort_bits=bits, pair_capacity=8_000_000 * cfg["views"],
                         mode="batched")
-    sampled_tile_parity(rp, P, gs, cams, [0] * len(cams), [0, N], TILE, cfg["sample"], 10, 33)
+    sampled_tile_parity(rp, P, gs, cams, [0] * len(cams), [0, N], tile, cfg["sample"], 10, 33)
+
+
+def test_fullsize_schedules_list_the_tuner_candidates():
+    from paper_2601_09417_amd import trainer
+    assert {(t, b) for c, t, b in SCHEDULES if c == "1M-8views"} == set(trainer.TUNE_CANDIDATES)
+
+
+def test_fullsize_dvr_sampled_pixels(h_case):
+    """The supervision renderer at the size whose images the benchmark fits: the 512^3 volume from the
+    8 orbit views at 1920x1080, 400 random pixels per view plus the corners and the centre, against
+    the oracle's ray-marcher on the same rays, within 1e-5 of the sampled image maximum."""
+    api = h_case["api"]
+    vol, tfn = h_case["vol"], h_case["tf"]
+    cams = [dataclasses.replace(c, fx=float(np.float32(c.fx)), fy=float(np.float32(c.fy)))
+            for c in vi.orbit_cameras(8, W, H)]
+    img = api.dvr_render(torch.from_numpy(vol).to(dev()), (tfn.xs, tfn.rgba), cams)
+    views = api.split_views(img, cams)
+    rng = np.random.default_rng(8)
+    worst, n_near, n_pix = 0.0, 0, 0
+    for v, c in enumerate(cams):
+        px = np.concatenate([rng.integers(0, W, 400), [0, W - 1, 0, W - 1, W // 2]])
+        py = np.concatenate([rng.integers(0, H, 400), [0, 0, H - 1, H - 1, H // 2]])
+        ref, _, near = odvr.render(vol, tfn.xs, tfn.rgba, c, pixels=(px, py), flag_rel=1e-6)
+        got = views[v][:, torch.as_tensor(py), torch.as_tensor(px)].cpu().numpy()
+        n_near += int(near.sum())
+        n_pix += px.size
+        err = float(np.abs(got - ref)[:, ~near].max() / max(np.abs(ref).max(), 1e-6))
+        worst = max(worst, err)
+        assert err <= 1e-5, (v, err)
+    say(f"  dvr 512^3 at {W}x{H}: {n_pix} rays, error {worst:.2e} of the image maximum, {n_near} near the stop")
+    assert n_near <= 2

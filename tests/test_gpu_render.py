@@ -28,14 +28,16 @@ def _scene(n, seed, views, W, H, log_scale=-3.0, opacity=(0.05, 0.95)):
 LOW_OPACITY = (0.001, 0.007)
 
 
-@pytest.mark.parametrize("tile,opacity", [(8, (0.05, 0.95)), (16, (0.05, 0.95)), (32, (0.05, 0.95)),
-                                          (16, LOW_OPACITY)])
-def test_projection_and_pair_lists_bit_exact(tile, opacity):
+# every (tile, digit width) schedule the autotuner tries, and digit widths between
+@pytest.mark.parametrize("tile,bits,opacity", [(8, 8, (0.05, 0.95)), (16, 8, (0.05, 0.95)), (32, 8, (0.05, 0.95)),
+                                               (16, 4, (0.05, 0.95)), (16, 8, LOW_OPACITY), (16, 4, LOW_OPACITY),
+                                               (8, 5, (0.05, 0.95)), (32, 6, (0.05, 0.95))])
+def test_projection_and_pair_lists_bit_exact(tile, bits, opacity):
     api = _api()
     gs, cams = _scene(3000, 11, 3, 131, 77, opacity=opacity)
-    say(f"pair lists tile={tile} n={gs.n} views=3 131x77 opacity {opacity}")
+    say(f"pair lists tile={tile} digits={bits} n={gs.n} views=3 131x77 opacity {opacity}")
     P = to_dev(gs)
-    rp = api.plan_batch(cams, [0, gs.n], tile=tile, pair_capacity=1 << 20)
+    rp = api.plan_batch(cams, [0, gs.n], tile=tile, sort_bits=bits, pair_capacity=1 << 20)
     out = api.render_fwd(rp, P)
     torch.cuda.synchronize()
     ref = binning.pair_lists(gs, cams, tile)
@@ -289,3 +291,46 @@ def test_autograd_function_matches_oracle():
     G = P.grad.cpu().numpy()
     for name, rows in ROWS.items():
         assert group_error(G[rows], g_ref[name].reshape(rows.stop - rows.start, -1)) <= GRAD_TOL, name
+
+
+def test_autograd_two_forwards_on_one_plan():
+    """Two renders through one plan before either backward (a second loss, a re-render): the plan's
+    workspace holds only the later forward's lists, so each backward re-runs its own forward first.
+    Both gradients match the oracle's; a raw backward with the stale forward output is refused; a
+    render whose pairs overflow the plan raises instead of returning an incomplete image."""
+    from paper_2601_09417_amd import _lib as L
+    from paper_2601_09417_amd import trainer
+    api = _api()
+    gs1, cams = _scene(1000, 45, 2, 72, 56)
+    gs2 = vi.GaussianSet(gs1.means + np.float32(0.03) * np.random.default_rng(1).normal(size=gs1.means.shape).astype(
+        np.float32), gs1.scales * np.float32(1.2), gs1.quats, np.clip(gs1.opacity * np.float32(0.9), 0.01, 0.99),
+        gs1.rgb[::-1].copy())
+    say("autograd Function: two forwards on one plan, then both backwards")
+    rp = api.plan_batch(cams, [0, gs1.n], tile=16, pair_capacity=1 << 18)
+    P1 = to_dev(gs1).requires_grad_(True)
+    P2 = to_dev(gs2).requires_grad_(True)
+    img1 = trainer.VBMRender.apply(P1, rp)
+    img2 = trainer.VBMRender.apply(P2, rp)
+    refs, dLs = [], []
+    for k, gs in enumerate((gs1, gs2)):
+        batch = render.Batch(gs, cams, 16)
+        ref = render.render_forward(batch)
+        refs.append((batch, ref))
+        dLs.append(masked_dL(cams, [r["flagged"] for r in ref], seed=50 + k))
+    for img, (batch, ref) in zip((img1, img2), refs):
+        for v, got in enumerate(api.split_views(img.detach(), cams)):
+            assert image_error(got.cpu().numpy(), ref[v]["image"], ref[v]["flagged"]) <= IMG_TOL, v
+    (img1 * flat(dLs[0])).sum().backward()
+    (img2 * flat(dLs[1])).sum().backward()
+    for P, (batch, _), dL in ((P1, refs[0], dLs[0]), (P2, refs[1], dLs[1])):
+        g_ref, _ = render.render_backward(batch, dL)
+        G = P.grad.cpu().numpy()
+        for name, rows in ROWS.items():
+            assert group_error(G[rows], g_ref[name].reshape(rows.stop - rows.start, -1)) <= GRAD_TOL, name
+    a = api.render_fwd(rp, P1.detach())
+    api.render_fwd(rp, P2.detach())
+    with pytest.raises(L.VBMError):
+        api.render_bwd(rp, P1.detach(), torch.ones_like(a.image), a)
+    small = api.plan_batch(cams, [0, gs1.n], tile=16, pair_capacity=64)
+    with pytest.raises(L.VBMError):
+        trainer.VBMRender.apply(P1, small)

@@ -234,3 +234,35 @@ def test_footprint_threshold_bounds_the_log():
     tau = binning.footprint_tau(o).astype(np.float64)
     exact = 2 * np.log(255 * o.astype(np.float64))
     assert np.all(tau >= exact * 1.005 + 0.005)
+
+
+def _outcome_set(res):
+    return sorted((round(c[0], 12), round(c[1], 12), round(c[2], 12), n) for c, _, n in res)
+
+
+def test_pixel_outcomes_branch_at_thresholds():
+    """At a decision that sits on a threshold both outcomes are correct: a Gaussian whose alpha is
+    exactly 1/255 is kept or skipped, and one that takes T to 1e-4 (up to rounding) is added or ends
+    the pixel.  Away from the thresholds the only outcome is the plain compositing result."""
+    m2d = [(0.5, 0.5)] * 3
+    con = [(1.0, 0.0, 1.0)] * 3
+    rgb = [(1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0)]
+    bg = (0.0, 0.0, 0.0)
+    # alpha exactly at 1/255 (centred Gaussian: exp(0) = 1)
+    op = [1.0 / 255.0, 0.5, 0.3]
+    res = render.composite_pixel_outcomes(0.5, 0.5, [0, 1], m2d, con, op, rgb, bg)
+    a0 = 1.0 / 255.0
+    want = [([a0, 0.5 * (1 - a0), 0.0], None, 2), ([0.0, 0.5, 0.0], None, 2)]
+    assert _outcome_set(res) == _outcome_set(want)
+    # the second 0.99 takes T to (1 - 0.99)^2 = 1e-4 up to rounding
+    op = [0.99, 0.99, 0.3]
+    res = render.composite_pixel_outcomes(0.5, 0.5, [0, 1, 2], m2d, con, op, rgb, bg)
+    t1 = 1 - 0.99
+    add = ([0.99, 0.99 * t1, 0.0], None, 2)          # the third then takes T below 1e-4: stop
+    stop = ([0.99, 0.0, 0.0], None, 1)
+    assert _outcome_set(res) == _outcome_set([add, stop])
+    # nothing near a threshold: one outcome, the plain result
+    op = [0.6, 0.5, 0.3]
+    res = render.composite_pixel_outcomes(0.5, 0.5, [0, 1, 2], m2d, con, op, rgb, bg)
+    col, T, n = render.composite_pixel_bruteforce(0.5, 0.5, [0, 1, 2], m2d, con, op, rgb, bg)
+    assert len(res) == 1 and np.allclose(res[0][0], col, atol=0, rtol=0) and res[0][2] == n
