@@ -607,7 +607,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--cpu-tiles", type=int, default=256, help="tiles in the CPU oracle sample")
-    ap.add_argument("--cpu-threads", type=int, default=8)
+    ap.add_argument("--cpu-threads", type=int, default=0, help="threads of the CPU oracle (0 = every host CPU)")
     ap.add_argument("--convergence", type=int, default=0,
                     help="also train each ablation variant (Sec. 5) for this many steps and report PSNR")
     ap.add_argument("--modes", type=int, default=0,
@@ -636,8 +636,9 @@ def main() -> int:
         ctx = mp.get_context("spawn")
         queue = ctx.Queue()
         go = ctx.Event()
+        threads = args.cpu_threads or host_cpu()["nproc"]
         proc = ctx.Process(target=cpu_baseline_worker,
-                           args=(queue, go, args.workload, args.cpu_tiles, args.cpu_threads), daemon=True)
+                           args=(queue, go, args.workload, args.cpu_tiles, threads), daemon=True)
         proc.start()
         log(f"CPU oracle baseline process started (pid {proc.pid}); it runs after the GPU measurements")
 
