@@ -317,6 +317,28 @@ vbm_status vbm_image_loss(const float* image, const float* target, const int32_t
                           void* stream);
 
 /* ------------------------------------------------------------------------------------------
+ * vbm_image_loss_static -- vbm_image_loss for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation): the same loss, gradient
+ * and kernels, with the scratch space taken from a fixed device array inside the library instead of
+ * a workspace argument.  Nothing is allocated by the call.
+ *   Arguments as vbm_image_loss without ws / ws_bytes.
+ *   Limit: the call needs vbm_image_loss_workspace_size(view_dims, n_views, kind) <=
+ *   VBM_IMAGE_LOSS_STATIC_SCRATCH_BYTES (64 MiB): any size for L1 (kind 0, about 8 KiB), and about
+ *   1.8 million pixels in all views for L1 + D-SSIM (kind 1, 36 bytes per pixel).  Larger calls
+ *   return VBM_ERR_CAPACITY and launch nothing.
+ *   Each GPU holds one copy of the array (64 MiB, until the process ends), looked up at the first
+ *   call on that device.  Every call on a GPU uses that GPU's copy: calls that overlap on one GPU
+ *   (on different streams or threads without ordering) race and give wrong results; calls ordered
+ *   on one stream are fine.  Nothing in the array needs clearing between calls.
+ * Errors: those of vbm_image_loss, VBM_ERR_CAPACITY beyond the limit, VBM_ERR_HIP if the array's
+ * device address cannot be looked up.
+ * ------------------------------------------------------------------------------------------ */
+#define VBM_IMAGE_LOSS_STATIC_SCRATCH_BYTES (64u << 20)
+vbm_status vbm_image_loss_static(const float* image, const float* target, const int32_t* view_dims_host,
+                                 int32_t n_views, int32_t kind, float lambda, float* dL_dimg, float* loss_dev,
+                                 void* stream);
+
+/* ------------------------------------------------------------------------------------------
  * vbm_adam_step -- Adam (Sec. 5, Implementation Details) on the raw parameters.
  *   raw, m, v  float32 [14][stride]: rows 0-2 means, 3-5 log scales, 6-9 quats, 10 logit opacity,
  *              11-13 rgb

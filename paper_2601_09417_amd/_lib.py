@@ -8,6 +8,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libvbm.so")
 
 VBM_TF_MAX_POINTS = 16
+VBM_IMAGE_LOSS_STATIC_SCRATCH_BYTES = 64 << 20
 VBM_BANK_FLOATS = 12
 VBM_WS_REGIONS = 24
 MODE_BATCHED, MODE_EXACT = 0, 1
@@ -102,6 +103,8 @@ _SIGS = {
     "vbm_image_loss_workspace_size": (C.c_size_t, [C.POINTER(C.c_int32), C.c_int32, C.c_int32]),
     "vbm_image_loss": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.c_int32, C.c_float,
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "vbm_image_loss_static": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.c_int32,
+                                          C.c_float, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vbm_adam_step": (C.c_int32, [C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, vbm_gaussians_c,
                                   vbm_gaussians, C.POINTER(vbm_adam_opts), C.c_void_p, C.c_void_p]),
     "vbm_adam_init": (C.c_int32, [C.c_int64, C.c_int64, vbm_gaussians_c, C.c_void_p, C.c_void_p, C.c_void_p,

@@ -309,6 +309,24 @@ class ImageLoss:
         return self.loss
 
 
+def image_loss_static(image: torch.Tensor, target: torch.Tensor, view_dims, kind: str = "l1", lam: float = 0.2,
+                      grad: torch.Tensor | None = None, loss: torch.Tensor | None = None):
+    """The image loss through vbm_image_loss_static (no workspace: the library's fixed scratch array).
+    Returns (loss float32 [1], dL/dI); pass ``grad`` and ``loss`` to write into existing tensors."""
+    lib = L.load()
+    _require_cuda(image, target)
+    dims = np.ascontiguousarray(np.asarray(view_dims, dtype=np.int32).reshape(-1, 2))
+    if grad is None:
+        grad = torch.empty_like(image)
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float32, device=image.device)
+    st = lib.vbm_image_loss_static(image.data_ptr(), target.data_ptr(), dims.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   dims.shape[0], 0 if kind == "l1" else 1, float(lam), grad.data_ptr(),
+                                   loss.data_ptr(), _stream(image.device))
+    L.check(st, "vbm_image_loss_static")
+    return loss, grad
+
+
 LR_DEFAULT = (1e-3, 5e-3, 1e-3, 5e-3, 2.5e-3)  # means, log scales, quats, logit opacity, rgb
 
 

@@ -19,9 +19,15 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
+
+// Scratch of vbm_image_loss_static: one copy per GPU, held by the loaded code object until the
+// process ends.  In host code this name is only a stand-in for the symbol: the device address of
+// each GPU's copy comes from hipGetSymbolAddress (static_scratch_ptr below).
+static __device__ __align__(256) unsigned char scratch[VBM_IMAGE_LOSS_STATIC_SCRATCH_BYTES];
 
 namespace vbm {
 namespace {
@@ -423,6 +429,35 @@ extern "C" size_t vbm_image_loss_workspace_size(const int32_t* dims, int32_t n_v
   return 3 * align_up(3 * px * 4, 256) + 2 * align_up(blocks * 4, 256) + red;
 }
 
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's copy of `scratch`, looked up once per device (with that
+// device current) and kept; nullptr with the error set when the lookup fails.
+void* static_scratch_ptr() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    set_error("vbm_image_loss_static: no current device (or device index %d beyond %d)", dev, kMaxDevices);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      hip_check(e == hipSuccess ? hipErrorInvalidSymbol : e, "vbm_image_loss_static: hipGetSymbolAddress(scratch)");
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
 extern "C" vbm_status vbm_image_loss(const float* image, const float* target, const int32_t* dims, int32_t n_views,
                                      int32_t kind, float lambda, float* grad, float* loss, void* ws, size_t ws_bytes,
                                      void* stream) {
@@ -506,4 +541,26 @@ extern "C" vbm_status vbm_image_loss(const float* image, const float* target, co
                      static_cast<double>(lambda), loss);
   VBM_LAUNCH_CHECK("loss_finalize");
   return VBM_OK;
+}
+
+extern "C" vbm_status vbm_image_loss_static(const float* image, const float* target, const int32_t* dims,
+                                            int32_t n_views, int32_t kind, float lambda, float* grad, float* loss,
+                                            void* stream) {
+  if (!dims || n_views < 1) {
+    set_error("vbm_image_loss_static: null view sizes or n_views < 1");
+    return VBM_ERR_INVALID;
+  }
+  const size_t need = vbm_image_loss_workspace_size(dims, n_views, kind);
+  if (need > static_cast<size_t>(VBM_IMAGE_LOSS_STATIC_SCRATCH_BYTES)) {
+    set_error("vbm_image_loss_static: this loss needs %zu bytes of scratch, more than the fixed %zu; use "
+              "vbm_image_loss with a workspace",
+              need, static_cast<size_t>(VBM_IMAGE_LOSS_STATIC_SCRATCH_BYTES));
+    return VBM_ERR_CAPACITY;
+  }
+  void* ws = static_scratch_ptr();
+  if (!ws) return VBM_ERR_HIP;
+  // The passes write every scratch value before they read it (maps, per-block partial sums, the
+  // reduction stage), so nothing is cleared first.
+  return vbm_image_loss(image, target, dims, n_views, kind, lambda, grad, loss, ws,
+                        static_cast<size_t>(VBM_IMAGE_LOSS_STATIC_SCRATCH_BYTES), stream);
 }
