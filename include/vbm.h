@@ -216,7 +216,11 @@ vbm_status vbm_construct_gaussians(const float* coeffs, int32_t G, int32_t J, co
  * ascending (global tile, float32 depth bits, item) order, front-to-back compositing per pixel with
  * alpha = min(0.99, o exp(power)), skip alpha < 1/255, stop before adding once T would drop below
  * 1e-4.  Images are planar float32 [3][H][W] per view, concatenated in view order;
- * final_T and n_contrib are [H][W] per view, concatenated.
+ * final_T and n_contrib are [H][W] per view, concatenated: final_T is the transmittance left after
+ * compositing, n_contrib (int32) the number of entries of the pixel's tile list that its
+ * compositing took into account -- the list position of the Gaussian that would have taken T below
+ * 1e-4 (that Gaussian excluded), or the whole list length when that never happens; the backward
+ * reads both.
  * ------------------------------------------------------------------------------------------ */
 typedef struct {
   int32_t scene;
@@ -239,7 +243,7 @@ typedef struct {
   int32_t pad;
 } vbm_schedule;
 
-#define VBM_WS_REGIONS 24
+#define VBM_WS_REGIONS 32
 typedef struct {
   int32_t n_views, n_scenes, tile, mode;
   int32_t sort_bits, tile_key_bits, pad0, pad1;
@@ -260,9 +264,10 @@ typedef struct {
 #define VBM_REGION_ITEM_BLUE 5   /* float32 [n_items]: blue */
 #define VBM_REGION_PAIR_TILE 6   /* uint32 [pair_capacity]: sorted global tile of each pair */
 #define VBM_REGION_PAIR_ITEM 7   /* uint32 [pair_capacity]: sorted item of each pair in bits 0..26;
-                                  * with 8x8 and 16x16 tiles vbm_render_fwd sets bit 27 + k of a pair
-                                  * it visited when lane group k (pixel rows k*64/tile of the tile)
-                                  * was evaluated, and vbm_render_bwd reads those marks */
+                                  * with 8x8 and 16x16 tiles bits 27 + k mark lane group k (pixel rows
+                                  * k*64/tile .. of the tile): set by the binning when the footprint's
+                                  * rows reach the group, kept by the compositing forward for a group
+                                  * it evaluated, read by vbm_render_bwd */
 #define VBM_REGION_RANGES 8      /* uint32 [n_tiles][2]: [start, end) of each tile's list */
 #define VBM_REGION_GRAD2D 9      /* float32 [n_items][16]: dmean2d.xy, dconic.abc, dopacity, drgb in
                                   * columns 0..8 after vbm_render_bwd (rows of items never binned

@@ -85,18 +85,21 @@ def _tile_pixels(cam, tile, tx, ty):
     return XX.reshape(-1), YY.reshape(-1)
 
 
-def composite_tile(pix, m2d, con, op, rgb, bg, rel_alpha=1e-4, rel_t=1e-3):
+def composite_tile(pix, m2d, con, op, rgb, bg, rel_alpha=1e-4, rel_t=1e-3, return_stop=False):
     """Vectorised compositing of one tile.  pix [P][2] sample points, list tensors of length L.
 
-    Returns (color [P][3], final_T [P], n_contrib [P], flagged [P], contrib mask [P][L]).
+    Returns (color [P][3], final_T [P], n_contrib [P], flagged [P], contrib mask [P][L]), and with
+    ``return_stop`` also the stop position [P]: the list position of the Gaussian that would have
+    taken T below 1e-4, or L when none does (the number of list entries the pixel takes into account).
     ``flagged`` marks pixels where an evaluated Gaussian sits within a relative window of a decision
     threshold (1/255, 0.99 or the 1e-4 stop), where float32 and float64 may legitimately branch apart.
     """
     P, L = pix.shape[0], m2d.shape[0]
     if L == 0:
         z = torch.zeros(P, dtype=torch.bool)
-        return (bg[None, :].expand(P, 3).clone(), torch.ones(P, dtype=F64), torch.zeros(P, dtype=torch.int64), z,
-                torch.zeros(P, 0, dtype=torch.bool))
+        out = (bg[None, :].expand(P, 3).clone(), torch.ones(P, dtype=F64), torch.zeros(P, dtype=torch.int64), z,
+               torch.zeros(P, 0, dtype=torch.bool))
+        return out + (torch.zeros(P, dtype=torch.int64),) if return_stop else out
     dx = m2d[None, :, 0] - pix[:, None, 0]
     dy = m2d[None, :, 1] - pix[:, None, 1]
     power = -0.5 * (con[None, :, 0] * dx * dx + con[None, :, 2] * dy * dy) - con[None, :, 1] * dx * dy
@@ -121,6 +124,8 @@ def composite_tile(pix, m2d, con, op, rgb, bg, rel_alpha=1e-4, rel_t=1e-3):
     t_before = torch.cat([torch.ones(P, 1, dtype=F64), cp[:, :-1]], 1)
     t_final = cp[:, -1]
     color = (a_c * t_before) @ rgb + t_final[:, None] * bg[None, :]
+    if return_stop:
+        return color, t_final, n_contrib, flagged, contrib, s
     return color, t_final, n_contrib, flagged, contrib
 
 
@@ -181,7 +186,8 @@ class Batch:
 
 
 def render_forward(batch: Batch, rel_alpha=1e-4, rel_t=1e-3):
-    """Returns per view: image [3][H][W], final_T [H][W], n_contrib [H][W], flagged [H][W] (numpy)."""
+    """Returns per view: image [3][H][W], final_T [H][W], n_contrib [H][W], flagged [H][W] and
+    n_visited [H][W] (the stop position of composite_tile) (numpy)."""
     with torch.no_grad():
         P = batch.leaf_params()
         m2d, con, op, rgb = batch.project_items(P)
@@ -189,19 +195,21 @@ def render_forward(batch: Batch, rel_alpha=1e-4, rel_t=1e-3):
     for cam in batch.cams:
         out.append(dict(image=np.zeros((3, cam.height, cam.width)), final_T=np.ones((cam.height, cam.width)),
                         n_contrib=np.zeros((cam.height, cam.width), dtype=np.int64),
-                        flagged=np.zeros((cam.height, cam.width), dtype=bool)))
+                        flagged=np.zeros((cam.height, cam.width), dtype=bool),
+                        n_visited=np.zeros((cam.height, cam.width), dtype=np.int64)))
     with torch.no_grad():
         for v, tx, ty, gt, xs, ys, it in batch.tiles():
             cam = batch.cams[v]
             it_t = torch.as_tensor(it, dtype=torch.int64)
             pix = torch.stack([_t(xs + 0.5), _t(ys + 0.5)], 1)
-            col, tf, nc, fl, _ = composite_tile(pix, m2d[it_t], con[it_t], op[it_t], rgb[it_t], _t(cam.bg),
-                                                rel_alpha, rel_t)
+            col, tf, nc, fl, _, stop = composite_tile(pix, m2d[it_t], con[it_t], op[it_t], rgb[it_t], _t(cam.bg),
+                                                      rel_alpha, rel_t, return_stop=True)
             o = out[v]
             o["image"][:, ys, xs] = col.T.numpy()
             o["final_T"][ys, xs] = tf.numpy()
             o["n_contrib"][ys, xs] = nc.numpy()
             o["flagged"][ys, xs] = fl.numpy()
+            o["n_visited"][ys, xs] = stop.numpy()
     return out
 
 

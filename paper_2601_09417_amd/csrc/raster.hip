@@ -5,9 +5,11 @@
 // four independent waves, an 8x8 tile one wave with one pixel per lane), each lane owning
 // PPL = 4 pixels of ONE pixel column (rows 64 / TILE apart), so the horizontal offset to a
 // Gaussian's centre is shared by a lane's pixels.  The tile's depth-sorted list is walked by every
-// wave in lockstep: a Gaussian's item id and its 36-byte record are wave-uniform, fetched with
-// buffer loads at a uniform offset (records two list steps ahead of use, item ids four) -- no LDS
-// staging, no barriers, and the per-Gaussian load cost is amortised over 256 pixels.
+// wave in lockstep: a Gaussian's pair value and its 36-byte record are wave-uniform and go through
+// the scalar data cache into SGPRs (each one list step ahead of its use) -- no LDS staging, no
+// barriers, no per-lane copies of a uniform value, and the per-Gaussian load cost is amortised
+// over 256 pixels.  A vector load of a uniform address would still move 64 lanes' copies through
+// the texture address and data units, which the list walk would saturate.
 //
 // The record holds the exponent in base 2 with the log-opacity folded in:
 //   e2(d) = hA dx^2 + hB dx dy + hC dy^2 + log2(o) = log2(o) + power(d) log2(e),
@@ -36,7 +38,7 @@ constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 // Item ids stay below 2^27 (the plan enforces it); the forward keeps per-pair lane-group marks in
 // the bits above.
-constexpr int kItemBits = 27;
+constexpr int kItemBits = kPairMarkShift;
 constexpr uint32_t kItemMask = (1u << kItemBits) - 1u;
 
 template <int TILE>
@@ -63,62 +65,53 @@ struct Rec {
   float mx, my, hA, hB, hC, lo, r, g, b;
 };
 
-typedef int v4i __attribute__((ext_vector_type(4)));
-constexpr int kRsrcWord3 = 0x00020000;  // raw (untyped) buffer access on the gfx9 family
-
-// Buffer descriptors of the arrays the list walk reads.  Buffer loads are vector-memory
-// operations (completed in issue order, so a prefetch is waited for exactly) with a
-// uniform SGPR offset (no per-lane address arithmetic), and the hardware range check turns a read
-// past num_records into a zero instead of an access fault.
-struct ListSrc {
-  __amdgpu_buffer_rsrc_t items, coef, blue;
-};
-
-__device__ __forceinline__ ListSrc make_list_src(const uint32_t* pair_item, int64_t n_pairs, const float* coef,
-                                                 const float* blue, int64_t n_items) {
-  // num_records is a 32-bit byte count: the plan bounds n_items by 2^27 and n_pairs by 2^30.
-  ListSrc s;
-  s.items = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(pair_item), (short)0,
-                                              static_cast<int>(static_cast<uint32_t>(n_pairs * 4)), kRsrcWord3);
-  s.coef = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(coef), (short)0,
-                                             static_cast<int>(static_cast<uint32_t>(n_items * 32)), kRsrcWord3);
-  s.blue = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(blue), (short)0,
-                                             static_cast<int>(static_cast<uint32_t>(n_items * 4)), kRsrcWord3);
-  return s;
+// The forward reads pair values with vector buffer loads, three list steps ahead: they complete
+// in issue order (so each is waited for exactly, without waiting for the next record's scalar
+// loads) and a position past num_records reads zero instead of faulting.  num_records is a 32-bit
+// byte count; the plan bounds the pair capacity by 2^30.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t item_rsrc(const uint32_t* pair_item, int64_t n_pairs) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(pair_item), (short)0,
+                                           static_cast<int>(static_cast<uint32_t>(n_pairs * 4)), 0x00020000);
+}
+__device__ __forceinline__ uint32_t load_item(__amdgpu_buffer_rsrc_t items, int j) {
+  return static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b32(items, 0, 4 * j, 0));
 }
 
-__device__ __forceinline__ uint32_t load_item(const ListSrc& s, int j) {
-  return static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b32(s.items, 0, 4 * j, 0));
-}
-
-// Rewrites the n <= 3 pair values j, j + 1, j + 2 (uniform v0, v1, v2) with one vector store from
-// lanes 0 .. n - 1.
-__device__ __forceinline__ void store_pair_values(const ListSrc& s, int lane, int j, int n, uint32_t v0, uint32_t v1,
-                                                  uint32_t v2) {
+// Rewrites the n <= 3 pair values j, j + 1, j + 2 (uniform v0, v1, v2) of the marked copy with
+// one vector store from lanes 0 .. n - 1.
+__device__ __forceinline__ void store_pair_values(uint32_t* __restrict__ marked, int lane, int j, int n, uint32_t v0,
+                                                  uint32_t v1, uint32_t v2) {
   const uint32_t v = lane == 0 ? v0 : lane == 1 ? v1 : v2;
-  if (lane < n) __builtin_amdgcn_raw_buffer_store_b32(v, s.items, 4 * lane, 4 * j, 0);
-}
-
-// The record of a pair value (the item id in its low kItemBits bits).
-__device__ __forceinline__ Rec load_rec(const ListSrc& s, uint32_t pv) {
-  const uint32_t it = pv & kItemMask;
-  const int off = static_cast<int>(32u * it);
-  const v4i a = __builtin_amdgcn_raw_buffer_load_b128(s.coef, 0, off, 0);
-  const v4i b = __builtin_amdgcn_raw_buffer_load_b128(s.coef, 16, off, 0);
-  Rec r;
-  r.mx = __int_as_float(a.x);
-  r.my = __int_as_float(a.y);
-  r.hA = __int_as_float(a.z);
-  r.hB = __int_as_float(a.w);
-  r.hC = __int_as_float(b.x);
-  r.lo = __int_as_float(b.y);
-  r.r = __int_as_float(b.z);
-  r.g = __int_as_float(b.w);
-  r.b = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(s.blue, 0, static_cast<int>(4u * it), 0));
-  return r;
+  if (lane < n) marked[j + lane] = v;
 }
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// The record of a (wave-uniform) pair value, fetched through the scalar data cache into SGPRs.
+// The item id is clamped to the record arrays (a past-the-end or empty-list step reads a valid
+// record that it then ignores).
+__device__ __forceinline__ Rec load_rec_s(const float4* __restrict__ crec, const float* __restrict__ cblue,
+                                          uint32_t pv, uint32_t imax) {
+  const uint32_t it = min(pv & kItemMask, imax);
+  const float4 a = crec[2 * it];
+  const float4 b = crec[2 * it + 1];
+  Rec r;
+  r.mx = a.x;
+  r.my = a.y;
+  r.hA = a.z;
+  r.hB = a.w;
+  r.hC = b.x;
+  r.lo = b.y;
+  r.r = b.z;
+  r.g = b.w;
+  r.b = cblue[it];
+  return r;
+}
+
+// Waits for every scalar load in flight (they may complete out of order, so only a full wait
+// identifies one): the list walks call it where the next record's loads are about to be issued,
+// so that the wait covers the record requested one step earlier and not the next one.
+__device__ __forceinline__ void wait_scalar_loads() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
 // True when the predicate holds on some active lane: one scalar test of the predicate's lane mask.
 __device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
@@ -254,20 +247,27 @@ __device__ __forceinline__ bool any_live(const float (&fy)[PPL]) {
   return wave_any(m < kLiveBound);
 }
 
-// One list step of the forward for the lane's pixels: alpha = min(0.99, 2^e2); a pixel takes the
-// Gaussian when alpha >= 1/255, unless the new transmittance would fall below 1e-4, in which case
-// the pixel stops without it.  Returns the mask of lane groups k that were evaluated: every group
-// with a pixel that took the Gaussian is among them.
+// One list step (0-based list position pos) of the forward for the lane's pixels:
+// alpha = min(0.99, 2^e2); a pixel takes the Gaussian when alpha >= 1/255, unless the new
+// transmittance would fall below 1e-4, in which case the pixel stops without it and records pos as
+// the number of list entries its compositing took into account.  `reach` holds the lane groups
+// that the binning found the Gaussian's footprint to reach (the others have alpha < 1/255 at every
+// pixel and are skipped without evaluating anything).  Returns the mask of lane groups k that were
+// evaluated: every group with a pixel that took the Gaussian is among them.
 template <int PPL, bool STATS>
-__device__ __forceinline__ uint32_t fwd_step(const Rec& r, int pos, float fx, float (&fy)[PPL], float (&T)[PPL],
-                                             float (&cr)[PPL], float (&cg)[PPL], float (&cb)[PPL], int (&last)[PPL],
-                                             uint32_t& n_eval, uint32_t& n_used) {
+__device__ __forceinline__ uint32_t fwd_step(const Rec& r, uint32_t reach, int pos, float fx, float (&fy)[PPL],
+                                             float (&T)[PPL], float (&cr)[PPL], float (&cg)[PPL], float (&cb)[PPL],
+                                             int (&nvis)[PPL], uint32_t& n_eval, uint32_t& n_used) {
   uint32_t groups = 0;
   const float dx = r.mx - fx;
   const float u = fmaf(r.hA, dx * dx, r.lo);
   const float vb = r.hB * dx;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
+    if (!((reach >> k) & 1u)) {
+      if (STATS) n_eval += fy[k] < kLiveBound ? 1u : 0u;
+      continue;
+    }
     const float dy = r.my - fy[k];
     const float e2 = exponent2(r, u, vb, dy);
     // A lane group where every pixel has 2^e2 clearly below 1/255 (or is terminated, e2 = -inf)
@@ -281,26 +281,26 @@ __device__ __forceinline__ uint32_t fwd_step(const Rec& r, int pos, float fx, fl
     const bool ok = alpha >= kAlphaMin;
     // A pixel that fails the alpha test takes weight 0, which leaves T and its colour unchanged.
     float w = (ok ? alpha : 0.0f) * T[k];
-    float Tn = T[k] - w;
+    T[k] -= w;
     // A live pixel keeps T >= 1e-4, so only one that takes the Gaussian can fall below: it stops
-    // without it (rare, so handled in a uniform branch).
-    const bool stop = Tn < kTMin;
-    if (wave_any(stop)) {
+    // without it (rare, so handled in a uniform branch), its transmittance going back to the value
+    // before the Gaussian (T + w, within a unit in the last place of it).
+    if (wave_any(T[k] < kTMin)) {
       __asm__ volatile("" ::: "memory");   // keeps this a branch: the compiler would select both ways
+      const bool stop = T[k] < kTMin;
+      T[k] = stop ? T[k] + w : T[k];
       w = stop ? 0.0f : w;
-      Tn = stop ? T[k] : Tn;
       fy[k] = stop ? kDeadRow : fy[k];
+      nvis[k] = stop ? pos : nvis[k];
+      if (STATS) n_eval += stop ? 1u : 0u;
     }
-    const bool use = ok && !stop;
     if (STATS) {
-      n_eval += fy[k] < kLiveBound || stop ? 1u : 0u;
-      n_used += use ? 1u : 0u;
+      n_eval += fy[k] < kLiveBound ? 1u : 0u;
+      n_used += ok && fy[k] < kLiveBound ? 1u : 0u;
     }
     cr[k] = fmaf(r.r, w, cr[k]);
     cg[k] = fmaf(r.g, w, cg[k]);
     cb[k] = fmaf(r.b, w, cb[k]);
-    T[k] = Tn;
-    last[k] = use ? pos : last[k];
   }
   return groups;
 }
@@ -309,9 +309,9 @@ template <int TILE, bool STATS>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
     const DevView* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ tile_order,
-    uint32_t* __restrict__ pair_item, int64_t n_pairs, const float* __restrict__ coef,
-    const float* __restrict__ blue, int64_t n_items, float* __restrict__ image, float* __restrict__ final_T,
-    int32_t* __restrict__ n_contrib, unsigned long long* __restrict__ stats) {
+    const uint32_t* __restrict__ pair_item, int64_t n_pairs, uint32_t* __restrict__ pair_marked,
+    const float* __restrict__ coef, const float* __restrict__ blue, int64_t n_items, float* __restrict__ image,
+    float* __restrict__ final_T, int32_t* __restrict__ n_contrib, unsigned long long* __restrict__ stats) {
   using C = TileCfg<TILE>;
   constexpr int PPL = C::kPPL;
   const int lane = static_cast<int>(threadIdx.x) & 63;
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
   const int local = tile - v.tile_offset;
   const int tx = local % v.tiles_x, ty = local / v.tiles_x;
   float fy[PPL], T[PPL], cr[PPL], cg[PPL], cb[PPL];
-  int last[PPL];
+  int nvis[PPL];
   bool inside[PPL];
   int py[PPL];
   const int q0 = wave * (C::kPix / C::kWaves) + lane;
@@ -334,47 +334,59 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
     fy[k] = inside[k] ? static_cast<float>(py[k]) + 0.5f : kDeadRow;
     T[k] = 1.0f;
     cr[k] = cg[k] = cb[k] = 0.0f;
-    last[k] = 0;
   }
   const uint2 rg = ranges[tile];
   const int start = static_cast<int>(rg.x), end = static_cast<int>(rg.y);
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) nvis[k] = end - start;
   uint32_t n_eval = 0, n_used = 0;
   // Load pipeline, unrolled by three so that buffers rotate without copies: the record of list
   // step s is requested at step s - 2 and the item id that addresses it at step s - 4 (three
   // record buffers R, three item slots L).  All three steps of an iteration run (a branch between
   // them would let the compiler sink the prefetch below it); past the end of the list a record is
   // a clamped duplicate whose log-opacity is set to -inf, so alpha = 0 and it changes nothing.
-  const ListSrc src = make_list_src(pair_item, n_pairs, coef, blue, n_items);
   const int lastj = end > start ? end - 1 : start;
-  // With one wave per tile, each processed pair value is written back with the mask of the lane
-  // groups that the step evaluated in bits kItemBits.. (see fwd_step): the backward visits only
-  // those groups.
+  // With one wave per tile, a pair value carries in bits kItemBits.. the lane groups that the
+  // binning found the footprint to reach, and each processed pair value is copied to pair_marked
+  // with the mask of the groups that the step evaluated (see fwd_step): the backward visits only
+  // those, reading the copy through the scalar cache.
   constexpr bool kMark = C::kWaves == 1;
-  uint32_t u0 = uniform(load_item(src, start)), u1 = uniform(load_item(src, min(start + 1, lastj))), u2;
-  Rec R0 = load_rec(src, u0);
-  Rec R1 = load_rec(src, u1);
-  Rec R2;
-  uint32_t L1, L2 = load_item(src, min(start + 2, lastj)), L0 = load_item(src, min(start + 3, lastj));
+  constexpr uint32_t kAll = (1u << PPL) - 1u;
+  // Records through the scalar cache one list step ahead of their use, pair values by vector loads
+  // three steps ahead (measured faster here than scalar pair-value loads, which put a second
+  // scalar round trip in front of every record), unrolled by three so that the item slots rotate
+  // without copies.
+  const __amdgpu_buffer_rsrc_t irs = item_rsrc(pair_item, n_pairs);
+  const float4* __restrict__ crec = reinterpret_cast<const float4*>(coef);
+  const uint32_t imax = n_items > 0 ? static_cast<uint32_t>(n_items - 1) : 0u;
+  uint32_t u0 = uniform(load_item(irs, start)), u1, u2;
+  Rec R0 = load_rec_s(crec, blue, u0, imax), R1, R2;
+  uint32_t L1 = load_item(irs, min(start + 1, lastj)), L2 = load_item(irs, min(start + 2, lastj)),
+           L0 = load_item(irs, min(start + 3, lastj));
   for (int j = start; j < end; j += 3) {
     if (!any_live(fy)) break;
-    u2 = uniform(L2);
-    R2 = load_rec(src, u2);
-    L1 = load_item(src, min(j + 4, lastj));
-    const uint32_t m0 = (u0 & kItemMask) | (fwd_step<PPL, STATS>(R0, j - start + 1, fx, fy, T, cr, cg, cb, last,
-                                                                  n_eval, n_used) << kItemBits);
-    R1.lo = j + 1 < end ? R1.lo : -__builtin_inff();
-    u0 = uniform(L0);
-    R0 = load_rec(src, u0);
-    L2 = load_item(src, min(j + 5, lastj));
-    const uint32_t m1 = (u1 & kItemMask) | (fwd_step<PPL, STATS>(R1, j - start + 2, fx, fy, T, cr, cg, cb, last,
-                                                                  n_eval, n_used) << kItemBits);
-    R2.lo = j + 2 < end ? R2.lo : -__builtin_inff();
+    wait_scalar_loads();
     u1 = uniform(L1);
-    R1 = load_rec(src, u1);
-    L0 = load_item(src, min(j + 6, lastj));
-    const uint32_t m2 = (u2 & kItemMask) | (fwd_step<PPL, STATS>(R2, j - start + 3, fx, fy, T, cr, cg, cb, last,
-                                                                  n_eval, n_used) << kItemBits);
-    if (kMark) store_pair_values(src, lane, j, min(end - j, 3), m0, m1, m2);
+    R1 = load_rec_s(crec, blue, u1, imax);
+    L1 = load_item(irs, min(j + 4, lastj));
+    const uint32_t m0 = (u0 & kItemMask) | (fwd_step<PPL, STATS>(R0, kMark ? u0 >> kItemBits : kAll, j - start, fx, fy,
+                                                                  T, cr, cg, cb, nvis, n_eval, n_used) << kItemBits);
+    wait_scalar_loads();
+    R1.lo = j + 1 < end ? R1.lo : -__builtin_inff();
+    u2 = uniform(L2);
+    R2 = load_rec_s(crec, blue, u2, imax);
+    L2 = load_item(irs, min(j + 5, lastj));
+    const uint32_t un = uniform(L0);
+    const uint32_t m1 = (u1 & kItemMask) | (fwd_step<PPL, STATS>(R1, kMark ? u1 >> kItemBits : kAll, j - start + 1, fx,
+                                                                  fy, T, cr, cg, cb, nvis, n_eval, n_used) << kItemBits);
+    wait_scalar_loads();
+    R2.lo = j + 2 < end ? R2.lo : -__builtin_inff();
+    R0 = load_rec_s(crec, blue, un, imax);
+    L0 = load_item(irs, min(j + 6, lastj));
+    const uint32_t m2 = (u2 & kItemMask) | (fwd_step<PPL, STATS>(R2, kMark ? u2 >> kItemBits : kAll, j - start + 2, fx,
+                                                                  fy, T, cr, cg, cb, nvis, n_eval, n_used) << kItemBits);
+    if (kMark) store_pair_values(pair_marked, lane, j, min(end - j, 3), m0, m1, m2);
+    u0 = un;
   }
   if (STATS) add_stats(stats, n_eval, n_used);
   const int64_t HW = static_cast<int64_t>(v.width) * v.height;
@@ -387,7 +399,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
     img[HW + pix] = cg[k] + T[k] * v.bg[1];
     img[2 * HW + pix] = cb[k] + T[k] * v.bg[2];
     final_T[v.pixel_offset + pix] = T[k];
-    n_contrib[v.pixel_offset + pix] = last[k];
+    n_contrib[v.pixel_offset + pix] = nvis[k];
   }
 }
 
@@ -465,7 +477,7 @@ template <int TILE, bool STATS>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
     const DevView* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ tile_order,
-    const uint32_t* __restrict__ pair_item, int64_t n_pairs, const float* __restrict__ coef,
+    const uint32_t* __restrict__ pair_values, const float* __restrict__ coef,
     const float* __restrict__ blue, const float* __restrict__ final_T, const int32_t* __restrict__ n_contrib,
     const float* __restrict__ dL_dimg, float* __restrict__ grad2d, int64_t n_items,
     unsigned long long* __restrict__ stats) {
@@ -517,90 +529,111 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
   // the atomics issued at the end of the previous step: vector-memory operations complete in issue
   // order, and the newest operation a step waits for was issued two steps earlier.  Positions
   // below 0 are clamped to 0 and their loads never used.
-  const ListSrc src = make_list_src(pair_item, n_pairs, coef, blue, n_items);
-  constexpr bool kMarked = C::kWaves == 1;   // the forward marked each pair's evaluated groups
+  // pair_values: the forward's marked copy with one wave per tile (marks of the groups it
+  // evaluated), else the sorted pair values.
+  constexpr bool kMarked = C::kWaves == 1;
+  // Records through the scalar cache one step ahead, item ids by vector loads three ahead (the
+  // forward's pipeline, walking positions maxn - 1 .. 0; positions below 0 are clamped to 0 and
+  // their loads never used).
+  const float4* __restrict__ crec = reinterpret_cast<const float4*>(coef);
+  const uint32_t imax = n_items > 0 ? static_cast<uint32_t>(n_items - 1) : 0u;
   const int top = max(maxn - 1, 0);
-  uint32_t u0 = uniform(load_item(src, start + top));
-  uint32_t u1 = uniform(load_item(src, start + max(top - 1, 0)));
-  uint32_t u2;
-  Rec R0 = load_rec(src, u0);
-  Rec R1 = load_rec(src, u1);
-  Rec R2;
-  uint32_t L1, L2 = load_item(src, start + max(top - 2, 0)), L0 = load_item(src, start + max(top - 3, 0));
+  uint32_t u0 = pair_values[start + top];
+  Rec R0 = load_rec_s(crec, blue, u0, imax), R1, R2;
+  uint32_t u1 = pair_values[start + max(top - 1, 0)], u2;
   for (int j = maxn - 1; j >= 0; j -= 3) {
-    u2 = uniform(L2);
-    R2 = load_rec(src, u2);
-    L1 = load_item(src, start + max(j - 4, 0));
+    wait_scalar_loads();
+    R1 = load_rec_s(crec, blue, u1, imax);
+    u2 = pair_values[start + max(j - 2, 0)];
     bwd_step<PPL, kMarked, kCols, STATS>(R0, u0, j, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
     if (j == 0) break;
-    u0 = uniform(L0);
-    R0 = load_rec(src, u0);
-    L2 = load_item(src, start + max(j - 5, 0));
+    wait_scalar_loads();
+    R2 = load_rec_s(crec, blue, u2, imax);
+    u0 = pair_values[start + max(j - 3, 0)];
     bwd_step<PPL, kMarked, kCols, STATS>(R1, u1, j - 1, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
     if (j == 1) break;
-    u1 = uniform(L1);
-    R1 = load_rec(src, u1);
-    L0 = load_item(src, start + max(j - 6, 0));
+    wait_scalar_loads();
+    R0 = load_rec_s(crec, blue, u0, imax);
+    u1 = pair_values[start + max(j - 4, 0)];
     bwd_step<PPL, kMarked, kCols, STATS>(R2, u2, j - 2, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
   }
   if (STATS) add_stats(stats, n_eval, n_used);
 }
 
 template <int TILE>
-static vbm_status launch_fwd_t(const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges, const uint32_t* tile_order,
-                               uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
-                               int64_t n_items, float* image, float* final_T, int32_t* n_contrib,
-                               unsigned long long* stats, hipStream_t s) {
+static vbm_status launch_fwd_t(const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
+                               const uint32_t* tile_order, const uint32_t* pair_item, int64_t n_pairs,
+                               uint32_t* pair_marked, const float* coef, const float* blue, int64_t n_items,
+                               float* image, float* final_T, int32_t* n_contrib, unsigned long long* stats,
+                               hipStream_t s) {
   const dim3 block(TileCfg<TILE>::kThreads);
   if (stats)
-    hipLaunchKernelGGL((k_composite_fwd<TILE, true>), dim3(n_tiles), block, 0, s, views, n_views, ranges, tile_order, pair_item,
-                       n_pairs, coef, blue, n_items, image, final_T, n_contrib, stats);
+    hipLaunchKernelGGL((k_composite_fwd<TILE, true>), dim3(n_tiles), block, 0, s, views, n_views, ranges, tile_order,
+                       pair_item, n_pairs, pair_marked, coef, blue, n_items, image, final_T, n_contrib, stats);
   else
-    hipLaunchKernelGGL((k_composite_fwd<TILE, false>), dim3(n_tiles), block, 0, s, views, n_views, ranges, tile_order, pair_item,
-                       n_pairs, coef, blue, n_items, image, final_T, n_contrib, stats);
+    hipLaunchKernelGGL((k_composite_fwd<TILE, false>), dim3(n_tiles), block, 0, s, views, n_views, ranges, tile_order,
+                       pair_item, n_pairs, pair_marked, coef, blue, n_items, image, final_T, n_contrib, stats);
   VBM_LAUNCH_CHECK("composite_fwd");
   return VBM_OK;
 }
 
 template <int TILE>
-static vbm_status launch_bwd_t(const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges, const uint32_t* tile_order,
-                               const uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
-                               const float* final_T,
-                               const int32_t* n_contrib, const float* dL_dimg, float* grad2d, int64_t n_items,
-                               unsigned long long* stats, hipStream_t s) {
+static vbm_status launch_bwd_t(const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
+                               const uint32_t* tile_order, const uint32_t* pair_item, const uint32_t* pair_marked,
+                               const float* coef, const float* blue, const float* final_T, const int32_t* n_contrib,
+                               const float* dL_dimg, float* grad2d, int64_t n_items, unsigned long long* stats,
+                               hipStream_t s) {
   const dim3 block(TileCfg<TILE>::kThreads);
+  // one wave per tile: the forward's marked copy; otherwise the sorted pair values
+  const uint32_t* values = TileCfg<TILE>::kWaves == 1 ? pair_marked : pair_item;
   if (stats)
-    hipLaunchKernelGGL((k_composite_bwd<TILE, true>), dim3(n_tiles), block, 0, s, views, n_views, ranges, tile_order, pair_item,
-                       n_pairs, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats);
+    hipLaunchKernelGGL((k_composite_bwd<TILE, true>), dim3(n_tiles), block, 0, s, views, n_views, ranges, tile_order,
+                       values, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats);
   else
-    hipLaunchKernelGGL((k_composite_bwd<TILE, false>), dim3(n_tiles), block, 0, s, views, n_views, ranges, tile_order, pair_item,
-                       n_pairs, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats);
+    hipLaunchKernelGGL((k_composite_bwd<TILE, false>), dim3(n_tiles), block, 0, s, views, n_views, ranges, tile_order,
+                       values, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats);
   VBM_LAUNCH_CHECK("composite_bwd");
   return VBM_OK;
 }
 
-vbm_status launch_composite_fwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges, const uint32_t* tile_order,
-                                uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
-                                int64_t n_items, float* image, float* final_T, int32_t* n_contrib,
-                                unsigned long long* stats, hipStream_t s) {
+vbm_status launch_composite_fwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
+                                const uint32_t* tile_order, const uint32_t* pair_item, int64_t n_pairs,
+                                uint32_t* pair_marked, const float* coef, const float* blue, int64_t n_items,
+                                float* image, float* final_T, int32_t* n_contrib, unsigned long long* stats,
+                                hipStream_t s) {
   switch (tile) {
-    case 8: return launch_fwd_t<8>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, coef, blue, n_items, image, final_T, n_contrib, stats, s);
-    case 16: return launch_fwd_t<16>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, coef, blue, n_items, image, final_T, n_contrib, stats, s);
-    case 32: return launch_fwd_t<32>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, coef, blue, n_items, image, final_T, n_contrib, stats, s);
+    case 8:
+      return launch_fwd_t<8>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, pair_marked, coef,
+                             blue, n_items,
+                             image, final_T, n_contrib, stats, s);
+    case 16:
+      return launch_fwd_t<16>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, pair_marked, coef,
+                              blue, n_items,
+                              image, final_T, n_contrib, stats, s);
+    case 32:
+      return launch_fwd_t<32>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, pair_marked, coef,
+                              blue, n_items,
+                              image, final_T, n_contrib, stats, s);
   }
   set_error("unsupported tile size %d", tile);
   return VBM_ERR_UNSUPPORTED;
 }
 
-vbm_status launch_composite_bwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges, const uint32_t* tile_order,
-                                const uint32_t* pair_item, int64_t n_pairs, const float* coef, const float* blue,
-                                const float* final_T,
-                                const int32_t* n_contrib, const float* dL_dimg, float* grad2d, int64_t n_items,
-                                unsigned long long* stats, hipStream_t s) {
+vbm_status launch_composite_bwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
+                                const uint32_t* tile_order, const uint32_t* pair_item, const uint32_t* pair_marked,
+                                const float* coef, const float* blue, const float* final_T, const int32_t* n_contrib,
+                                const float* dL_dimg, float* grad2d, int64_t n_items, unsigned long long* stats,
+                                hipStream_t s) {
   switch (tile) {
-    case 8: return launch_bwd_t<8>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s);
-    case 16: return launch_bwd_t<16>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s);
-    case 32: return launch_bwd_t<32>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s);
+    case 8:
+      return launch_bwd_t<8>(views, n_views, n_tiles, ranges, tile_order, pair_item, pair_marked, coef, blue, final_T,
+                             n_contrib, dL_dimg, grad2d, n_items, stats, s);
+    case 16:
+      return launch_bwd_t<16>(views, n_views, n_tiles, ranges, tile_order, pair_item, pair_marked, coef, blue, final_T,
+                              n_contrib, dL_dimg, grad2d, n_items, stats, s);
+    case 32:
+      return launch_bwd_t<32>(views, n_views, n_tiles, ranges, tile_order, pair_item, pair_marked, coef, blue, final_T,
+                              n_contrib, dL_dimg, grad2d, n_items, stats, s);
   }
   set_error("unsupported tile size %d", tile);
   return VBM_ERR_UNSUPPORTED;

@@ -152,7 +152,8 @@ def test_forward_backward_parity(tile, W, H):
         assert err <= IMG_TOL
         ok = ~ref[v]["flagged"]
         assert np.abs(fts[v] - ref[v]["final_T"])[ok].max() <= 1e-5
-        assert np.array_equal(ncs[v][ok], ref[v]["n_contrib"][ok])
+        # the number of list entries each pixel took into account (its stop position, else the list length)
+        assert np.array_equal(ncs[v][ok], ref[v]["n_visited"][ok])
     dL = masked_dL(cams, [r["flagged"] for r in ref], seed=tile)
     grads = api.render_bwd(rp, P, flat(dL), out)
     g_ref, g2_ref = render.render_backward(batch, dL)

@@ -266,3 +266,28 @@ def test_pixel_outcomes_branch_at_thresholds():
     res = render.composite_pixel_outcomes(0.5, 0.5, [0, 1, 2], m2d, con, op, rgb, bg)
     col, T, n = render.composite_pixel_bruteforce(0.5, 0.5, [0, 1, 2], m2d, con, op, rgb, bg)
     assert len(res) == 1 and np.allclose(res[0][0], col, atol=0, rtol=0) and res[0][2] == n
+
+
+def test_stop_position_bounds_the_contributions():
+    """n_visited (the stop position, else the list length) is at least n_contrib (the last
+    contributor + 1) and every list entry between them fails the alpha test, so a backward that
+    takes entries below n_visited with alpha >= 1/255 visits exactly the contributions."""
+    gs, cams = _scene(n=400, seed=19)
+    gs.opacity[:] = np.float32(0.9)
+    b = render.Batch(gs, cams[:1], 16)
+    out = render.render_forward(b)[0]
+    assert np.all(out["n_visited"] >= out["n_contrib"])
+    assert (out["n_visited"] > out["n_contrib"]).any()
+    P = b.leaf_params()
+    m2d, con, op, rgb = (t.detach().numpy() for t in b.project_items(P))
+    cam = cams[0]
+    for v, tx, ty, gt, xs, ys, it in b.tiles():
+        for x, y in list(zip(xs, ys))[::7]:
+            nc, nv = out["n_contrib"][y, x], out["n_visited"][y, x]
+            assert nv <= len(it)
+            for pos in range(nc, nv):
+                i = it[pos]
+                dx, dy = m2d[i, 0] - (x + 0.5), m2d[i, 1] - (y + 0.5)
+                A, B, C = con[i]
+                a = min(0.99, op[i] * math.exp(-0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy))
+                assert a < 1 / 255
