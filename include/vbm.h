@@ -243,7 +243,7 @@ typedef struct {
   int32_t pad;
 } vbm_schedule;
 
-#define VBM_WS_REGIONS 32
+#define VBM_WS_REGIONS 24
 typedef struct {
   int32_t n_views, n_scenes, tile, mode;
   int32_t sort_bits, tile_key_bits, pad0, pad1;
@@ -263,11 +263,11 @@ typedef struct {
 #define VBM_REGION_ITEM_REC 4    /* float32 [n_items][8]: mean2d.xy, conic.abc, opacity, r, g */
 #define VBM_REGION_ITEM_BLUE 5   /* float32 [n_items]: blue */
 #define VBM_REGION_PAIR_TILE 6   /* uint32 [pair_capacity]: sorted global tile of each pair */
-#define VBM_REGION_PAIR_ITEM 7   /* uint32 [pair_capacity]: sorted item of each pair in bits 0..26;
-                                  * with 8x8 and 16x16 tiles bits 27 + k mark lane group k (pixel rows
-                                  * k*64/tile .. of the tile): set by the binning when the footprint's
-                                  * rows reach the group, kept by the compositing forward for a group
-                                  * it evaluated, read by vbm_render_bwd */
+#define VBM_REGION_PAIR_ITEM 7   /* uint32 [pair_capacity]: sorted item of each pair (bits 0..26; the
+                                  * bits above are 0).  With 8x8 and 16x16 tiles vbm_render_fwd keeps
+                                  * a copy elsewhere in ws with bit 27 + k set when it evaluated lane
+                                  * group k (pixel rows k*64/tile .. of the tile) of the pair, which
+                                  * vbm_render_bwd reads */
 #define VBM_REGION_RANGES 8      /* uint32 [n_tiles][2]: [start, end) of each tile's list */
 #define VBM_REGION_GRAD2D 9      /* float32 [n_items][16]: dmean2d.xy, dconic.abc, dopacity, drgb in
                                   * columns 0..8 after vbm_render_bwd (rows of items never binned

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(_PKG, "libvbm.so")
 VBM_TF_MAX_POINTS = 16
 VBM_IMAGE_LOSS_STATIC_SCRATCH_BYTES = 64 << 20
 VBM_BANK_FLOATS = 12
-VBM_WS_REGIONS = 32
+VBM_WS_REGIONS = 24
 MODE_BATCHED, MODE_EXACT = 0, 1
 WAVELETS = {"haar": 0, "bior4.4": 1}
 REGION = dict(counters=0, item_depth=1, item_rect=2, item_ntiles=3, item_rec=4, item_blue=5, pair_tile=6,

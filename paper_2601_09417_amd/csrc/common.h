@@ -65,10 +65,6 @@ struct DevScene {
   int32_t gauss_offset, n_gauss;
 };
 
-// Pair values: the item id below bit kPairMarkShift (items < 2^27), lane-group masks above it
-// (written by the emission, narrowed by the compositing forward, read by the backward).
-constexpr int kPairMarkShift = 27;
-
 // ------------------------------------------------------------------ wave helpers
 __device__ __forceinline__ uint32_t lane_id() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));

@@ -22,40 +22,6 @@ struct ProjResult {
   bool visible;
 };
 
-// Rows of pixel centres that the footprint {q <= tau} can reach: the ellipse spans
-// |dy| <= sqrt(tau Sigma2_yy) with Sigma2_yy = A / (A C - B^2) from the compositing conic (in float64,
-// so that thin ellipses lose nothing to cancellation), widened by 1e-4 relative and 1/64 pixel.
-// Returns the first row | last row << 16 (clamped to 0..65535; 65535 | 0 << 16 when none).  The
-// compositing forward skips a lane group whose pixel rows lie outside this span: it has
-// alpha < 1/255 there.
-__device__ __forceinline__ uint32_t footprint_rows(float py, float A, float B, float C, float tau) {
-  const double a = A, b = B, c = C;
-  const double syy = a / (a * c - b * b);
-  const double ry = sqrt(fmax(static_cast<double>(tau), 0.0) * syy) * (1.0 + 1e-4) + 1.0 / 64.0;
-  // pixel row r has its centre at r + 0.5
-  const double lo = ceil(static_cast<double>(py) - ry - 0.5);
-  const double hi = floor(static_cast<double>(py) + ry - 0.5);
-  if (hi < lo || hi < 0.0) return 0xFFFFu;   // first row 65535, last row 0: no row
-  const uint32_t r0 = static_cast<uint32_t>(fmin(fmax(lo, 0.0), 65535.0));
-  const uint32_t r1 = static_cast<uint32_t>(fmin(hi, 65535.0));
-  return r0 | (r1 << 16);
-}
-
-// Lane groups of the compositing kernels that the footprint's rows reach in tile row ty: with
-// 16x16 tiles group k is pixel rows 4k..4k+3 of the tile; 8x8 tiles have one group; with 32x32
-// tiles every group is taken (that kernel does not read the mask).
-__device__ __forceinline__ uint32_t group_mask(uint32_t rows, uint32_t ty, int tile) {
-  if (tile != 16) return tile == 8 ? 1u : 0xFu;
-  const uint32_t r0 = rows & 0xFFFFu, r1 = rows >> 16;
-  uint32_t m = 0;
-#pragma unroll
-  for (uint32_t k = 0; k < 4; ++k) {
-    const uint32_t g0 = 16u * ty + 4u * k;
-    m |= (g0 <= r1 && g0 + 3u >= r0) ? (1u << k) : 0u;
-  }
-  return m;
-}
-
 __device__ __forceinline__ void rot_from_quat(float qw, float qx, float qy, float qz, float Rq[3][3], float qn[4]) {
   const float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
   const float nq = sqrt_rn_f32(n2);
@@ -235,8 +201,7 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
                                                  uint32_t* __restrict__ ntiles, float4* __restrict__ rec,
                                                  float4* __restrict__ coef, float* __restrict__ blue,
                                                  uint32_t* __restrict__ vis_flag, uint4* __restrict__ bin,
-                                                 uint32_t* __restrict__ rows, int64_t n_items,
-                                                 unsigned long long* __restrict__ word_count,
+                                                 int64_t n_items, unsigned long long* __restrict__ word_count,
                                                  unsigned long long* __restrict__ words, uint32_t word_cap) {
   __shared__ float s_par[8][256];      // per thread: mean2d.xy, conic A B C, tau, nBA, nBC
   __shared__ uint32_t s_org[256];      // rectangle origin x0 | y0 << 16
@@ -269,9 +234,8 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
                                      g.scales[S + gi], g.scales[2 * S + gi], g.quats[gi], g.quats[S + gi],
                                      g.quats[2 * S + gi], g.quats[3 * S + gi], op);
     if (p.visible) {
-      const float tau = footprint_tau(op);
-      const float par[8] = {p.px, p.py, p.ca, p.cb, p.cc, tau, -__fdiv_rn(p.cb, p.ca), -__fdiv_rn(p.cb, p.cc)};
-      rows[item] = footprint_rows(p.py, p.ca, p.cb, p.cc, tau);
+      const float par[8] = {p.px, p.py, p.ca, p.cb, p.cc, footprint_tau(op), -__fdiv_rn(p.cb, p.ca),
+                            -__fdiv_rn(p.cb, p.cc)};
 #pragma unroll
       for (int k = 0; k < 8; ++k) s_par[k][threadIdx.x] = par[k];
       s_org[threadIdx.x] = p.x0 | (p.y0 << 16);
@@ -397,17 +361,13 @@ __device__ __forceinline__ int view_of_item(const DevView* __restrict__ views, i
 // gathered once into sorted order for the emission, and their tile counts for the pair offsets.
 __global__ __launch_bounds__(256) void k_gather_bins(const uint32_t* __restrict__ vals,
                                                      const uint4* __restrict__ bin,
-                                                     const uint32_t* __restrict__ rows,
                                                      const uint32_t* __restrict__ counters, int64_t n_max,
-                                                     uint32_t* __restrict__ out, uint4* __restrict__ sorted_bin,
-                                                     uint32_t* __restrict__ sorted_rows) {
+                                                     uint32_t* __restrict__ out, uint4* __restrict__ sorted_bin) {
   const int64_t n = min(static_cast<int64_t>(counters[0]), n_max);
   for (int64_t p = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; p < n;
        p += static_cast<int64_t>(gridDim.x) * 256) {
-    const uint32_t it = vals[p];
-    const uint4 b = bin[it];
+    const uint4 b = bin[vals[p]];
     sorted_bin[p] = b;
-    sorted_rows[p] = rows[it];
     out[p] = b.w;
   }
 }
@@ -418,8 +378,7 @@ __global__ __launch_bounds__(256) void k_gather_bins(const uint32_t* __restrict_
 // positions from the ballot of reached tiles).
 __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views, int n_views,
                                               const uint32_t* __restrict__ vals, const uint32_t* __restrict__ offs,
-                                              const uint4* __restrict__ sorted_bin,
-                                              const uint32_t* __restrict__ sorted_rows, const float4* __restrict__ rec,
+                                              const uint4* __restrict__ sorted_bin, const float4* __restrict__ rec,
                                               const unsigned long long* __restrict__ words,
                                               int tile, uint32_t* __restrict__ counters, int64_t n_max,
                                               int64_t capacity, uint32_t* __restrict__ pair_tile,
@@ -444,15 +403,13 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
         int64_t o = offs[p];
         bool over = false;
         uint32_t m = b.z;
-        const uint32_t rows = sorted_rows[p];
         const uint32_t row_mask = w >= 32 ? 0xFFFFFFFFu : (1u << w) - 1u;
         uint32_t t_row = static_cast<uint32_t>(v.tile_offset) + y0 * static_cast<uint32_t>(v.tiles_x) + x0;
-        for (uint32_t ty = y0; m; m >>= w, t_row += static_cast<uint32_t>(v.tiles_x), ++ty) {
-          const uint32_t pv = item | (group_mask(rows, ty, tile) << kPairMarkShift);
+        for (; m; m >>= w, t_row += static_cast<uint32_t>(v.tiles_x)) {
           for (uint32_t r = m & row_mask; r; r &= r - 1) {
             if (o < capacity) {
               pair_tile[o] = t_row + static_cast<uint32_t>(__builtin_ctz(r));
-              pair_item[o] = pv;
+              pair_item[o] = item;
             } else {
               over = true;
             }
@@ -475,7 +432,6 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
       const uint32_t x0 = b.x & 0xFFFFu, x1 = b.x >> 16, y0 = b.y & 0xFFFFu, y1 = b.y >> 16;
       const uint32_t w = x1 - x0, area = w * (y1 - y0);
       const float inv_w = 1.0f / static_cast<float>(w);
-      const uint32_t rows = sorted_rows[q];
       int64_t o = offs[q];
       bool over = false;
       if (b.z != kNoWords) {
@@ -491,7 +447,7 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
             if (oo < capacity) {
               pair_tile[oo] = static_cast<uint32_t>(v.tile_offset) + (y0 + ty) * static_cast<uint32_t>(v.tiles_x) +
                               x0 + tx;
-              pair_item[oo] = item | (group_mask(rows, y0 + ty, tile) << kPairMarkShift);
+              pair_item[oo] = item;
             } else {
               over = true;
             }
@@ -518,7 +474,7 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
           const int64_t oo = o + lanes_below(m);
           if (oo < capacity) {
             pair_tile[oo] = static_cast<uint32_t>(v.tile_offset) + ty * static_cast<uint32_t>(v.tiles_x) + tx;
-            pair_item[oo] = item | (group_mask(rows, ty, tile) << kPairMarkShift);
+            pair_item[oo] = item;
           } else {
             over = true;
           }

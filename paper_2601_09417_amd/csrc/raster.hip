@@ -38,7 +38,7 @@ constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 // Item ids stay below 2^27 (the plan enforces it); the forward keeps per-pair lane-group marks in
 // the bits above.
-constexpr int kItemBits = kPairMarkShift;
+constexpr int kItemBits = 27;
 constexpr uint32_t kItemMask = (1u << kItemBits) - 1u;
 
 template <int TILE>
@@ -250,12 +250,10 @@ __device__ __forceinline__ bool any_live(const float (&fy)[PPL]) {
 // One list step (0-based list position pos) of the forward for the lane's pixels:
 // alpha = min(0.99, 2^e2); a pixel takes the Gaussian when alpha >= 1/255, unless the new
 // transmittance would fall below 1e-4, in which case the pixel stops without it and records pos as
-// the number of list entries its compositing took into account.  `reach` holds the lane groups
-// that the binning found the Gaussian's footprint to reach (the others have alpha < 1/255 at every
-// pixel and are skipped without evaluating anything).  Returns the mask of lane groups k that were
-// evaluated: every group with a pixel that took the Gaussian is among them.
+// the number of list entries its compositing took into account.  Returns the mask of lane groups k
+// that were evaluated: every group with a pixel that took the Gaussian is among them.
 template <int PPL, bool STATS>
-__device__ __forceinline__ uint32_t fwd_step(const Rec& r, uint32_t reach, int pos, float fx, float (&fy)[PPL],
+__device__ __forceinline__ uint32_t fwd_step(const Rec& r, int pos, float fx, float (&fy)[PPL],
                                              float (&T)[PPL], float (&cr)[PPL], float (&cg)[PPL], float (&cb)[PPL],
                                              int (&nvis)[PPL], uint32_t& n_eval, uint32_t& n_used) {
   uint32_t groups = 0;
@@ -264,10 +262,6 @@ __device__ __forceinline__ uint32_t fwd_step(const Rec& r, uint32_t reach, int p
   const float vb = r.hB * dx;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
-    if (!((reach >> k) & 1u)) {
-      if (STATS) n_eval += fy[k] < kLiveBound ? 1u : 0u;
-      continue;
-    }
     const float dy = r.my - fy[k];
     const float e2 = exponent2(r, u, vb, dy);
     // A lane group where every pixel has 2^e2 clearly below 1/255 (or is terminated, e2 = -inf)
@@ -346,12 +340,10 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
   // them would let the compiler sink the prefetch below it); past the end of the list a record is
   // a clamped duplicate whose log-opacity is set to -inf, so alpha = 0 and it changes nothing.
   const int lastj = end > start ? end - 1 : start;
-  // With one wave per tile, a pair value carries in bits kItemBits.. the lane groups that the
-  // binning found the footprint to reach, and each processed pair value is copied to pair_marked
-  // with the mask of the groups that the step evaluated (see fwd_step): the backward visits only
-  // those, reading the copy through the scalar cache.
+  // With one wave per tile, each processed pair value is copied to pair_marked with the mask of the
+  // lane groups that the step evaluated in bits kItemBits.. (see fwd_step): the backward visits
+  // only those, reading the copy through the scalar cache.
   constexpr bool kMark = C::kWaves == 1;
-  constexpr uint32_t kAll = (1u << PPL) - 1u;
   // Records through the scalar cache one list step ahead of their use, pair values by vector loads
   // three steps ahead (measured faster here than scalar pair-value loads, which put a second
   // scalar round trip in front of every record), unrolled by three so that the item slots rotate
@@ -369,22 +361,22 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
     u1 = uniform(L1);
     R1 = load_rec_s(crec, blue, u1, imax);
     L1 = load_item(irs, min(j + 4, lastj));
-    const uint32_t m0 = (u0 & kItemMask) | (fwd_step<PPL, STATS>(R0, kMark ? u0 >> kItemBits : kAll, j - start, fx, fy,
-                                                                  T, cr, cg, cb, nvis, n_eval, n_used) << kItemBits);
+    const uint32_t m0 = (u0 & kItemMask) | (fwd_step<PPL, STATS>(R0, j - start, fx, fy, T, cr, cg, cb, nvis,
+                                                                  n_eval, n_used) << kItemBits);
     wait_scalar_loads();
     R1.lo = j + 1 < end ? R1.lo : -__builtin_inff();
     u2 = uniform(L2);
     R2 = load_rec_s(crec, blue, u2, imax);
     L2 = load_item(irs, min(j + 5, lastj));
     const uint32_t un = uniform(L0);
-    const uint32_t m1 = (u1 & kItemMask) | (fwd_step<PPL, STATS>(R1, kMark ? u1 >> kItemBits : kAll, j - start + 1, fx,
-                                                                  fy, T, cr, cg, cb, nvis, n_eval, n_used) << kItemBits);
+    const uint32_t m1 = (u1 & kItemMask) | (fwd_step<PPL, STATS>(R1, j - start + 1, fx, fy, T, cr, cg, cb, nvis,
+                                                                  n_eval, n_used) << kItemBits);
     wait_scalar_loads();
     R2.lo = j + 2 < end ? R2.lo : -__builtin_inff();
     R0 = load_rec_s(crec, blue, un, imax);
     L0 = load_item(irs, min(j + 6, lastj));
-    const uint32_t m2 = (u2 & kItemMask) | (fwd_step<PPL, STATS>(R2, kMark ? u2 >> kItemBits : kAll, j - start + 2, fx,
-                                                                  fy, T, cr, cg, cb, nvis, n_eval, n_used) << kItemBits);
+    const uint32_t m2 = (u2 & kItemMask) | (fwd_step<PPL, STATS>(R2, j - start + 2, fx, fy, T, cr, cg, cb, nvis,
+                                                                  n_eval, n_used) << kItemBits);
     if (kMark) store_pair_values(pair_marked, lane, j, min(end - j, 3), m0, m1, m2);
     u0 = un;
   }

@@ -20,13 +20,11 @@
 namespace vbm {
 
 __global__ void k_project(const DevView*, int, vbm_gaussians_c, float*, uint32_t*, uint32_t*, float4*, float4*,
-                          float*, uint32_t*, uint4*, uint32_t*, int64_t, unsigned long long*, unsigned long long*,
-                          uint32_t);
+                          float*, uint32_t*, uint4*, int64_t, unsigned long long*, unsigned long long*, uint32_t);
 __global__ void k_compact_visible(const DevView*, const uint32_t*, const float*, const uint32_t*, uint32_t*,
                                   uint32_t*);
-__global__ void k_gather_bins(const uint32_t*, const uint4*, const uint32_t*, const uint32_t*, int64_t, uint32_t*,
-                              uint4*, uint32_t*);
-__global__ void k_emit(const DevView*, int, const uint32_t*, const uint32_t*, const uint4*, const uint32_t*,
+__global__ void k_gather_bins(const uint32_t*, const uint4*, const uint32_t*, int64_t, uint32_t*, uint4*);
+__global__ void k_emit(const DevView*, int, const uint32_t*, const uint32_t*, const uint4*,
                        const float4*, const unsigned long long*, int, uint32_t*, int64_t, int64_t, uint32_t*,
                        uint32_t*);
 __global__ void k_ranges(const uint32_t*, const uint32_t*, int64_t, uint2*);
@@ -73,9 +71,7 @@ enum Region {
   R_TORDER = 21,   // uint32 [4][n_tiles]: sort keys, tiles, and the sorted keys and tiles (the launch order)
   R_WORDS = 22,    // uint64 [ballot_words(n_items)]: large rectangles' reached-tile ballots
   R_SBIN = 23,     // uint4 [n_items]: the visible items' bin entries in depth order
-  R_ROWS = 24,     // uint32 [n_items]: first | last pixel row the footprint reaches << 16
-  R_SROWS = 25,    // uint32 [n_items]: the visible items' rows in depth order
-  R_COUNT = 26
+  R_COUNT = 24
 };
 static_assert(R_COUNT <= VBM_WS_REGIONS, "plan has room for every region");
 
@@ -126,8 +122,6 @@ void layout(vbm_plan* p) {
   sz[R_TORDER] = 4 * NT * 4;
   sz[R_WORDS] = 8 * ballot_words(I);
   sz[R_SBIN] = I * 16;
-  sz[R_ROWS] = I * 4;
-  sz[R_SROWS] = I * 4;
   size_t off = 0;
   for (int r = 0; r < VBM_WS_REGIONS; ++r) {
     p->region_offset[r] = 0;
@@ -346,7 +340,7 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
   const int gx = static_cast<int>(ceil_div(p->n_gaussians > 0 ? p->n_gaussians : 1, 256));
   if (I > 0) {
     hipLaunchKernelGGL(k_project, dim3(gx, p->n_views), dim3(256), 0, s, views, p->tile, g, depth, rect, ntiles, rec,
-                       coef, blue, visflag, region<uint4>(p, ws, R_BIN), region<uint32_t>(p, ws, R_ROWS), I,
+                       coef, blue, visflag, region<uint4>(p, ws, R_BIN), I,
                        reinterpret_cast<unsigned long long*>(counters + 4), region<unsigned long long>(p, ws, R_WORDS),
                        static_cast<uint32_t>(ballot_words(I)));
     VBM_LAUNCH_CHECK("project");
@@ -365,8 +359,7 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
     VBM_TRY(radix_sort_pairs<uint32_t>(vk[first], vv[first], vk[1 - first], vv[1 - first], I, &counters[0],
                                        kDepthKeyBits, 8, scratch, s, &in_alt));
     hipLaunchKernelGGL(k_gather_bins, dim3(grid_cap(I, 8192)), dim3(256), 0, s, vv[0], region<uint4>(p, ws, R_BIN),
-                       region<uint32_t>(p, ws, R_ROWS), counters, I, poffs, region<uint4>(p, ws, R_SBIN),
-                       region<uint32_t>(p, ws, R_SROWS));
+                       counters, I, poffs, region<uint4>(p, ws, R_SBIN));
     VBM_LAUNCH_CHECK("gather_bins");
     VBM_TRY(scan_exclusive_u32(poffs, poffs, I, &counters[0], &counters[1], scratch, s));
   }
@@ -387,8 +380,7 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
   const int pfirst = tile_passes % 2;
   if (I > 0 && emit_grid_n > 0) {
     hipLaunchKernelGGL(k_emit, dim3(grid_cap(emit_grid_n, 16384)), dim3(256), 0, s, views, p->n_views, vv[0], poffs,
-                       region<uint4>(p, ws, R_SBIN), region<uint32_t>(p, ws, R_SROWS), rec,
-                       region<unsigned long long>(p, ws, R_WORDS), p->tile,
+                       region<uint4>(p, ws, R_SBIN), rec, region<unsigned long long>(p, ws, R_WORDS), p->tile,
                        counters, I, cap, pt[pfirst], pi[pfirst]);
     VBM_LAUNCH_CHECK("emit");
   }
