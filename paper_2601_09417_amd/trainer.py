@@ -5,13 +5,20 @@
 * ``FineTuner``  -- one fine-tuning iteration in three schedules:
     plain    one view per launch: per view a forward (which synchronises once to size the sort
              exactly), one loss over all views, per view a backward; then Adam
-    batched  every view (and scene) in one launch per phase, counts kept on the device
+    batched  every view (and scene) in one launch per phase, counts kept on the device; or, with
+             size classes, one launch per phase for each class of views (consecutive views of one
+             size), each with its own tile edge and radix digit width
     graph    the batched step captured once in a HIP graph and replayed
   All three produce identical pair lists and images; gradients agree up to float atomics order.
+  Images do not depend on the tile edge either: a tile's list differs from another tiling's only
+  in Gaussians that reach none of its pixels, which every pixel skips.
 * ``render_images`` -- a forward-only batch render with exactly counted pair lists (used to render
   the visual-mode sets concatenated or separately after fine-tuning).
 * ``autotune``   -- times the batched step for each (tile, radix digit) candidate and picks the
-  fastest; run before capture, on a copy of the parameters.
+  fastest; run before capture, on a copy of the parameters.  ``autotune_classes`` does so for
+  each size class of a batch on its own; ``autotune_schedule`` keeps one schedule for the batch
+  or one per size class, whichever step is faster.
+* ``size_classes`` -- the runs of consecutive views of equal size.
 """
 from __future__ import annotations
 
@@ -58,10 +65,24 @@ class VBMRender(torch.autograd.Function):
         return g, None
 
 
+def size_classes(cams) -> list:
+    """Runs of consecutive views with the same (width, height), as [(v0, v1), ...]."""
+    out, v0 = [], 0
+    for v in range(1, len(cams) + 1):
+        if v == len(cams) or (cams[v].width, cams[v].height) != (cams[v0].width, cams[v0].height):
+            out.append((v0, v))
+            v0 = v
+    return out
+
+
 class FineTuner:
     def __init__(self, P: torch.Tensor, cams, targets: torch.Tensor, scene_offsets=None, view_scene=None,
                  tile: int = 16, sort_bits: int = 8, loss: str = "l1", lam: float = 0.2, lr=api.LR_DEFAULT,
-                 schedule: str = "batched", pair_capacity: int | None = None, capacity_margin: float = 1.25):
+                 schedule: str = "batched", pair_capacity: int | None = None, capacity_margin: float = 1.25,
+                 classes=None, class_schedules=None):
+        """``classes``: consecutive view ranges [(v0, v1), ...] covering every view, each rendered by
+        its own launches with (tile, sort_bits) from ``class_schedules`` (default: one class, the
+        whole batch, with ``tile`` and ``sort_bits``)."""
         assert schedule in ("plain", "batched", "graph")
         self.dev = P.device
         self.cams = list(cams)
@@ -69,6 +90,14 @@ class FineTuner:
         self.scene_offsets = np.asarray(scene_offsets if scene_offsets is not None else [0, self.N], np.int64)
         self.view_scene = list(view_scene) if view_scene is not None else [0] * len(self.cams)
         self.tile, self.sort_bits = tile, sort_bits
+        self.classes = [tuple(c) for c in classes] if classes is not None else [(0, len(self.cams))]
+        if [v for c in self.classes for v in range(c[0], c[1])] != list(range(len(self.cams))):
+            raise ValueError("classes must be consecutive view ranges covering every view once, in order")
+        self.class_schedules = ([tuple(x) for x in class_schedules] if class_schedules is not None
+                                else [(tile, sort_bits)] * len(self.classes))
+        if len(self.class_schedules) != len(self.classes):
+            raise ValueError("one (tile, sort_bits) per class")
+        self.view_schedule = [self.class_schedules[c] for c, (a, b) in enumerate(self.classes) for _ in range(a, b)]
         self.schedule = schedule
         self.lr = lr
         self.margin = capacity_margin
@@ -93,8 +122,8 @@ class FineTuner:
         """Exact pair count per view from one exact-mode forward (planning only)."""
         counts = []
         for v, cam in enumerate(self.cams):
-            rp = api.plan_batch([cam], self.scene_offsets, [self.view_scene[v]], self.tile, self.sort_bits, 1, "exact",
-                                self.dev)
+            tile, bits = self.view_schedule[v]
+            rp = api.plan_batch([cam], self.scene_offsets, [self.view_scene[v]], tile, bits, 1, "exact", self.dev)
             out = api.render_fwd(rp, self.act)
             torch.cuda.synchronize(self.dev)
             counts.append(int(out.status[1].item()))
@@ -107,35 +136,30 @@ class FineTuner:
             counts = [capacity] * len(self.cams)
         self.view_caps = [max(1, int(c * self.margin) + 1024) for c in counts]
         if self.schedule == "plain":
-            self.plans = [api.plan_batch([cam], self.scene_offsets, [self.view_scene[v]], self.tile, self.sort_bits,
-                                         self.view_caps[v], "exact", self.dev) for v, cam in enumerate(self.cams)]
-            self.outs = []
-            for v in range(len(self.cams)):
-                a, b = int(self.pix_off[v]), int(self.pix_off[v + 1])
-                self.outs.append(api.FwdOut(self.image[3 * a:3 * b], self.final_T[a:b], self.n_contrib[a:b],
-                                            torch.zeros(4, dtype=torch.int32, device=self.dev)))
+            groups = [(v, v + 1, *self.view_schedule[v], self.view_caps[v], "exact") for v in range(len(self.cams))]
         else:
-            total = sum(self.view_caps) if capacity is None else capacity
-            self.plans = [api.plan_batch(self.cams, self.scene_offsets, self.view_scene, self.tile, self.sort_bits,
-                                         total, "batched", self.dev)]
-            self.outs = [api.FwdOut(self.image, self.final_T, self.n_contrib,
-                                    torch.zeros(4, dtype=torch.int32, device=self.dev))]
+            groups = [(a, b, *self.class_schedules[c], sum(self.view_caps[a:b]) if capacity is None else capacity,
+                       "batched") for c, (a, b) in enumerate(self.classes)]
+        self.plans, self.outs = [], []
+        for a, b, tile, bits, cap, mode in groups:
+            self.plans.append(api.plan_batch(self.cams[a:b], self.scene_offsets, self.view_scene[a:b], tile, bits, cap,
+                                             mode, self.dev))
+            pa, pb = int(self.pix_off[a]), int(self.pix_off[b])
+            self.outs.append(api.FwdOut(self.image[3 * pa:3 * pb], self.final_T[pa:pb], self.n_contrib[pa:pb],
+                                        torch.zeros(4, dtype=torch.int32, device=self.dev)))
         self.graph = None
 
     # -- one iteration ---------------------------------------------------------------------------
     def _step_body(self):
-        if self.schedule == "plain":
-            for rp, out in zip(self.plans, self.outs):
-                api.render_fwd(rp, self.act, out)
-            self.loss_fn(self.image, self.targets, self.dL)
-            for v, (rp, out) in enumerate(zip(self.plans, self.outs)):
-                a, b = int(self.pix_off[v]), int(self.pix_off[v + 1])
-                api.render_bwd(rp, self.act, self.dL[3 * a:3 * b], out, self.grads, accumulate=v > 0)
-        else:
-            rp, out = self.plans[0], self.outs[0]
+        # plain: one plan per view (exact mode); batched / graph: one plan per class of views
+        for rp, out in zip(self.plans, self.outs):
             api.render_fwd(rp, self.act, out)
-            self.loss_fn(self.image, self.targets, self.dL)
-            api.render_bwd(rp, self.act, self.dL, out, self.grads, accumulate=False)
+        self.loss_fn(self.image, self.targets, self.dL)
+        pix = 0
+        for k, (rp, out) in enumerate(zip(self.plans, self.outs)):
+            n = rp.n_pixels
+            api.render_bwd(rp, self.act, self.dL[3 * pix:3 * (pix + n)], out, self.grads, accumulate=k > 0)
+            pix += n
         api.adam_step(self.raw, self.m, self.v, self.grads, self.act, self.lr, step_dev=self.step_dev)
 
     def step(self):
@@ -204,6 +228,30 @@ def render_images(P: torch.Tensor, cams, scene_offsets=None, view_scene=None, ti
 TUNE_CANDIDATES = ((16, 8), (8, 8), (32, 8), (16, 4))
 
 
+def _pixel_range(cams, a, b):
+    off = np.concatenate([[0], np.cumsum([c.width * c.height for c in cams])]).astype(np.int64)
+    return int(off[a]), int(off[b])
+
+
+def autotune_classes(P: torch.Tensor, cams, targets: torch.Tensor, scene_offsets=None, view_scene=None,
+                     classes=None, loss: str = "l1", lam: float = 0.2, candidates=TUNE_CANDIDATES, steps: int = 3,
+                     warmup: int = 1) -> dict:
+    """Picks (tile, sort_bits) for each size class of a batch on its own (default classes: the runs
+    of equal-size views): every candidate runs the batched step of that class's views alone (their
+    targets, all Gaussians, Adam included) and the fastest is kept.  Returns dict(classes,
+    schedules [(tile, sort_bits)] per class, tables [per-class candidate tables])."""
+    classes = size_classes(cams) if classes is None else [tuple(c) for c in classes]
+    vs = list(view_scene) if view_scene is not None else [0] * len(cams)
+    schedules, tables = [], []
+    for a, b in classes:
+        pa, pb = _pixel_range(cams, a, b)
+        r = autotune(P, cams[a:b], targets[3 * pa:3 * pb], scene_offsets, vs[a:b], loss=loss, lam=lam,
+                     candidates=candidates, steps=steps, warmup=warmup)
+        schedules.append((r["tile"], r["sort_bits"]))
+        tables.append(r["table"])
+    return dict(classes=classes, schedules=schedules, tables=tables)
+
+
 def autotune(P: torch.Tensor, cams, targets: torch.Tensor, scene_offsets=None, view_scene=None, loss: str = "l1",
              lam: float = 0.2, candidates=TUNE_CANDIDATES, steps: int = 3, warmup: int = 1) -> dict:
     """Chooses the tile edge and the radix digit width of the tile sort for a batch.
@@ -217,17 +265,46 @@ def autotune(P: torch.Tensor, cams, targets: torch.Tensor, scene_offsets=None, v
     for tile, bits in candidates:
         ft = FineTuner(P, cams, targets, scene_offsets, view_scene, tile=tile, sort_bits=bits, loss=loss, lam=lam,
                        schedule="batched")
-        for _ in range(warmup):
-            ft.step()
-        torch.cuda.synchronize(P.device)
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            ft.step()
-        torch.cuda.synchronize(P.device)
-        ms = (time.perf_counter() - t0) * 1e3 / steps
-        if ft.overflowed():
-            ms = float("inf")
-        table.append(dict(tile=tile, sort_bits=bits, ms=ms))
+        table.append(dict(tile=tile, sort_bits=bits, ms=_time_steps(ft, steps, warmup)))
         del ft
     best = min(table, key=lambda d: d["ms"])
     return dict(tile=best["tile"], sort_bits=best["sort_bits"], ms=best["ms"], table=table)
+
+
+def _time_steps(ft: "FineTuner", steps: int, warmup: int) -> float:
+    """ms per eager step after ``warmup`` steps (device-synchronised on both sides); inf when a
+    step overflowed its pair capacity."""
+    for _ in range(warmup):
+        ft.step()
+    torch.cuda.synchronize(ft.dev)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ft.step()
+    torch.cuda.synchronize(ft.dev)
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return float("inf") if ft.overflowed() else ms
+
+
+def autotune_schedule(P: torch.Tensor, cams, targets: torch.Tensor, scene_offsets=None, view_scene=None,
+                      loss: str = "l1", lam: float = 0.2, candidates=TUNE_CANDIDATES, steps: int = 3,
+                      warmup: int = 1) -> dict:
+    """The step schedule of a batch: the best single (tile, sort_bits) for the whole batch and, when
+    the batch holds views of several sizes, the best per size class (autotune_classes); the per-class
+    schedule (one launch per class and phase) is taken when its whole step is faster.  Returns the
+    FineTuner keywords (tile, sort_bits, classes, class_schedules) plus the measurements."""
+    whole = autotune(P, cams, targets, scene_offsets, view_scene, loss=loss, lam=lam, candidates=candidates,
+                     steps=steps, warmup=warmup)
+    out = dict(tile=whole["tile"], sort_bits=whole["sort_bits"], classes=None, class_schedules=None,
+               ms=whole["ms"], table=whole["table"])
+    classes = size_classes(cams)
+    if len(classes) > 1:
+        ct = autotune_classes(P, cams, targets, scene_offsets, view_scene, classes, loss=loss, lam=lam,
+                              candidates=candidates, steps=steps, warmup=warmup)
+        ft = FineTuner(P, cams, targets, scene_offsets, view_scene, loss=loss, lam=lam, schedule="batched",
+                       classes=classes, class_schedules=ct["schedules"])
+        ms = _time_steps(ft, steps, warmup)
+        del ft
+        out.update(class_tables=ct["tables"], per_class=dict(classes=classes, schedules=ct["schedules"], ms=ms))
+        if ms < whole["ms"]:
+            out.update(classes=classes, class_schedules=ct["schedules"], ms=ms)
+    return out

@@ -330,3 +330,41 @@ def test_trainer_replans_after_overflow():
     ref.step()
     torch.cuda.synchronize()
     assert torch.equal(ft.image, ref.image)
+
+
+def test_size_class_schedules_match_the_single_schedule():
+    """A batch of two scenes seen at two resolutions, rendered with one plan per size class and a
+    different (tile, digit width) in each, gives the first forward of one plan over the whole batch
+    bit for bit (a tiling changes a tile's list only by Gaussians that no pixel of it takes) and the
+    same step up to float atomics order; the per-class autotuner returns a candidate per class."""
+    from oracle import render
+    from paper_2601_09417_amd import trainer
+    from tests.gpu_common import IMG_TOL, image_error
+    api = _api()
+    s1 = vi.random_gaussians(900, 31, log_scale_mean=-3.2)
+    s2 = vi.random_gaussians(1400, 32, log_scale_mean=-3.4)
+    gs = vi.GaussianSet.concat([s1, s2])
+    so = [0, s1.n, s1.n + s2.n]
+    cams = vi.orbit_cameras(2, 96, 72) + vi.orbit_cameras(3, 61, 45, azimuth0=0.7)
+    vs = [0, 1, 1, 0, 1]
+    classes = trainer.size_classes(cams)
+    assert classes == [(0, 2), (2, 5)]
+    tgt = torch.rand(sum(3 * c.width * c.height for c in cams), device=dev())
+    P = api.pack_params(gs.means, gs.scales, gs.quats, gs.opacity, gs.rgb, dev())
+    say("size classes: 2 x 96x72 (tile 8, 8-bit) and 3 x 61x45 (tile 32, 4-bit) against one 16x16 plan")
+    a = trainer.FineTuner(P, cams, tgt, so, vs, tile=16, sort_bits=8, schedule="batched")
+    b = trainer.FineTuner(P, cams, tgt, so, vs, schedule="graph", classes=classes, class_schedules=[(8, 8), (32, 4)])
+    a.step()
+    b.step()
+    torch.cuda.synchronize()
+    assert not a.overflowed() and not b.overflowed()
+    assert torch.equal(a.image, b.image)
+    assert (a.act - b.act).abs().max().item() <= 1e-4
+    ref = render.render_forward(render.Batch(gs, cams, 16, vs, so))
+    for v, got in enumerate(api.split_views(b.image, cams)):
+        assert image_error(got.cpu().numpy(), ref[v]["image"], ref[v]["flagged"]) <= IMG_TOL, v
+    res = trainer.autotune_classes(P, cams, tgt, so, vs, steps=1, warmup=1)
+    assert res["classes"] == classes and len(res["schedules"]) == 2
+    assert all(tuple(s) in trainer.TUNE_CANDIDATES for s in res["schedules"])
+    full = trainer.autotune_schedule(P, cams, tgt, so, vs, steps=1, warmup=1)
+    assert full["per_class"]["schedules"] and np.isfinite(full["ms"])
