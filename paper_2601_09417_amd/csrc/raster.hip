@@ -299,7 +299,56 @@ __device__ __forceinline__ uint32_t fwd_step(const Rec& r, int pos, float fx, fl
   return groups;
 }
 
-template <int TILE, bool STATS>
+// Records of an LDS batch (the optional staged list walk): B consecutive list entries, one per
+// lane, loaded with per-lane vector loads and written to LDS, then read back at a uniform address
+// by every list step of the batch.
+template <int B>
+struct LdsBatch {
+  float4 a[2][B], b[2][B];
+  float blue[2][B];
+};
+
+template <int B>
+__device__ __forceinline__ void lds_put(LdsBatch<B>& L, int buf, int lane, const float4& ra, const float4& rb,
+                                        float bl) {
+  if (lane < B) {
+    L.a[buf][lane] = ra;
+    L.b[buf][lane] = rb;
+    L.blue[buf][lane] = bl;
+  }
+}
+
+template <int B>
+__device__ __forceinline__ Rec lds_get(const LdsBatch<B>& L, int buf, int b) {
+  const float4 a = L.a[buf][b], c = L.b[buf][b];
+  Rec r;
+  r.mx = a.x;
+  r.my = a.y;
+  r.hA = a.z;
+  r.hB = a.w;
+  r.hC = c.x;
+  r.lo = c.y;
+  r.r = c.z;
+  r.g = c.w;
+  r.b = L.blue[buf][b];
+  return r;
+}
+
+// Lane t's entry of the batch at list positions pos(t) (per-lane vector loads): its pair value and
+// record (the record of a clamped item when the position lies outside [lo, hi], never read).
+__device__ __forceinline__ void lds_fetch(const uint32_t* __restrict__ values, const float4* __restrict__ crec,
+                                          const float* __restrict__ cblue, uint32_t imax, int pos, bool ok,
+                                          uint32_t& pv, float4& ra, float4& rb, float& bl) {
+  pv = ok ? values[pos] : 0u;
+  const uint32_t it = min(pv & kItemMask, imax);
+  ra = crec[2 * it];
+  rb = crec[2 * it + 1];
+  bl = cblue[it];
+}
+
+// LDSB = 0: records through the scalar cache (the default); LDSB = 32 or 64: the list is staged in
+// LDS batches of that many entries (one wave per tile only), a tuning candidate.
+template <int TILE, bool STATS, int LDSB>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
     const DevView* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ tile_order,
@@ -334,23 +383,50 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
 #pragma unroll
   for (int k = 0; k < PPL; ++k) nvis[k] = end - start;
   uint32_t n_eval = 0, n_used = 0;
-  // Load pipeline, unrolled by three so that buffers rotate without copies: the record of list
-  // step s is requested at step s - 2 and the item id that addresses it at step s - 4 (three
-  // record buffers R, three item slots L).  All three steps of an iteration run (a branch between
-  // them would let the compiler sink the prefetch below it); past the end of the list a record is
-  // a clamped duplicate whose log-opacity is set to -inf, so alpha = 0 and it changes nothing.
   const int lastj = end > start ? end - 1 : start;
   // With one wave per tile, each processed pair value is copied to pair_marked with the mask of the
   // lane groups that the step evaluated in bits kItemBits.. (see fwd_step): the backward visits
   // only those, reading the copy through the scalar cache.
   constexpr bool kMark = C::kWaves == 1;
+  const float4* __restrict__ crec = reinterpret_cast<const float4*>(coef);
+  const uint32_t imax = n_items > 0 ? static_cast<uint32_t>(n_items - 1) : 0u;
+  if constexpr (LDSB > 0) {
+    static_assert(C::kWaves == 1, "LDS batches are wave-private");
+    // Double-buffered batches: the next batch's entries are loaded into registers (one per lane)
+    // while the current one is walked, then written to the other LDS buffer.  A single wave uses
+    // the LDS, whose operations it issues in order, so no barrier separates the writes from the
+    // reads.  The marks of a batch collect in one register (lane b: step b) and are stored with
+    // one coalesced store.
+    __shared__ LdsBatch<LDSB> L;
+    uint32_t pv, pvc;
+    float4 ra, rb;
+    float bl;
+    lds_fetch(pair_item, crec, blue, imax, start + lane, lane < LDSB && start + lane < end, pvc, ra, rb, bl);
+    lds_put<LDSB>(L, 0, lane, ra, rb, bl);
+    int buf = 0;
+    for (int base = start; base < end; base += LDSB) {
+      if (!any_live(fy)) break;
+      const int nb = base + LDSB;
+      lds_fetch(pair_item, crec, blue, imax, nb + lane, lane < LDSB && nb + lane < end, pv, ra, rb, bl);
+      const int n = min(LDSB, end - base);
+      uint32_t marks = 0;
+      for (int b = 0; b < n; ++b) {
+        const Rec r = lds_get<LDSB>(L, buf, b);
+        const uint32_t g = fwd_step<PPL, STATS>(r, base - start + b, fx, fy, T, cr, cg, cb, nvis, n_eval, n_used);
+        marks = lane == b ? g : marks;
+      }
+      if (lane < n) pair_marked[base + lane] = (pvc & kItemMask) | (marks << kItemBits);
+      buf ^= 1;
+      pvc = pv;
+      lds_put<LDSB>(L, buf, lane, ra, rb, bl);
+    }
+  } else {
   // Records through the scalar cache one list step ahead of their use, pair values by vector loads
   // three steps ahead (measured faster here than scalar pair-value loads, which put a second
   // scalar round trip in front of every record), unrolled by three so that the item slots rotate
-  // without copies.
+  // without copies.  All three steps of an iteration run; past the end of the list a record is a
+  // duplicate whose log-opacity is set to -inf, so alpha = 0 and it changes nothing.
   const __amdgpu_buffer_rsrc_t irs = item_rsrc(pair_item, n_pairs);
-  const float4* __restrict__ crec = reinterpret_cast<const float4*>(coef);
-  const uint32_t imax = n_items > 0 ? static_cast<uint32_t>(n_items - 1) : 0u;
   uint32_t u0 = uniform(load_item(irs, start)), u1, u2;
   Rec R0 = load_rec_s(crec, blue, u0, imax), R1, R2;
   uint32_t L1 = load_item(irs, min(start + 1, lastj)), L2 = load_item(irs, min(start + 2, lastj)),
@@ -379,6 +455,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
                                                                   n_eval, n_used) << kItemBits);
     if (kMark) store_pair_values(pair_marked, lane, j, min(end - j, 3), m0, m1, m2);
     u0 = un;
+  }
   }
   if (STATS) add_stats(stats, n_eval, n_used);
   const int64_t HW = static_cast<int64_t>(v.width) * v.height;
@@ -465,7 +542,7 @@ __device__ __forceinline__ void bwd_step(const Rec& r, uint32_t pv, int j, float
   if (out_lane && sum != 0.0f) unsafeAtomicAdd(&grad2d[16 * static_cast<size_t>(pv & kItemMask) + out_k], sum);
 }
 
-template <int TILE, bool STATS>
+template <int TILE, bool STATS, int LDSB>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
     const DevView* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ tile_order,
@@ -516,19 +593,42 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
   const int out_k = kCols ? col_index(lane) : rs_index(lane & 15);
   const bool out_lane = kCols ? out_k >= 0 : lane < 16 && ((lane & 1) == 0 || lane == 1);
   uint32_t n_eval = 0, n_used = 0;
-  // The forward's load pipeline, walking list positions maxn - 1 .. 0 (a step's record is
-  // requested two steps ahead, its item id four).  The distance also keeps every wait clear of
-  // the atomics issued at the end of the previous step: vector-memory operations complete in issue
-  // order, and the newest operation a step waits for was issued two steps earlier.  Positions
-  // below 0 are clamped to 0 and their loads never used.
   // pair_values: the forward's marked copy with one wave per tile (marks of the groups it
   // evaluated), else the sorted pair values.
   constexpr bool kMarked = C::kWaves == 1;
-  // Records through the scalar cache one step ahead, item ids by vector loads three ahead (the
-  // forward's pipeline, walking positions maxn - 1 .. 0; positions below 0 are clamped to 0 and
-  // their loads never used).
   const float4* __restrict__ crec = reinterpret_cast<const float4*>(coef);
   const uint32_t imax = n_items > 0 ? static_cast<uint32_t>(n_items - 1) : 0u;
+  if constexpr (LDSB > 0) {
+    static_assert(C::kWaves == 1, "LDS batches are wave-private");
+    // The forward's LDS batches walked in reverse: the batch ending at list position hi holds
+    // positions hi, hi - 1, ... in lanes 0, 1, ...
+    __shared__ LdsBatch<LDSB> L;
+    __shared__ uint32_t s_pv[2][LDSB];
+    uint32_t pv;
+    float4 ra, rb;
+    float bl;
+    int hi = maxn - 1;
+    lds_fetch(pair_values, crec, blue, imax, start + hi - lane, lane < LDSB && hi - lane >= 0, pv, ra, rb, bl);
+    lds_put<LDSB>(L, 0, lane, ra, rb, bl);
+    if (lane < LDSB) s_pv[0][lane] = pv;
+    int buf = 0;
+    for (; hi >= 0; hi -= LDSB) {
+      const int nh = hi - LDSB;
+      lds_fetch(pair_values, crec, blue, imax, start + nh - lane, lane < LDSB && nh - lane >= 0, pv, ra, rb, bl);
+      const int n = min(LDSB, hi + 1);
+      for (int b = 0; b < n; ++b) {
+        const Rec r = lds_get<LDSB>(L, buf, b);
+        bwd_step<PPL, kMarked, kCols, STATS>(r, uniform(s_pv[buf][b]), hi - b, fx, P, lane, out_k, out_lane,
+                                             grad2d, n_eval, n_used);
+      }
+      buf ^= 1;
+      lds_put<LDSB>(L, buf, lane, ra, rb, bl);
+      if (lane < LDSB) s_pv[buf][lane] = pv;
+    }
+  } else {
+  // Records through the scalar cache one step ahead of their use, pair values through the scalar
+  // cache one step before the record they address, walking positions maxn - 1 .. 0 (positions
+  // below 0 are clamped to 0 and their loads never used).
   const int top = max(maxn - 1, 0);
   uint32_t u0 = pair_values[start + top];
   Rec R0 = load_rec_s(crec, blue, u0, imax), R1, R2;
@@ -549,10 +649,11 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
     u1 = pair_values[start + max(j - 4, 0)];
     bwd_step<PPL, kMarked, kCols, STATS>(R2, u2, j - 2, fx, P, lane, out_k, out_lane, grad2d, n_eval, n_used);
   }
+  }
   if (STATS) add_stats(stats, n_eval, n_used);
 }
 
-template <int TILE>
+template <int TILE, int LDSB>
 static vbm_status launch_fwd_t(const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
                                const uint32_t* tile_order, const uint32_t* pair_item, int64_t n_pairs,
                                uint32_t* pair_marked, const float* coef, const float* blue, int64_t n_items,
@@ -560,16 +661,18 @@ static vbm_status launch_fwd_t(const DevView* views, int n_views, int64_t n_tile
                                hipStream_t s) {
   const dim3 block(TileCfg<TILE>::kThreads);
   if (stats)
-    hipLaunchKernelGGL((k_composite_fwd<TILE, true>), dim3(n_tiles), block, 0, s, views, n_views, ranges, tile_order,
-                       pair_item, n_pairs, pair_marked, coef, blue, n_items, image, final_T, n_contrib, stats);
+    hipLaunchKernelGGL((k_composite_fwd<TILE, true, LDSB>), dim3(n_tiles), block, 0, s, views, n_views, ranges,
+                       tile_order, pair_item, n_pairs, pair_marked, coef, blue, n_items, image, final_T, n_contrib,
+                       stats);
   else
-    hipLaunchKernelGGL((k_composite_fwd<TILE, false>), dim3(n_tiles), block, 0, s, views, n_views, ranges, tile_order,
-                       pair_item, n_pairs, pair_marked, coef, blue, n_items, image, final_T, n_contrib, stats);
+    hipLaunchKernelGGL((k_composite_fwd<TILE, false, LDSB>), dim3(n_tiles), block, 0, s, views, n_views, ranges,
+                       tile_order, pair_item, n_pairs, pair_marked, coef, blue, n_items, image, final_T, n_contrib,
+                       stats);
   VBM_LAUNCH_CHECK("composite_fwd");
   return VBM_OK;
 }
 
-template <int TILE>
+template <int TILE, int LDSB>
 static vbm_status launch_bwd_t(const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
                                const uint32_t* tile_order, const uint32_t* pair_item, const uint32_t* pair_marked,
                                const float* coef, const float* blue, const float* final_T, const int32_t* n_contrib,
@@ -579,55 +682,52 @@ static vbm_status launch_bwd_t(const DevView* views, int n_views, int64_t n_tile
   // one wave per tile: the forward's marked copy; otherwise the sorted pair values
   const uint32_t* values = TileCfg<TILE>::kWaves == 1 ? pair_marked : pair_item;
   if (stats)
-    hipLaunchKernelGGL((k_composite_bwd<TILE, true>), dim3(n_tiles), block, 0, s, views, n_views, ranges, tile_order,
-                       values, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats);
+    hipLaunchKernelGGL((k_composite_bwd<TILE, true, LDSB>), dim3(n_tiles), block, 0, s, views, n_views, ranges,
+                       tile_order, values, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats);
   else
-    hipLaunchKernelGGL((k_composite_bwd<TILE, false>), dim3(n_tiles), block, 0, s, views, n_views, ranges, tile_order,
-                       values, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats);
+    hipLaunchKernelGGL((k_composite_bwd<TILE, false, LDSB>), dim3(n_tiles), block, 0, s, views, n_views, ranges,
+                       tile_order, values, coef, blue, final_T, n_contrib, dL_dimg, grad2d, n_items, stats);
   VBM_LAUNCH_CHECK("composite_bwd");
   return VBM_OK;
 }
 
-vbm_status launch_composite_fwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
-                                const uint32_t* tile_order, const uint32_t* pair_item, int64_t n_pairs,
-                                uint32_t* pair_marked, const float* coef, const float* blue, int64_t n_items,
-                                float* image, float* final_T, int32_t* n_contrib, unsigned long long* stats,
-                                hipStream_t s) {
-  switch (tile) {
-    case 8:
-      return launch_fwd_t<8>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, pair_marked, coef,
-                             blue, n_items,
-                             image, final_T, n_contrib, stats, s);
-    case 16:
-      return launch_fwd_t<16>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, pair_marked, coef,
-                              blue, n_items,
-                              image, final_T, n_contrib, stats, s);
-    case 32:
-      return launch_fwd_t<32>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, pair_marked, coef,
-                              blue, n_items,
-                              image, final_T, n_contrib, stats, s);
-  }
-  set_error("unsupported tile size %d", tile);
+vbm_status launch_composite_fwd(int tile, int lds_batch, const DevView* views, int n_views, int64_t n_tiles,
+                                const uint2* ranges, const uint32_t* tile_order, const uint32_t* pair_item,
+                                int64_t n_pairs, uint32_t* pair_marked, const float* coef, const float* blue,
+                                int64_t n_items, float* image, float* final_T, int32_t* n_contrib,
+                                unsigned long long* stats, hipStream_t s) {
+#define VBM_FWD(T, B)                                                                                              \
+  return launch_fwd_t<T, B>(views, n_views, n_tiles, ranges, tile_order, pair_item, n_pairs, pair_marked, coef,   \
+                            blue, n_items, image, final_T, n_contrib, stats, s)
+  if (tile == 8 && lds_batch == 0) VBM_FWD(8, 0);
+  if (tile == 8 && lds_batch == 32) VBM_FWD(8, 32);
+  if (tile == 8 && lds_batch == 64) VBM_FWD(8, 64);
+  if (tile == 16 && lds_batch == 0) VBM_FWD(16, 0);
+  if (tile == 16 && lds_batch == 32) VBM_FWD(16, 32);
+  if (tile == 16 && lds_batch == 64) VBM_FWD(16, 64);
+  if (tile == 32 && lds_batch == 0) VBM_FWD(32, 0);
+#undef VBM_FWD
+  set_error("unsupported tile size %d with LDS batch %d", tile, lds_batch);
   return VBM_ERR_UNSUPPORTED;
 }
 
-vbm_status launch_composite_bwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
-                                const uint32_t* tile_order, const uint32_t* pair_item, const uint32_t* pair_marked,
-                                const float* coef, const float* blue, const float* final_T, const int32_t* n_contrib,
-                                const float* dL_dimg, float* grad2d, int64_t n_items, unsigned long long* stats,
-                                hipStream_t s) {
-  switch (tile) {
-    case 8:
-      return launch_bwd_t<8>(views, n_views, n_tiles, ranges, tile_order, pair_item, pair_marked, coef, blue, final_T,
-                             n_contrib, dL_dimg, grad2d, n_items, stats, s);
-    case 16:
-      return launch_bwd_t<16>(views, n_views, n_tiles, ranges, tile_order, pair_item, pair_marked, coef, blue, final_T,
-                              n_contrib, dL_dimg, grad2d, n_items, stats, s);
-    case 32:
-      return launch_bwd_t<32>(views, n_views, n_tiles, ranges, tile_order, pair_item, pair_marked, coef, blue, final_T,
-                              n_contrib, dL_dimg, grad2d, n_items, stats, s);
-  }
-  set_error("unsupported tile size %d", tile);
+vbm_status launch_composite_bwd(int tile, int lds_batch, const DevView* views, int n_views, int64_t n_tiles,
+                                const uint2* ranges, const uint32_t* tile_order, const uint32_t* pair_item,
+                                const uint32_t* pair_marked, const float* coef, const float* blue,
+                                const float* final_T, const int32_t* n_contrib, const float* dL_dimg, float* grad2d,
+                                int64_t n_items, unsigned long long* stats, hipStream_t s) {
+#define VBM_BWD(T, B)                                                                                              \
+  return launch_bwd_t<T, B>(views, n_views, n_tiles, ranges, tile_order, pair_item, pair_marked, coef, blue,       \
+                            final_T, n_contrib, dL_dimg, grad2d, n_items, stats, s)
+  if (tile == 8 && lds_batch == 0) VBM_BWD(8, 0);
+  if (tile == 8 && lds_batch == 32) VBM_BWD(8, 32);
+  if (tile == 8 && lds_batch == 64) VBM_BWD(8, 64);
+  if (tile == 16 && lds_batch == 0) VBM_BWD(16, 0);
+  if (tile == 16 && lds_batch == 32) VBM_BWD(16, 32);
+  if (tile == 16 && lds_batch == 64) VBM_BWD(16, 64);
+  if (tile == 32 && lds_batch == 0) VBM_BWD(32, 0);
+#undef VBM_BWD
+  set_error("unsupported tile size %d with LDS batch %d", tile, lds_batch);
   return VBM_ERR_UNSUPPORTED;
 }
 

@@ -32,16 +32,16 @@ __global__ void k_status(const uint32_t*, int32_t*);
 __global__ void k_tile_keys(const uint2*, int64_t, uint32_t*, uint32_t*);
 __global__ void k_project_bwd(const DevView*, int, const DevScene*, int, vbm_gaussians_c, float*, const float4*,
                               int64_t, const uint32_t*, vbm_gaussians, int, int64_t);
-vbm_status launch_composite_fwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
-                                const uint32_t* tile_order, const uint32_t* pair_item, int64_t n_pairs,
-                                uint32_t* pair_marked, const float* coef, const float* blue, int64_t n_items,
-                                float* image, float* final_T, int32_t* n_contrib, unsigned long long* stats,
-                                hipStream_t s);
-vbm_status launch_composite_bwd(int tile, const DevView* views, int n_views, int64_t n_tiles, const uint2* ranges,
-                                const uint32_t* tile_order, const uint32_t* pair_item, const uint32_t* pair_marked,
-                                const float* coef, const float* blue, const float* final_T, const int32_t* n_contrib,
-                                const float* dL_dimg, float* grad2d, int64_t n_items, unsigned long long* stats,
-                                hipStream_t s);
+vbm_status launch_composite_fwd(int tile, int lds_batch, const DevView* views, int n_views, int64_t n_tiles,
+                                const uint2* ranges, const uint32_t* tile_order, const uint32_t* pair_item,
+                                int64_t n_pairs, uint32_t* pair_marked, const float* coef, const float* blue,
+                                int64_t n_items, float* image, float* final_T, int32_t* n_contrib,
+                                unsigned long long* stats, hipStream_t s);
+vbm_status launch_composite_bwd(int tile, int lds_batch, const DevView* views, int n_views, int64_t n_tiles,
+                                const uint2* ranges, const uint32_t* tile_order, const uint32_t* pair_item,
+                                const uint32_t* pair_marked, const float* coef, const float* blue,
+                                const float* final_T, const int32_t* n_contrib, const float* dL_dimg, float* grad2d,
+                                int64_t n_items, unsigned long long* stats, hipStream_t s);
 
 namespace {
 
@@ -207,6 +207,10 @@ extern "C" vbm_status vbm_plan_make(const vbm_view* views, int32_t n_views, cons
     set_error("vbm_plan_make: tile must be 8, 16 or 32 (got %d)", sch->tile);
     return VBM_ERR_UNSUPPORTED;
   }
+  if (!(sch->lds_batch == 0 || ((sch->lds_batch == 32 || sch->lds_batch == 64) && sch->tile <= 16))) {
+    set_error("vbm_plan_make: lds_batch must be 0, or 32 or 64 with 8x8 or 16x16 tiles");
+    return VBM_ERR_UNSUPPORTED;
+  }
   if (sch->sort_bits < 4 || sch->sort_bits > 8) {
     set_error("vbm_plan_make: sort_bits must be 4..8");
     return VBM_ERR_INVALID;
@@ -234,6 +238,7 @@ extern "C" vbm_status vbm_plan_make(const vbm_view* views, int32_t n_views, cons
   plan->tile = sch->tile;
   plan->mode = sch->mode;
   plan->sort_bits = sch->sort_bits;
+  plan->lds_batch = sch->lds_batch;
   plan->pair_capacity = sch->pair_capacity;
   plan->n_gaussians = scene_offsets[n_scenes];
   std::vector<DevView> dv(n_views);
@@ -405,7 +410,8 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
   }
   VBM_TRY(record(0, s));
   // the sorted pair values stay in pi[0]; the forward's marked copy goes to the idle ping-pong buffer
-  VBM_TRY(launch_composite_fwd(p->tile, views, p->n_views, p->n_tiles, ranges, tile_order(p, ws), pi[0], cap, pi[1],
+  VBM_TRY(launch_composite_fwd(p->tile, p->lds_batch, views, p->n_views, p->n_tiles, ranges, tile_order(p, ws), pi[0],
+                               cap, pi[1],
                                reinterpret_cast<const float*>(coef), blue, I, image, final_T, n_contrib, g_stats, s));
   VBM_TRY(record(1, s));
   hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, s, counters, status);
@@ -436,7 +442,8 @@ extern "C" vbm_status vbm_render_bwd(const vbm_plan* p, const void* view_table, 
   float* grad2d = region<float>(p, ws, R_GRAD2D);
   VBM_TRY(fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, 16 * I, s));
   VBM_TRY(record(2, s));
-  VBM_TRY(launch_composite_bwd(p->tile, views, p->n_views, p->n_tiles, region<uint2>(p, ws, R_RANGES), tile_order(p, ws),
+  VBM_TRY(launch_composite_bwd(p->tile, p->lds_batch, views, p->n_views, p->n_tiles, region<uint2>(p, ws, R_RANGES),
+                               tile_order(p, ws),
                                region<uint32_t>(p, ws, R_PITEM), region<uint32_t>(p, ws, R_PITEM_ALT),
                                region<float>(p, ws, R_COEF), region<float>(p, ws, R_BLUE), final_T, n_contrib, dL_dimg,
                                grad2d, I, g_stats ? g_stats + 2 : nullptr, s));

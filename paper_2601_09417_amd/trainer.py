@@ -79,10 +79,10 @@ class FineTuner:
     def __init__(self, P: torch.Tensor, cams, targets: torch.Tensor, scene_offsets=None, view_scene=None,
                  tile: int = 16, sort_bits: int = 8, loss: str = "l1", lam: float = 0.2, lr=api.LR_DEFAULT,
                  schedule: str = "batched", pair_capacity: int | None = None, capacity_margin: float = 1.25,
-                 classes=None, class_schedules=None):
+                 classes=None, class_schedules=None, lds_batch: int = 0):
         """``classes``: consecutive view ranges [(v0, v1), ...] covering every view, each rendered by
-        its own launches with (tile, sort_bits) from ``class_schedules`` (default: one class, the
-        whole batch, with ``tile`` and ``sort_bits``)."""
+        its own launches with (tile, sort_bits[, lds_batch]) from ``class_schedules`` (default: one
+        class, the whole batch, with ``tile``, ``sort_bits`` and ``lds_batch``)."""
         assert schedule in ("plain", "batched", "graph")
         self.dev = P.device
         self.cams = list(cams)
@@ -93,8 +93,8 @@ class FineTuner:
         self.classes = [tuple(c) for c in classes] if classes is not None else [(0, len(self.cams))]
         if [v for c in self.classes for v in range(c[0], c[1])] != list(range(len(self.cams))):
             raise ValueError("classes must be consecutive view ranges covering every view once, in order")
-        self.class_schedules = ([tuple(x) for x in class_schedules] if class_schedules is not None
-                                else [(tile, sort_bits)] * len(self.classes))
+        self.class_schedules = ([(tuple(x) + (0,))[:3] for x in class_schedules] if class_schedules is not None
+                                else [(tile, sort_bits, lds_batch)] * len(self.classes))
         if len(self.class_schedules) != len(self.classes):
             raise ValueError("one (tile, sort_bits) per class")
         self.view_schedule = [self.class_schedules[c] for c, (a, b) in enumerate(self.classes) for _ in range(a, b)]
@@ -122,8 +122,8 @@ class FineTuner:
         """Exact pair count per view from one exact-mode forward (planning only)."""
         counts = []
         for v, cam in enumerate(self.cams):
-            tile, bits = self.view_schedule[v]
-            rp = api.plan_batch([cam], self.scene_offsets, [self.view_scene[v]], tile, bits, 1, "exact", self.dev)
+            tile, bits, lds = self.view_schedule[v]
+            rp = api.plan_batch([cam], self.scene_offsets, [self.view_scene[v]], tile, bits, 1, "exact", self.dev, lds)
             out = api.render_fwd(rp, self.act)
             torch.cuda.synchronize(self.dev)
             counts.append(int(out.status[1].item()))
@@ -141,9 +141,9 @@ class FineTuner:
             groups = [(a, b, *self.class_schedules[c], sum(self.view_caps[a:b]) if capacity is None else capacity,
                        "batched") for c, (a, b) in enumerate(self.classes)]
         self.plans, self.outs = [], []
-        for a, b, tile, bits, cap, mode in groups:
+        for a, b, tile, bits, lds, cap, mode in groups:
             self.plans.append(api.plan_batch(self.cams[a:b], self.scene_offsets, self.view_scene[a:b], tile, bits, cap,
-                                             mode, self.dev))
+                                             mode, self.dev, lds))
             pa, pb = int(self.pix_off[a]), int(self.pix_off[b])
             self.outs.append(api.FwdOut(self.image[3 * pa:3 * pb], self.final_T[pa:pb], self.n_contrib[pa:pb],
                                         torch.zeros(4, dtype=torch.int32, device=self.dev)))
@@ -225,7 +225,8 @@ def render_images(P: torch.Tensor, cams, scene_offsets=None, view_scene=None, ti
     return out.image
 
 
-TUNE_CANDIDATES = ((16, 8), (8, 8), (32, 8), (16, 4))
+# (tile edge, tile-sort digit width, LDS batch depth of the compositing list walk; 0 = scalar cache)
+TUNE_CANDIDATES = ((16, 8, 0), (8, 8, 0), (32, 8, 0), (16, 4, 0), (16, 4, 32), (16, 4, 64))
 
 
 def _pixel_range(cams, a, b):
@@ -247,28 +248,31 @@ def autotune_classes(P: torch.Tensor, cams, targets: torch.Tensor, scene_offsets
         pa, pb = _pixel_range(cams, a, b)
         r = autotune(P, cams[a:b], targets[3 * pa:3 * pb], scene_offsets, vs[a:b], loss=loss, lam=lam,
                      candidates=candidates, steps=steps, warmup=warmup)
-        schedules.append((r["tile"], r["sort_bits"]))
+        schedules.append((r["tile"], r["sort_bits"], r["lds_batch"]))
         tables.append(r["table"])
     return dict(classes=classes, schedules=schedules, tables=tables)
 
 
 def autotune(P: torch.Tensor, cams, targets: torch.Tensor, scene_offsets=None, view_scene=None, loss: str = "l1",
              lam: float = 0.2, candidates=TUNE_CANDIDATES, steps: int = 3, warmup: int = 1) -> dict:
-    """Chooses the tile edge and the radix digit width of the tile sort for a batch.
+    """Chooses the tile edge, the radix digit width of the tile sort and the LDS batch depth of the
+    compositing list walk for a batch.
 
-    Each candidate (tile, sort_bits) gets its own plan (exact pair counts, capacity margin) and runs
-    ``warmup`` + ``steps`` eager batched iterations on a copy of P (FineTuner clones it), timed with a
-    device synchronisation on both sides.  Returns the fastest as dict(tile, sort_bits, ms) plus the
-    table of every candidate's ms per step.
+    Each candidate (tile, sort_bits, lds_batch) gets its own plan (exact pair counts, capacity
+    margin) and runs ``warmup`` + ``steps`` eager batched iterations on a copy of P (FineTuner
+    clones it), timed with a device synchronisation on both sides.  Returns the fastest as
+    dict(tile, sort_bits, lds_batch, ms) plus the table of every candidate's ms per step.
     """
     table = []
-    for tile, bits in candidates:
-        ft = FineTuner(P, cams, targets, scene_offsets, view_scene, tile=tile, sort_bits=bits, loss=loss, lam=lam,
-                       schedule="batched")
-        table.append(dict(tile=tile, sort_bits=bits, ms=_time_steps(ft, steps, warmup)))
+    for cand in candidates:
+        tile, bits, lds = (tuple(cand) + (0,))[:3]
+        ft = FineTuner(P, cams, targets, scene_offsets, view_scene, tile=tile, sort_bits=bits, lds_batch=lds,
+                       loss=loss, lam=lam, schedule="batched")
+        table.append(dict(tile=tile, sort_bits=bits, lds_batch=lds, ms=_time_steps(ft, steps, warmup)))
         del ft
     best = min(table, key=lambda d: d["ms"])
-    return dict(tile=best["tile"], sort_bits=best["sort_bits"], ms=best["ms"], table=table)
+    return dict(tile=best["tile"], sort_bits=best["sort_bits"], lds_batch=best["lds_batch"], ms=best["ms"],
+                table=table)
 
 
 def _time_steps(ft: "FineTuner", steps: int, warmup: int) -> float:
@@ -294,8 +298,8 @@ def autotune_schedule(P: torch.Tensor, cams, targets: torch.Tensor, scene_offset
     FineTuner keywords (tile, sort_bits, classes, class_schedules) plus the measurements."""
     whole = autotune(P, cams, targets, scene_offsets, view_scene, loss=loss, lam=lam, candidates=candidates,
                      steps=steps, warmup=warmup)
-    out = dict(tile=whole["tile"], sort_bits=whole["sort_bits"], classes=None, class_schedules=None,
-               ms=whole["ms"], table=whole["table"])
+    out = dict(tile=whole["tile"], sort_bits=whole["sort_bits"], lds_batch=whole["lds_batch"], classes=None,
+               class_schedules=None, ms=whole["ms"], table=whole["table"])
     classes = size_classes(cams)
     if len(classes) > 1:
         ct = autotune_classes(P, cams, targets, scene_offsets, view_scene, classes, loss=loss, lam=lam,

@@ -234,12 +234,12 @@ def test_autotune_pick_matches_oracle_and_digit_widths_agree():
     P = api.pack_params(gs.means, gs.scales, gs.quats, gs.opacity, gs.rgb, dev())
     res = trainer.autotune(P, cams, tgt, steps=2, warmup=1)
     say(f"autotune: {res['table']} -> tile {res['tile']}, {res['sort_bits']}-bit digits")
-    assert [(r["tile"], r["sort_bits"]) for r in res["table"]] == list(trainer.TUNE_CANDIDATES)
+    assert [(r["tile"], r["sort_bits"], r["lds_batch"]) for r in res["table"]] == list(trainer.TUNE_CANDIDATES)
     assert all(np.isfinite(r["ms"]) and r["ms"] > 0 for r in res["table"])
     assert res["ms"] == min(r["ms"] for r in res["table"])
 
-    def run(tile, bits):
-        rp = api.plan_batch(cams, [0, gs.n], tile=tile, sort_bits=bits, pair_capacity=1 << 20)
+    def run(tile, bits, lds=0):
+        rp = api.plan_batch(cams, [0, gs.n], tile=tile, sort_bits=bits, pair_capacity=1 << 20, lds_batch=lds)
         out = api.render_fwd(rp, P)
         torch.cuda.synchronize()
         assert int(out.status[0]) == 0
@@ -250,7 +250,7 @@ def test_autotune_pick_matches_oracle_and_digit_widths_agree():
                     image=out.image.cpu().numpy(), final_T=out.final_T.cpu().numpy(),
                     n_contrib=out.n_contrib.cpu().numpy())
 
-    pick = run(res["tile"], res["sort_bits"])
+    pick = run(res["tile"], res["sort_bits"], res["lds_batch"])
     ref = binning.pair_lists(gs, cams, res["tile"])
     assert np.array_equal(pick["tile"], ref["tile"])
     assert np.array_equal(pick["item"] & ITEM_MASK, ref["item"])
@@ -260,6 +260,12 @@ def test_autotune_pick_matches_oracle_and_digit_widths_agree():
             other = run(tile, bits)
             for k in base:
                 assert np.array_equal(base[k], other[k]), (tile, bits, k)
+        if tile <= 16:
+            # the LDS-staged list walk composites in the same order: the same forward bit for bit
+            for lds in (32, 64):
+                other = run(tile, 8, lds)
+                for k in ("tile", "item", "ranges", "image", "final_T", "n_contrib"):
+                    assert np.array_equal(base[k], other[k]), (tile, lds, k)
 
 
 def test_graph_replay_matches_eager_repeatedly():

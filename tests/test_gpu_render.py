@@ -133,13 +133,15 @@ def test_large_footprints_beyond_the_ballot_word_buffer():
     assert np.array_equal(rp.region("pair_item", torch.int32).cpu().numpy()[:n] & ITEM_MASK, ref["item"])
 
 
-@pytest.mark.parametrize("tile,W,H", [(16, 64, 64), (16, 101, 67), (8, 50, 37), (32, 96, 80)])
-def test_forward_backward_parity(tile, W, H):
+# (the last three stage the compositing lists in LDS batches of 32 or 64 entries)
+@pytest.mark.parametrize("tile,W,H,lds", [(16, 64, 64, 0), (16, 101, 67, 0), (8, 50, 37, 0), (32, 96, 80, 0),
+                                          (16, 101, 67, 32), (16, 64, 64, 64), (8, 50, 37, 64)])
+def test_forward_backward_parity(tile, W, H, lds):
     api = _api()
     gs, cams = _scene(600, 3, 2, W, H)
-    say(f"fwd/bwd parity tile={tile} {W}x{H} n={gs.n}")
+    say(f"fwd/bwd parity tile={tile} {W}x{H} n={gs.n} lds batch {lds}")
     P = to_dev(gs)
-    rp = api.plan_batch(cams, [0, gs.n], tile=tile, pair_capacity=1 << 18)
+    rp = api.plan_batch(cams, [0, gs.n], tile=tile, pair_capacity=1 << 18, lds_batch=lds)
     out = api.render_fwd(rp, P)
     batch = render.Batch(gs, cams, tile)
     ref = render.render_forward(batch)
