@@ -413,31 +413,34 @@ def timed_step_runs(args, out, P, cams, targets, wl, scene_offsets, view_scene):
     ckw = {}       # per-size-class schedule, when the autotuner keeps one
     if args.tile == "auto":
         tune = trainer.autotune_schedule(P, cams, targets, so, vs, loss=loss_kind, lam=0.2)
-        tile, bits, lds = tune["tile"], tune["sort_bits"], tune["lds_batch"]
-        out["autotune"] = [dict(tile=d["tile"], sort_bits=d["sort_bits"], lds_batch=d["lds_batch"], ms=round(d["ms"], 3))
-                           for d in tune["table"]]
-        log("autotune: " + ", ".join(f"tile {d['tile']}/{d['sort_bits']}b/lds{d['lds_batch']} {d['ms']:.2f} ms"
-                                     for d in tune["table"]) + f" -> tile {tile}, {bits}-bit digits, LDS batch {lds}")
+        tile, bits, lds, lds_bwd = tune["tile"], tune["sort_bits"], tune["lds_batch"], tune["lds_batch_bwd"]
+        out["autotune"] = [dict(tile=d["tile"], sort_bits=d["sort_bits"], lds_batch=d["lds_batch"],
+                                lds_batch_bwd=d["lds_batch_bwd"], ms=round(d["ms"], 3)) for d in tune["table"]]
+        log("autotune: " + ", ".join(f"tile {d['tile']}/{d['sort_bits']}b/lds{d['lds_batch']}/{d['lds_batch_bwd']} "
+                                     f"{d['ms']:.2f} ms" for d in tune["table"])
+            + f" -> tile {tile}, {bits}-bit digits, LDS batch {lds} forward / {lds_bwd} backward")
         if "per_class" in tune:
             pc = tune["per_class"]
             out["autotune_classes"] = dict(classes=pc["classes"], schedules=pc["schedules"], step_ms=round(pc["ms"], 3),
-                                           single_schedule_step_ms=round(min(d["ms"] for d in tune["table"]), 3),
+                                           single_schedule_step_ms=round(tune["single_ms"], 3),
                                            kept=tune["classes"] is not None,
                                            tables=[[dict(tile=d["tile"], sort_bits=d["sort_bits"],
-                                                         lds_batch=d["lds_batch"], ms=round(d["ms"], 3))
+                                                         lds_batch=d["lds_batch"], lds_batch_bwd=d["lds_batch_bwd"],
+                                                         ms=round(d["ms"], 3))
                                                     for d in t] for t in tune["class_tables"]])
             log(f"autotune per size class: {pc['schedules']} -> step {pc['ms']:.2f} ms "
                 f"({'kept' if tune['classes'] is not None else 'one schedule is faster'})")
         if tune["classes"] is not None:
             ckw = dict(classes=tune["classes"], class_schedules=tune["class_schedules"])
     else:
-        tile, bits, lds = int(args.tile), 8, 0
-    out["tile"], out["sort_bits"], out["lds_batch"], out["loss_kind"] = tile, bits, lds, loss_kind
+        tile, bits, lds, lds_bwd = int(args.tile), args.sort_bits, args.lds_batch, args.lds_batch_bwd
+    out["tile"], out["sort_bits"], out["loss_kind"] = tile, bits, loss_kind
+    out["lds_batch"], out["lds_batch_bwd"] = lds, lds_bwd
     out["class_schedules"] = ckw.get("class_schedules")
 
     # batched schedule, captured as a graph: the reported value
     ft = trainer.FineTuner(P, cams, targets, so, vs, loss=loss_kind, lam=0.2,
-                           tile=tile, sort_bits=bits, lds_batch=lds, schedule="graph", **ckw)
+                           tile=tile, sort_bits=bits, lds_batch=lds, lds_batch_bwd=lds_bwd, schedule="graph", **ckw)
     wall, ev = timed(ft, args.steps, args.warmup)
     if ft.overflowed():
         raise RuntimeError("pair capacity overflow during the timed region")
@@ -451,7 +454,7 @@ def timed_step_runs(args, out, P, cams, targets, wl, scene_offsets, view_scene):
     reps = [args.steps / wall]
     for _ in range(max(args.repeats - 1, 0)):
         fr = trainer.FineTuner(P, cams, targets, so, vs, loss=loss_kind, lam=0.2,
-                               tile=tile, sort_bits=bits, lds_batch=lds, schedule="graph", **ckw)
+                               tile=tile, sort_bits=bits, lds_batch=lds, lds_batch_bwd=lds_bwd, schedule="graph", **ckw)
         w2, _ = timed(fr, args.steps, args.warmup)
         if not fr.overflowed():
             reps.append(args.steps / w2)
@@ -462,7 +465,7 @@ def timed_step_runs(args, out, P, cams, targets, wl, scene_offsets, view_scene):
     # (one launch per phase: with a per-class schedule the kernels are timed on the whole batch with
     # the best single schedule, since the library's profiling events bracket one launch)
     fb = trainer.FineTuner(P, cams, targets, so, vs, loss=loss_kind, lam=0.2,
-                           tile=tile, sort_bits=bits, lds_batch=lds, schedule="batched")
+                           tile=tile, sort_bits=bits, lds_batch=lds, lds_batch_bwd=lds_bwd, schedule="batched")
     for _ in range(args.warmup):
         fb.step()
     # one untimed step with the counting kernel variants (evaluations and contributions) ...
@@ -504,7 +507,7 @@ def timed_step_runs(args, out, P, cams, targets, wl, scene_offsets, view_scene):
     # plain schedule: one view per launch, one host sync per view forward
     if not args.skip_plain:
         fp = trainer.FineTuner(P, cams, targets, so, vs, loss=loss_kind, lam=0.2,
-                               tile=tile, sort_bits=bits, lds_batch=lds, schedule="plain")
+                               tile=tile, sort_bits=bits, lds_batch=lds, lds_batch_bwd=lds_bwd, schedule="plain")
         wall_p, _ = timed(fp, args.steps, args.warmup)
         out["plain_wall_s"] = wall_p
         log(f"plain: {args.steps / wall_p:.2f} it/s")
@@ -619,6 +622,12 @@ def main() -> int:
     ap.add_argument("--workload", default="H", choices=sorted(WORKLOADS))
     ap.add_argument("--tile", default="auto", choices=["auto", "8", "16", "32"],
                     help="tile edge; auto = pick (tile, radix digit) by timing each before the timed run")
+    ap.add_argument("--sort-bits", type=int, default=8, choices=[4, 8],
+                    help="radix digit width of the tile sort when --tile is fixed")
+    ap.add_argument("--lds-batch", type=int, default=0, choices=[0, 32, 64],
+                    help="forward compositing list entries staged in LDS per wave when --tile is fixed (8 and 16 only)")
+    ap.add_argument("--lds-batch-bwd", type=int, default=0, choices=[0, 32, 64],
+                    help="the same for the backward compositing")
     ap.add_argument("--loss", default="default", choices=["default", "l1", "l1_dssim"],
                     help="image loss; default = the workload's")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -696,7 +705,8 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl['desc']}", **workload_config(wl), "tile": gpu["tile"],
-                   "sort_bits": gpu["sort_bits"], "lds_batch": gpu["lds_batch"], "loss": gpu["loss_kind"],
+                   "sort_bits": gpu["sort_bits"], "lds_batch": gpu["lds_batch"],
+                   "lds_batch_bwd": gpu["lds_batch_bwd"], "loss": gpu["loss_kind"],
                    "schedule": ("batched per size class " + str(gpu["class_schedules"]) if gpu.get("class_schedules")
                                 else "batched") + ", HIP graph"},
         "autotune": gpu.get("autotune"),

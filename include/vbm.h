@@ -240,15 +240,18 @@ typedef struct {
   int32_t sort_bits;     /* radix digit width for the tile sort: 4..8 */
   int64_t pair_capacity; /* pair slots reserved in the workspace, in [1, 2^30) */
   int32_t mode;          /* VBM_MODE_BATCHED or VBM_MODE_EXACT */
-  int32_t lds_batch;     /* compositing record staging: 0 = each record through the scalar cache
-                          * into registers; 32 or 64 = the tile's list staged in LDS batches of that
-                          * many entries (8x8 and 16x16 tiles only).  Results are identical. */
+  int32_t lds_batch;     /* record staging of the forward compositing: 0 = each record through the
+                          * scalar cache into registers; 32 or 64 = the tile's list staged in LDS
+                          * batches of that many entries (8x8 and 16x16 tiles only).  Results are
+                          * identical. */
+  int32_t lds_batch_bwd; /* the same choice for the backward compositing */
+  int32_t pad0;
 } vbm_schedule;
 
 #define VBM_WS_REGIONS 24
 typedef struct {
   int32_t n_views, n_scenes, tile, mode;
-  int32_t sort_bits, tile_key_bits, lds_batch, pad1;
+  int32_t sort_bits, tile_key_bits, lds_batch, lds_batch_bwd;
   int64_t n_gaussians, n_items, n_tiles, n_pixels, pair_capacity;
   size_t view_table_bytes; /* device view table written by vbm_plan_make into view_table_host */
   size_t ws_bytes;         /* workspace needed by vbm_render_fwd + vbm_render_bwd */

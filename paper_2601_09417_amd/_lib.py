@@ -60,12 +60,13 @@ class vbm_view(C.Structure):
 
 class vbm_schedule(C.Structure):
     _fields_ = [("tile", C.c_int32), ("sort_bits", C.c_int32), ("pair_capacity", C.c_int64), ("mode", C.c_int32),
-                ("lds_batch", C.c_int32)]
+                ("lds_batch", C.c_int32), ("lds_batch_bwd", C.c_int32), ("pad0", C.c_int32)]
 
 
 class vbm_plan(C.Structure):
     _fields_ = [("n_views", C.c_int32), ("n_scenes", C.c_int32), ("tile", C.c_int32), ("mode", C.c_int32),
-                ("sort_bits", C.c_int32), ("tile_key_bits", C.c_int32), ("lds_batch", C.c_int32), ("pad1", C.c_int32),
+                ("sort_bits", C.c_int32), ("tile_key_bits", C.c_int32), ("lds_batch", C.c_int32),
+                ("lds_batch_bwd", C.c_int32),
                 ("n_gaussians", C.c_int64), ("n_items", C.c_int64), ("n_tiles", C.c_int64), ("n_pixels", C.c_int64),
                 ("pair_capacity", C.c_int64), ("view_table_bytes", C.c_size_t), ("ws_bytes", C.c_size_t),
                 ("region_offset", C.c_size_t * VBM_WS_REGIONS), ("region_bytes", C.c_size_t * VBM_WS_REGIONS)]

@@ -210,7 +210,8 @@ class RenderPlan:
 
 
 def plan_batch(cams, scene_offsets=None, view_scene=None, tile: int = 16, sort_bits: int = 8,
-               pair_capacity: int = 1 << 20, mode: str = "batched", device="cuda", lds_batch: int = 0) -> RenderPlan:
+               pair_capacity: int = 1 << 20, mode: str = "batched", device="cuda", lds_batch: int = 0,
+               lds_batch_bwd: int = 0) -> RenderPlan:
     lib = L.load()
     V = len(cams)
     view_scene = list(view_scene) if view_scene is not None else [0] * V
@@ -218,7 +219,7 @@ def plan_batch(cams, scene_offsets=None, view_scene=None, tile: int = 16, sort_b
     S = scene_offsets.shape[0] - 1
     views = (L.vbm_view * V)(*[make_view(c, s) for c, s in zip(cams, view_scene)])
     sch = L.vbm_schedule(tile, sort_bits, int(pair_capacity), L.MODE_EXACT if mode == "exact" else L.MODE_BATCHED,
-                         int(lds_batch))
+                         int(lds_batch), int(lds_batch_bwd))
     plan = L.vbm_plan()
     so = np.ascontiguousarray(scene_offsets)
     L.check(lib.vbm_plan_make(views, V, so.ctypes.data_as(C.POINTER(C.c_int64)), S, C.byref(sch), C.byref(plan), None),

@@ -91,9 +91,10 @@ size_t scan_scratch_bytes(int64_t n_max);
 vbm_status scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n_max, const uint32_t* n_dev,
                               uint32_t* total_dev, void* scratch, hipStream_t s);
 
-// Stable LSD radix sort of (key, value) pairs over key bits [0, end_bit), digit width 4..8 bits.
-// Passes ping-pong between (k0, v0) and (k1, v1); returns in *result_in_k1 whether the sorted data
-// ends in the second buffer.  The element count is read from *n_dev (<= n_max) when non-null.
+// Stable LSD radix sort of (key, value) pairs over key bits [0, end_bit) (end_bit <= 32), digit
+// width 4..8 bits.  Passes ping-pong between (k0, v0) and (k1, v1); returns in *result_in_k1
+// whether the sorted data ends in the second buffer.  The element count is read from *n_dev
+// (<= n_max) when non-null.
 size_t radix_scratch_bytes(int64_t n_max, int digit_bits);
 template <class K>
 vbm_status radix_sort_pairs(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t n_max, const uint32_t* n_dev,

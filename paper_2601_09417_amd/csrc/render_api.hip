@@ -207,8 +207,9 @@ extern "C" vbm_status vbm_plan_make(const vbm_view* views, int32_t n_views, cons
     set_error("vbm_plan_make: tile must be 8, 16 or 32 (got %d)", sch->tile);
     return VBM_ERR_UNSUPPORTED;
   }
-  if (!(sch->lds_batch == 0 || ((sch->lds_batch == 32 || sch->lds_batch == 64) && sch->tile <= 16))) {
-    set_error("vbm_plan_make: lds_batch must be 0, or 32 or 64 with 8x8 or 16x16 tiles");
+  auto lds_ok = [&](int32_t b) { return b == 0 || ((b == 32 || b == 64) && sch->tile <= 16); };
+  if (!lds_ok(sch->lds_batch) || !lds_ok(sch->lds_batch_bwd)) {
+    set_error("vbm_plan_make: lds_batch and lds_batch_bwd must be 0, or 32 or 64 with 8x8 or 16x16 tiles");
     return VBM_ERR_UNSUPPORTED;
   }
   if (sch->sort_bits < 4 || sch->sort_bits > 8) {
@@ -239,6 +240,7 @@ extern "C" vbm_status vbm_plan_make(const vbm_view* views, int32_t n_views, cons
   plan->mode = sch->mode;
   plan->sort_bits = sch->sort_bits;
   plan->lds_batch = sch->lds_batch;
+  plan->lds_batch_bwd = sch->lds_batch_bwd;
   plan->pair_capacity = sch->pair_capacity;
   plan->n_gaussians = scene_offsets[n_scenes];
   std::vector<DevView> dv(n_views);
@@ -442,7 +444,7 @@ extern "C" vbm_status vbm_render_bwd(const vbm_plan* p, const void* view_table, 
   float* grad2d = region<float>(p, ws, R_GRAD2D);
   VBM_TRY(fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, 16 * I, s));
   VBM_TRY(record(2, s));
-  VBM_TRY(launch_composite_bwd(p->tile, p->lds_batch, views, p->n_views, p->n_tiles, region<uint2>(p, ws, R_RANGES),
+  VBM_TRY(launch_composite_bwd(p->tile, p->lds_batch_bwd, views, p->n_views, p->n_tiles, region<uint2>(p, ws, R_RANGES),
                                tile_order(p, ws),
                                region<uint32_t>(p, ws, R_PITEM), region<uint32_t>(p, ws, R_PITEM_ALT),
                                region<float>(p, ws, R_COEF), region<float>(p, ws, R_BLUE), final_T, n_contrib, dL_dimg,

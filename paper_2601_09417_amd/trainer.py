@@ -79,10 +79,11 @@ class FineTuner:
     def __init__(self, P: torch.Tensor, cams, targets: torch.Tensor, scene_offsets=None, view_scene=None,
                  tile: int = 16, sort_bits: int = 8, loss: str = "l1", lam: float = 0.2, lr=api.LR_DEFAULT,
                  schedule: str = "batched", pair_capacity: int | None = None, capacity_margin: float = 1.25,
-                 classes=None, class_schedules=None, lds_batch: int = 0):
+                 classes=None, class_schedules=None, lds_batch: int = 0, lds_batch_bwd: int = 0):
         """``classes``: consecutive view ranges [(v0, v1), ...] covering every view, each rendered by
-        its own launches with (tile, sort_bits[, lds_batch]) from ``class_schedules`` (default: one
-        class, the whole batch, with ``tile``, ``sort_bits`` and ``lds_batch``)."""
+        its own launches with (tile, sort_bits[, lds_batch[, lds_batch_bwd]]) from ``class_schedules``
+        (default: one class, the whole batch, with ``tile``, ``sort_bits``, ``lds_batch`` and
+        ``lds_batch_bwd``)."""
         assert schedule in ("plain", "batched", "graph")
         self.dev = P.device
         self.cams = list(cams)
@@ -93,10 +94,10 @@ class FineTuner:
         self.classes = [tuple(c) for c in classes] if classes is not None else [(0, len(self.cams))]
         if [v for c in self.classes for v in range(c[0], c[1])] != list(range(len(self.cams))):
             raise ValueError("classes must be consecutive view ranges covering every view once, in order")
-        self.class_schedules = ([(tuple(x) + (0,))[:3] for x in class_schedules] if class_schedules is not None
-                                else [(tile, sort_bits, lds_batch)] * len(self.classes))
+        self.class_schedules = ([(tuple(x) + (0, 0))[:4] for x in class_schedules] if class_schedules is not None
+                                else [(tile, sort_bits, lds_batch, lds_batch_bwd)] * len(self.classes))
         if len(self.class_schedules) != len(self.classes):
-            raise ValueError("one (tile, sort_bits) per class")
+            raise ValueError("one schedule (tile, sort_bits[, lds_batch[, lds_batch_bwd]]) per class")
         self.view_schedule = [self.class_schedules[c] for c, (a, b) in enumerate(self.classes) for _ in range(a, b)]
         self.schedule = schedule
         self.lr = lr
@@ -122,8 +123,9 @@ class FineTuner:
         """Exact pair count per view from one exact-mode forward (planning only)."""
         counts = []
         for v, cam in enumerate(self.cams):
-            tile, bits, lds = self.view_schedule[v]
-            rp = api.plan_batch([cam], self.scene_offsets, [self.view_scene[v]], tile, bits, 1, "exact", self.dev, lds)
+            tile, bits, lds, lds_bwd = self.view_schedule[v]
+            rp = api.plan_batch([cam], self.scene_offsets, [self.view_scene[v]], tile, bits, 1, "exact", self.dev, lds,
+                                lds_bwd)
             out = api.render_fwd(rp, self.act)
             torch.cuda.synchronize(self.dev)
             counts.append(int(out.status[1].item()))
@@ -141,9 +143,9 @@ class FineTuner:
             groups = [(a, b, *self.class_schedules[c], sum(self.view_caps[a:b]) if capacity is None else capacity,
                        "batched") for c, (a, b) in enumerate(self.classes)]
         self.plans, self.outs = [], []
-        for a, b, tile, bits, lds, cap, mode in groups:
+        for a, b, tile, bits, lds, lds_bwd, cap, mode in groups:
             self.plans.append(api.plan_batch(self.cams[a:b], self.scene_offsets, self.view_scene[a:b], tile, bits, cap,
-                                             mode, self.dev, lds))
+                                             mode, self.dev, lds, lds_bwd))
             pa, pb = int(self.pix_off[a]), int(self.pix_off[b])
             self.outs.append(api.FwdOut(self.image[3 * pa:3 * pb], self.final_T[pa:pb], self.n_contrib[pa:pb],
                                         torch.zeros(4, dtype=torch.int32, device=self.dev)))
@@ -225,8 +227,12 @@ def render_images(P: torch.Tensor, cams, scene_offsets=None, view_scene=None, ti
     return out.image
 
 
-# (tile edge, tile-sort digit width, LDS batch depth of the compositing list walk; 0 = scalar cache)
-TUNE_CANDIDATES = ((16, 8, 0), (8, 8, 0), (32, 8, 0), (16, 4, 0), (16, 4, 32), (16, 4, 64))
+# (tile edge, tile-sort digit width, LDS batch depth of the forward and of the backward compositing
+# list walk; 0 = scalar cache), in order of preference: the tuner keeps the first one within
+# TUNE_MARGIN of the fastest
+TUNE_CANDIDATES = ((16, 8, 0, 0), (16, 4, 0, 0), (8, 8, 0, 0), (32, 8, 0, 0), (16, 8, 32, 0), (16, 8, 64, 0),
+                   (16, 8, 32, 32))
+TUNE_MARGIN = 0.01
 
 
 def _pixel_range(cams, a, b):
@@ -235,12 +241,13 @@ def _pixel_range(cams, a, b):
 
 
 def autotune_classes(P: torch.Tensor, cams, targets: torch.Tensor, scene_offsets=None, view_scene=None,
-                     classes=None, loss: str = "l1", lam: float = 0.2, candidates=TUNE_CANDIDATES, steps: int = 3,
-                     warmup: int = 1) -> dict:
-    """Picks (tile, sort_bits) for each size class of a batch on its own (default classes: the runs
+                     classes=None, loss: str = "l1", lam: float = 0.2, candidates=TUNE_CANDIDATES, steps: int = 5,
+                     warmup: int = 2) -> dict:
+    """Picks a schedule (tile, sort_bits, lds_batch, lds_batch_bwd) for each size class of a batch on its own (default classes: the runs
     of equal-size views): every candidate runs the batched step of that class's views alone (their
     targets, all Gaussians, Adam included) and the fastest is kept.  Returns dict(classes,
-    schedules [(tile, sort_bits)] per class, tables [per-class candidate tables])."""
+    schedules [(tile, sort_bits, lds_batch, lds_batch_bwd)] per class, tables [per-class candidate
+    tables])."""
     classes = size_classes(cams) if classes is None else [tuple(c) for c in classes]
     vs = list(view_scene) if view_scene is not None else [0] * len(cams)
     schedules, tables = [], []
@@ -248,31 +255,37 @@ def autotune_classes(P: torch.Tensor, cams, targets: torch.Tensor, scene_offsets
         pa, pb = _pixel_range(cams, a, b)
         r = autotune(P, cams[a:b], targets[3 * pa:3 * pb], scene_offsets, vs[a:b], loss=loss, lam=lam,
                      candidates=candidates, steps=steps, warmup=warmup)
-        schedules.append((r["tile"], r["sort_bits"], r["lds_batch"]))
+        schedules.append((r["tile"], r["sort_bits"], r["lds_batch"], r["lds_batch_bwd"]))
         tables.append(r["table"])
     return dict(classes=classes, schedules=schedules, tables=tables)
 
 
 def autotune(P: torch.Tensor, cams, targets: torch.Tensor, scene_offsets=None, view_scene=None, loss: str = "l1",
-             lam: float = 0.2, candidates=TUNE_CANDIDATES, steps: int = 3, warmup: int = 1) -> dict:
+             lam: float = 0.2, candidates=TUNE_CANDIDATES, steps: int = 5, warmup: int = 2,
+             margin: float = TUNE_MARGIN) -> dict:
     """Chooses the tile edge, the radix digit width of the tile sort and the LDS batch depth of the
     compositing list walk for a batch.
 
-    Each candidate (tile, sort_bits, lds_batch) gets its own plan (exact pair counts, capacity
+    Each candidate (tile, sort_bits, lds_batch, lds_batch_bwd) gets its own plan (exact pair counts, capacity
     margin) and runs ``warmup`` + ``steps`` eager batched iterations on a copy of P (FineTuner
-    clones it), timed with a device synchronisation on both sides.  Returns the fastest as
-    dict(tile, sort_bits, lds_batch, ms) plus the table of every candidate's ms per step.
+    clones it), timed with a device synchronisation on both sides.  The pick is the first candidate,
+    in the given order of preference, whose time is within ``margin`` (a fraction) of the fastest,
+    so that differences at the level of timing noise do not change the schedule from run to run.
+    Returns it as dict(tile, sort_bits, lds_batch, lds_batch_bwd, ms) plus the table of every
+    candidate's ms per step.
     """
     table = []
     for cand in candidates:
-        tile, bits, lds = (tuple(cand) + (0,))[:3]
+        tile, bits, lds, lds_bwd = (tuple(cand) + (0, 0))[:4]
         ft = FineTuner(P, cams, targets, scene_offsets, view_scene, tile=tile, sort_bits=bits, lds_batch=lds,
-                       loss=loss, lam=lam, schedule="batched")
-        table.append(dict(tile=tile, sort_bits=bits, lds_batch=lds, ms=_time_steps(ft, steps, warmup)))
+                       lds_batch_bwd=lds_bwd, loss=loss, lam=lam, schedule="batched")
+        table.append(dict(tile=tile, sort_bits=bits, lds_batch=lds, lds_batch_bwd=lds_bwd,
+                          ms=_time_steps(ft, steps, warmup)))
         del ft
-    best = min(table, key=lambda d: d["ms"])
-    return dict(tile=best["tile"], sort_bits=best["sort_bits"], lds_batch=best["lds_batch"], ms=best["ms"],
-                table=table)
+    fastest = min(d["ms"] for d in table)
+    best = next(d for d in table if d["ms"] <= fastest * (1.0 + margin))
+    return dict(tile=best["tile"], sort_bits=best["sort_bits"], lds_batch=best["lds_batch"],
+                lds_batch_bwd=best["lds_batch_bwd"], ms=best["ms"], table=table)
 
 
 def _time_steps(ft: "FineTuner", steps: int, warmup: int) -> float:
@@ -290,16 +303,18 @@ def _time_steps(ft: "FineTuner", steps: int, warmup: int) -> float:
 
 
 def autotune_schedule(P: torch.Tensor, cams, targets: torch.Tensor, scene_offsets=None, view_scene=None,
-                      loss: str = "l1", lam: float = 0.2, candidates=TUNE_CANDIDATES, steps: int = 3,
-                      warmup: int = 1) -> dict:
-    """The step schedule of a batch: the best single (tile, sort_bits) for the whole batch and, when
+                      loss: str = "l1", lam: float = 0.2, candidates=TUNE_CANDIDATES, steps: int = 5,
+                      warmup: int = 2) -> dict:
+    """The step schedule of a batch: the best single schedule for the whole batch and, when
     the batch holds views of several sizes, the best per size class (autotune_classes); the per-class
-    schedule (one launch per class and phase) is taken when its whole step is faster.  Returns the
-    FineTuner keywords (tile, sort_bits, classes, class_schedules) plus the measurements."""
+    schedule (one launch per class and phase) is taken when its whole step is faster by more than
+    TUNE_MARGIN.  Returns the FineTuner keywords (tile, sort_bits, lds_batch, lds_batch_bwd, classes,
+    class_schedules) plus the measurements (single_ms: the single schedule's step)."""
     whole = autotune(P, cams, targets, scene_offsets, view_scene, loss=loss, lam=lam, candidates=candidates,
                      steps=steps, warmup=warmup)
-    out = dict(tile=whole["tile"], sort_bits=whole["sort_bits"], lds_batch=whole["lds_batch"], classes=None,
-               class_schedules=None, ms=whole["ms"], table=whole["table"])
+    out = dict(tile=whole["tile"], sort_bits=whole["sort_bits"], lds_batch=whole["lds_batch"],
+               lds_batch_bwd=whole["lds_batch_bwd"], classes=None,
+               class_schedules=None, ms=whole["ms"], single_ms=whole["ms"], table=whole["table"])
     classes = size_classes(cams)
     if len(classes) > 1:
         ct = autotune_classes(P, cams, targets, scene_offsets, view_scene, classes, loss=loss, lam=lam,
@@ -309,6 +324,6 @@ def autotune_schedule(P: torch.Tensor, cams, targets: torch.Tensor, scene_offset
         ms = _time_steps(ft, steps, warmup)
         del ft
         out.update(class_tables=ct["tables"], per_class=dict(classes=classes, schedules=ct["schedules"], ms=ms))
-        if ms < whole["ms"]:
+        if ms < whole["ms"] * (1.0 - TUNE_MARGIN):
             out.update(classes=classes, class_schedules=ct["schedules"], ms=ms)
     return out

@@ -89,27 +89,28 @@ def test_fullsize_adaptive_selection(h_case):
 
 # every schedule the autotuner chooses from (tile edge, tile-sort digit width) at the benchmark's
 # size, and the autotuner's usual pick at the large batch
-SCHEDULES = [("1M-8views", 16, 4, 0), ("1M-8views", 16, 8, 0), ("1M-8views", 8, 8, 0), ("1M-8views", 32, 8, 0),
-             ("1M-8views", 16, 4, 32), ("1M-8views", 16, 4, 64), ("2M-16views", 16, 4, 0)]
+SCHEDULES = [("1M-8views", 16, 8, 0, 0), ("1M-8views", 16, 4, 0, 0), ("1M-8views", 8, 8, 0, 0),
+             ("1M-8views", 32, 8, 0, 0), ("1M-8views", 16, 8, 32, 0), ("1M-8views", 16, 8, 64, 0),
+             ("1M-8views", 16, 8, 32, 32), ("2M-16views", 16, 8, 0, 0)]
 
 
-@pytest.mark.parametrize("case,tile,bits,lds", SCHEDULES)
-def test_fullsize_render_sampled_tiles(h_case, case, tile, bits, lds):
+@pytest.mark.parametrize("case,tile,bits,lds,lds_bwd", SCHEDULES)
+def test_fullsize_render_sampled_tiles(h_case, case, tile, bits, lds, lds_bwd):
     api = h_case["api"]
     _, _, gs = h_case["sets"][case]
     cfg = CASES[case]
     cams = vi.orbit_cameras(cfg["views"], W, H)
     P = api.pack_params(gs.means, gs.scales, gs.quats, gs.opacity, gs.rgb, dev())
     N = P.shape[1]
-    say(f"  {case}: {N} Gaussians, {cfg['views']} views {W}x{H}, tile {tile}, {bits}-bit digits, LDS batch {lds}")
+    say(f"  {case}: {N} Gaussians, {cfg['views']} views {W}x{H}, tile {tile}, {bits}-bit digits, LDS batch {lds}/{lds_bwd}")
     rp = api.plan_batch(cams, [0, N], tile=tile, sort_bits=bits, pair_capacity=8_000_000 * cfg["views"],
-                        mode="batched", lds_batch=lds)
+                        mode="batched", lds_batch=lds, lds_batch_bwd=lds_bwd)
     sampled_tile_parity(rp, P, gs, cams, [0] * len(cams), [0, N], tile, cfg["sample"], 10, 33)
 
 
 def test_fullsize_schedules_list_the_tuner_candidates():
     from paper_2601_09417_amd import trainer
-    assert {(t, b, k) for c, t, b, k in SCHEDULES if c == "1M-8views"} == set(trainer.TUNE_CANDIDATES)
+    assert {(t, b, k, kb) for c, t, b, k, kb in SCHEDULES if c == "1M-8views"} == set(trainer.TUNE_CANDIDATES)
 
 
 def test_fullsize_dvr_sampled_pixels(h_case):

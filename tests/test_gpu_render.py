@@ -141,7 +141,7 @@ def test_forward_backward_parity(tile, W, H, lds):
     gs, cams = _scene(600, 3, 2, W, H)
     say(f"fwd/bwd parity tile={tile} {W}x{H} n={gs.n} lds batch {lds}")
     P = to_dev(gs)
-    rp = api.plan_batch(cams, [0, gs.n], tile=tile, pair_capacity=1 << 18, lds_batch=lds)
+    rp = api.plan_batch(cams, [0, gs.n], tile=tile, pair_capacity=1 << 18, lds_batch=lds, lds_batch_bwd=lds)
     out = api.render_fwd(rp, P)
     batch = render.Batch(gs, cams, tile)
     ref = render.render_forward(batch)
