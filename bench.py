@@ -216,8 +216,9 @@ def cpu_baseline_worker(queue, go, workload: str, n_tiles: int, threads: int) ->
 # ----------------------------------------------------------------------------- GPU side
 
 def traffic_from_profiles(kernel_src: str):
-    """HBM bytes per launch of the backward compositing kernel from committed rocprofv3 counter runs,
-    or None when absent or taken on a different kernel source."""
+    """HBM traffic of one launch of the backward compositing kernel from committed rocprofv3 counter
+    runs, as dict(bytes_per_launch, algorithmic_bytes, pairs) of the profiled launch, or None when
+    absent or taken on a different kernel source."""
     path = os.path.join(ROOT, "profiles", "composite_bwd_H_counters.md")
     if not os.path.exists(path):
         return None
@@ -226,7 +227,7 @@ def traffic_from_profiles(kernel_src: str):
         if line.startswith("traffic_json:"):
             d = json.loads(line.split(":", 1)[1])
             if d.get("kernel_sha") == digest:
-                return d.get("bytes_per_launch")
+                return d
     return None
 
 
@@ -686,7 +687,8 @@ def main() -> int:
     kf = gpu["kernels"]["composite_fwd"]
     # the committed counter run covers the 16x16-tile kernel of the workload's own loss only
     traffic = (traffic_from_profiles(os.path.join(ROOT, "paper_2601_09417_amd", "csrc", "raster.hip"))
-               if args.workload == "H" and gpu["tile"] == 16 and gpu["loss_kind"] == wl["loss"] else None)
+               if args.workload == "H" and gpu["tile"] == 16 and gpu["lds_batch_bwd"] == 0
+               and gpu["loss_kind"] == wl["loss"] else None)
     result = {
         "metric": (METRIC if args.workload == "H" else
                    "fine-tune iters/sec (fwd+bwd, " + workload_shape(wl) + ") batched vs plain"),
@@ -728,8 +730,11 @@ def main() -> int:
             "peak": FP32_ALU_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(k["tflops"] / FP32_ALU_PEAK_TFLOPS, 4),
-            "traffic": traffic,
-            "traffic_over_algorithmic": None if traffic is None else round(traffic / k["bytes"], 3),
+            # measured on the profiled launch (its own pair count), not re-measured here
+            "traffic": None if traffic is None else traffic["bytes_per_launch"],
+            "traffic_over_algorithmic": (None if traffic is None else
+                                         round(traffic["bytes_per_launch"] / traffic["algorithmic_bytes"], 3)),
+            "traffic_pairs": None if traffic is None else traffic["pairs"],
             "peak_published_packed": FP32_PUBLISHED_PACKED_TFLOPS,
             "frac_of_published_packed": round(k["tflops"] / FP32_PUBLISHED_PACKED_TFLOPS, 4),
             "hbm": {name: {"algorithmic_bytes": int(d["bytes"]), "ms": round(d["ms"], 4),
