@@ -5,28 +5,32 @@
 // four independent waves, an 8x8 tile one wave with one pixel per lane), each lane owning
 // PPL = 4 pixels of ONE pixel column (rows 64 / TILE apart), so the horizontal offset to a
 // Gaussian's centre is shared by a lane's pixels.  The tile's depth-sorted list is walked by every
-// wave in lockstep: a Gaussian's pair value and its 36-byte record are wave-uniform and go through
-// the scalar data cache into SGPRs (each one list step ahead of its use) -- no LDS staging, no
-// barriers, no per-lane copies of a uniform value, and the per-Gaussian load cost is amortised
-// over 256 pixels.  A vector load of a uniform address would still move 64 lanes' copies through
-// the texture address and data units, which the list walk would saturate.
+// wave in lockstep, with each Gaussian's 36-byte record wave-uniform, in one of two ways chosen by
+// the plan: through the scalar data cache into SGPRs, each record one list step ahead of its use
+// (no LDS, no barriers, no per-lane copies of a uniform value); or staged in LDS, where the first
+// LDSB lanes each gather one list entry's record with vector loads into a double-buffered batch
+// that the wave then reads entry by entry.  Either way the per-Gaussian load cost is amortised over
+// 256 pixels; a vector load of a uniform address instead would move 64 lanes' copies through the
+// texture address and data units, which the list walk would saturate.
 //
 // The record holds the exponent in base 2 with the log-opacity folded in:
 //   e2(d) = hA dx^2 + hB dx dy + hC dy^2 + log2(o) = log2(o) + power(d) log2(e),
 // so alpha = min(0.99, 2^e2) costs one exponential and no multiply by the opacity.  Projection
 // keeps only Gaussians with a positive-definite conic, for which power <= 0 at every pixel, so a
 // "skip when power > 0" guard could only fire on float32 rounding near the centre and is left out.
+// The forward keeps each pixel's transmittance in place; a pixel that stops records its list
+// position as n_contrib and parks at a far row, where alpha underflows to zero.
 //
 // The backward walks the list in reverse from the wave's largest n_contrib, recomputes each
-// pixel's transmittance from final_T by division and keeps the normalised colour behind the
-// current Gaussian in one running value per channel.  The geometric gradient is accumulated as
-// three per-lane moments of dL/dpower (sum, first and second moment in dy); the lane's column
-// offset dx turns them into the five sums the 2D parameters need.  Nine per-wave sums are then
-// formed with a DPP reduce-scatter inside 16-lane rows (27 VALU operations, one value per lane)
-// plus two cross-row lane swaps, and nine lanes issue one float atomic each into the item's
-// 64-byte accumulator row (one cache segment per pair instead of nine lines) -- only when some
-// pixel contributed.  The atomics add those raw moments; the projection backward turns them into
-// mean/conic/opacity gradients with the item's conic, since that map is linear.
+// pixel's transmittance from final_T by division and carries one scalar per pixel for the colour
+// behind the current Gaussian (see bwd_step).  The geometric gradient is accumulated as three
+// per-lane moments of dL/dpower (sum, first and second moment in dy); the lane's column offset dx
+// turns them into the five sums the 2D parameters need.  Nine per-wave sums are then formed by
+// cross-row lane swaps and a DPP reduction inside 16-lane rows (one value per lane), and nine lanes
+// issue one float atomic each into the item's 64-byte accumulator row (one cache segment per pair
+// instead of nine lines) -- only when some pixel contributed.  The atomics add those raw moments;
+// the projection backward turns them into mean/conic/opacity gradients with the item's conic,
+// since that map is linear.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
