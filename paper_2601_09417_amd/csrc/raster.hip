@@ -309,7 +309,7 @@ __device__ __forceinline__ uint32_t fwd_step(const Rec& r, int pos, float fx, fl
 template <int B>
 struct LdsBatch {
   float4 a[2][B], b[2][B];
-  float blue[2][B];
+  float4 c[2][B];   // c.x: blue (a 16-byte slot, so that one address serves all three reads)
 };
 
 template <int B>
@@ -318,7 +318,7 @@ __device__ __forceinline__ void lds_put(LdsBatch<B>& L, int buf, int lane, const
   if (lane < B) {
     L.a[buf][lane] = ra;
     L.b[buf][lane] = rb;
-    L.blue[buf][lane] = bl;
+    L.c[buf][lane].x = bl;
   }
 }
 
@@ -334,9 +334,48 @@ __device__ __forceinline__ Rec lds_get(const LdsBatch<B>& L, int buf, int b) {
   r.lo = c.y;
   r.r = c.z;
   r.g = c.w;
-  r.b = L.blue[buf][b];
+  r.b = L.c[buf][b].x;
   return r;
 }
+
+// Lane-group marks of an LDS batch, one 4-bit nibble per list step, kept in wave-uniform 64-bit
+// words (scalar registers, so collecting them costs the vector pipes nothing).  A step ORs its
+// marks into the current word at bits 4 (b mod 16); every 16 steps the word is pushed onto a short
+// queue of filled words (most recent first), so the per-step cost does not grow with the batch and
+// no word is ever selected by a computed index (which would put them in scratch memory).
+template <int B>
+struct MarkWords {
+  static_assert(B == 32 || B == 64, "16 list steps per word, two or four words");
+  uint64_t cur = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+  int filled = 0;
+  __device__ __forceinline__ void set(int b, uint32_t g) {
+    cur |= static_cast<uint64_t>(g) << (4 * (b & 15));
+    if ((b & 15) == 15) push();
+  }
+  // after the batch's n steps: pushes a partly filled last word
+  __device__ __forceinline__ void finish(int n) {
+    if (n & 15) push();
+  }
+  // The marks of step `lane` (lane < B).
+  __device__ __forceinline__ uint32_t of_lane(int lane) const {
+    const int q = filled - 1 - (lane >> 4);   // queue slot of the lane's word
+    uint64_t x = q == 0 ? w0 : w1;
+    if (B == 64) x = q == 2 ? w2 : (q == 3 ? w3 : x);
+    return static_cast<uint32_t>(x >> (4 * (lane & 15))) & 15u;
+  }
+
+ private:
+  __device__ __forceinline__ void push() {
+    if (B == 64) {
+      w3 = w2;
+      w2 = w1;
+    }
+    w1 = w0;
+    w0 = cur;
+    cur = 0;
+    ++filled;
+  }
+};
 
 // Lane t's entry of the batch at list positions pos(t) (per-lane vector loads): its pair value and
 // record (the record of a clamped item when the position lies outside [lo, hi], never read).
@@ -383,7 +422,8 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
     cr[k] = cg[k] = cb[k] = 0.0f;
   }
   const uint2 rg = ranges[tile];
-  const int start = static_cast<int>(rg.x), end = static_cast<int>(rg.y);
+  // the range is the same for every lane: keep it (and the list walk's counters) in scalar registers
+  const int start = static_cast<int>(uniform(rg.x)), end = static_cast<int>(uniform(rg.y));
 #pragma unroll
   for (int k = 0; k < PPL; ++k) nvis[k] = end - start;
   uint32_t n_eval = 0, n_used = 0;
@@ -399,8 +439,8 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
     // Double-buffered batches: the next batch's entries are loaded into registers (one per lane)
     // while the current one is walked, then written to the other LDS buffer.  A single wave uses
     // the LDS, whose operations it issues in order, so no barrier separates the writes from the
-    // reads.  The marks of a batch collect in one register (lane b: step b) and are stored with
-    // one coalesced store.
+    // reads.  The marks of a batch collect in uniform words and go out with one coalesced store
+    // (lane b: step b).
     __shared__ LdsBatch<LDSB> L;
     uint32_t pv, pvc;
     float4 ra, rb;
@@ -412,14 +452,16 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
       if (!any_live(fy)) break;
       const int nb = base + LDSB;
       lds_fetch(pair_item, crec, blue, imax, nb + lane, lane < LDSB && nb + lane < end, pv, ra, rb, bl);
-      const int n = min(LDSB, end - base);
-      uint32_t marks = 0;
+      // batch length and first list position, kept scalar so that the step loop runs on the SALU
+      const int n = static_cast<int>(uniform(static_cast<uint32_t>(min(LDSB, end - base))));
+      const int pos0 = static_cast<int>(uniform(static_cast<uint32_t>(base - start)));
+      MarkWords<LDSB> mw;
       for (int b = 0; b < n; ++b) {
         const Rec r = lds_get<LDSB>(L, buf, b);
-        const uint32_t g = fwd_step<PPL, STATS>(r, base - start + b, fx, fy, T, cr, cg, cb, nvis, n_eval, n_used);
-        marks = lane == b ? g : marks;
+        mw.set(b, fwd_step<PPL, STATS>(r, pos0 + b, fx, fy, T, cr, cg, cb, nvis, n_eval, n_used));
       }
-      if (lane < n) pair_marked[base + lane] = (pvc & kItemMask) | (marks << kItemBits);
+      mw.finish(n);
+      if (lane < n) pair_marked[base + lane] = (pvc & kItemMask) | (mw.of_lane(lane) << kItemBits);
       buf ^= 1;
       pvc = pv;
       lds_put<LDSB>(L, buf, lane, ra, rb, bl);
@@ -591,7 +633,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) maxn = max(maxn, __shfl_xor(maxn, d, 64));
   maxn = __builtin_amdgcn_readfirstlane(maxn);
-  const int start = static_cast<int>(ranges[tile].x);
+  const int start = static_cast<int>(uniform(ranges[tile].x));
   // Lanes l, l + 16, l + 32, l + 48 share a pixel column when the tile is at most 16 wide.
   constexpr bool kCols = 16 % TILE == 0;
   const int out_k = kCols ? col_index(lane) : rs_index(lane & 15);
