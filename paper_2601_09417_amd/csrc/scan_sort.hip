@@ -19,7 +19,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kItems = 16;
 constexpr int kChunk = kThreads * kItems;  // elements per block
-constexpr int kWaves = kThreads / 64;
 static_assert(kThreads == 256, "one thread per 8-bit digit in the scatter's LDS bookkeeping");
 
 __device__ __forceinline__ bool aligned16(const void* p) {
@@ -175,6 +174,31 @@ constexpr uint32_t kFlagInc = 2u << 30;   // status word: the count in this tile
 constexpr uint32_t kCountMask = kFlagAgg - 1u;
 constexpr int kFallbackRounds = 128;  // look-back rounds that find a tile unpublished before counting it directly
 constexpr int kLookback = 8;          // earlier tiles' status words read per look-back round
+// Threads of a one-sweep pass block (kItems keys each, so 8192-key tiles): at workload H the pass
+// time per step was 0.435 ms with 4096-key tiles, 0.404 ms with 8192 and 0.461 ms with 16384 (one
+// block per CU); fewer tiles shorten the look-back chain and lengthen each digit's output run.
+constexpr int kSweepThreads = 512;
+
+// Exclusive scan of one value per thread across a block of NT threads (NT a multiple of 64);
+// block total in *total.  Every thread of the block must call it (it synchronises).
+template <int NT, class T>
+__device__ __forceinline__ T block_excl_scan_n(T v, T* total) {
+  __shared__ T s_wave[NT / 64];
+  const int w = threadIdx.x >> 6;
+  T incl = wave_incl_scan(v);
+  if (lane_id() == 63) s_wave[w] = incl;
+  __syncthreads();
+  T base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    T x = s_wave[i];
+    if (i < w) base += x;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + incl - v;
+}
 
 __device__ __forceinline__ uint32_t status_load(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -183,13 +207,13 @@ __device__ __forceinline__ void status_store(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Keys of digit d in the full 4096-key tile j (the look-back's fallback for a tile whose block has
+// Keys of digit d in the full tile j of CH keys (the look-back's fallback for a tile whose block has
 // not published its counts).
-template <class K>
+template <int CH, class K>
 __device__ uint32_t count_digit(const K* __restrict__ kin, int64_t j, int shift, uint32_t mask, uint32_t d) {
-  const K* src = kin + j * kChunk;
+  const K* src = kin + j * CH;
   uint32_t c = 0;
-  for (int i = 0; i < kChunk; ++i) c += (static_cast<uint32_t>(src[i] >> shift) & mask) == d ? 1u : 0u;
+  for (int i = 0; i < CH; ++i) c += (static_cast<uint32_t>(src[i] >> shift) & mask) == d ? 1u : 0u;
   return c;
 }
 
@@ -270,32 +294,34 @@ __global__ __launch_bounds__(kTopThreads) void k_radix_totals(const uint32_t* __
   }
 }
 
-// One stable pass over 4096-key tiles.  Wave w of a tile owns keys [1024 w, 1024 w + 1024) and
-// ranks them in 16 rounds of 64 against its own LDS digit counters: a lane's rank among the
+// One stable pass over tiles of NT x 16 keys.  Wave w of a tile owns keys [1024 w, 1024 w + 1024)
+// and ranks them in 16 rounds of 64 against its own LDS digit counters: a lane's rank among the
 // round's equal digits comes from ballots, and the wave's LDS operations complete in issue order,
 // so a round reads its digits' counters before its leaders advance them with no barrier in
 // between.  The per-wave counts give the tile's digit counts (published for the later tiles) and
 // per-wave bases; the look-back gives the keys of each digit in the earlier tiles; the tile is
 // partitioned in LDS and written out in digit order, so consecutive lanes store to consecutive
 // addresses of a digit's output run.
-template <class K>
-__global__ __launch_bounds__(kThreads) void k_radix_onesweep(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+template <int NT, class K>
+__global__ __launch_bounds__(NT) void k_radix_onesweep(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                              K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                              const uint32_t* __restrict__ totals,
                                                              uint32_t* __restrict__ status, int64_t n_max,
                                                              const uint32_t* n_dev, int shift, int bits) {
-  constexpr int kPerWave = kChunk / kWaves;
-  __shared__ K s_key[kChunk];
-  __shared__ uint32_t s_val[kChunk];
-  __shared__ uint32_t s_cnt[kWaves][256];   // per-wave digit counts, then per-wave digit bases
+  constexpr int CH = NT * kItems;          // keys per tile
+  constexpr int NW = NT / 64;
+  constexpr int kPerWave = CH / NW;
+  __shared__ K s_key[CH];
+  __shared__ uint32_t s_val[CH];
+  __shared__ uint32_t s_cnt[NW][256];       // per-wave digit counts, then per-wave digit bases
   __shared__ uint32_t s_start[256];         // start of each digit in the partitioned tile
   __shared__ uint32_t s_glob[256];          // global start of this tile's run of each digit
   const int64_t n = active_count(n_max, n_dev);
   const int64_t tile = blockIdx.x;
-  const int64_t base = tile * kChunk;
+  const int64_t base = tile * CH;
   if (base >= n) return;  // uniform per block; no tile waits on a later one
-  for (int x = threadIdx.x; x < kWaves * 256; x += kThreads) (&s_cnt[0][0])[x] = 0;
-  const int count = static_cast<int>(min(static_cast<int64_t>(kChunk), n - base));
+  for (int x = threadIdx.x; x < NW * 256; x += NT) (&s_cnt[0][0])[x] = 0;
+  const int count = static_cast<int>(min(static_cast<int64_t>(CH), n - base));
   const int radix = 1 << bits;
   const uint32_t mask = static_cast<uint32_t>(radix - 1);
   const int w = threadIdx.x >> 6;
@@ -327,24 +353,27 @@ __global__ __launch_bounds__(kThreads) void k_radix_onesweep(const K* __restrict
   }
   __syncthreads();
   const bool has = static_cast<int>(threadIdx.x) < radix;
+  const bool dig = threadIdx.x < 256;   // the threads that own a digit's bookkeeping
   {
-    uint32_t c[kWaves], t = 0;
+    uint32_t c[NW], t = 0;
 #pragma unroll
-    for (int ww = 0; ww < kWaves; ++ww) {
-      c[ww] = s_cnt[ww][threadIdx.x];
+    for (int ww = 0; ww < NW; ++ww) {
+      c[ww] = dig ? s_cnt[ww][threadIdx.x] : 0u;
       t += c[ww];
     }
     uint32_t tot;
-    uint32_t run = block_excl_scan(t, &tot);
-    s_start[threadIdx.x] = run;
+    uint32_t run = block_excl_scan_n<NT>(t, &tot);
+    if (dig) {
+      s_start[threadIdx.x] = run;
 #pragma unroll
-    for (int ww = 0; ww < kWaves; ++ww) {
-      s_cnt[ww][threadIdx.x] = run;
-      run += c[ww];
+      for (int ww = 0; ww < NW; ++ww) {
+        s_cnt[ww][threadIdx.x] = run;
+        run += c[ww];
+      }
     }
     // keys of lower digits in the whole input: the exclusive scan of the digit totals
     uint32_t all;
-    const uint32_t below = block_excl_scan(has ? totals[threadIdx.x] : 0u, &all);
+    const uint32_t below = block_excl_scan_n<NT>(has ? totals[threadIdx.x] : 0u, &all);
     if (has) {
       uint32_t* mine = status + tile * radix + threadIdx.x;
       uint32_t excl = 0;
@@ -380,7 +409,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_onesweep(const K* __restrict
           j -= k;
           if (k < kLookback) {
             if (++rounds > kFallbackRounds) {
-              excl += count_digit(kin, j, shift, mask, threadIdx.x);   // tile j < tile is full
+              excl += count_digit<CH>(kin, j, shift, mask, threadIdx.x);   // tile j < tile is full
               --j;
               rounds = 0;
             } else {
@@ -406,7 +435,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_onesweep(const K* __restrict
   // write out in digit order
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    const int lp = r * kThreads + threadIdx.x;
+    const int lp = r * NT + threadIdx.x;
     if (lp < count) {
       const K key = s_key[lp];
       const uint32_t d = static_cast<uint32_t>(key >> shift) & mask;
@@ -522,8 +551,9 @@ vbm_status radix_sort_pairs(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t n_
   for (int p = 0; p < passes; ++p) {
     const int shift = p * digit_bits;
     const int bits = (end_bit - shift) < digit_bits ? (end_bit - shift) : digit_bits;
-    hipLaunchKernelGGL(k_radix_onesweep<K>, dim3(L.nb), dim3(kThreads), 0, s, kin, vin, kout, vout, tot + p * 256,
-                       status + p * pass_words, n_max, n_dev, shift, bits);
+    hipLaunchKernelGGL((k_radix_onesweep<kSweepThreads, K>), dim3(ceil_div(n_max, kSweepThreads * kItems)),
+                       dim3(kSweepThreads), 0, s, kin, vin, kout, vout, tot + p * 256, status + p * pass_words, n_max,
+                       n_dev, shift, bits);
     VBM_LAUNCH_CHECK("radix_onesweep");
     K* tk = kin;
     kin = kout;
