@@ -425,9 +425,12 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
     __syncthreads();
     const uint32_t n_q = s_n;
     for (uint32_t d = threadIdx.x >> 6; d < n_q; d += 4) {
-      const int64_t q = base + s_q[d];
-      const uint32_t item = vals[q];
-      const DevView& v = views[view_of_item(views, n_views, item)];
+      // Everything about a queued rectangle is the same for the whole wave: with its position and
+      // item in scalar registers its bin entry, view and ballot words come through the scalar cache
+      // instead of 64 lanes' copies through the texture units, which this loop would saturate.
+      const int64_t q = base + __builtin_amdgcn_readfirstlane(s_q[d]);
+      const uint32_t item = __builtin_amdgcn_readfirstlane(vals[q]);
+      const DevView& v = views[__builtin_amdgcn_readfirstlane(view_of_item(views, n_views, item))];
       const uint4 b = sorted_bin[q];
       const uint32_t x0 = b.x & 0xFFFFu, x1 = b.x >> 16, y0 = b.y & 0xFFFFu, y1 = b.y >> 16;
       const uint32_t w = x1 - x0, area = w * (y1 - y0);
