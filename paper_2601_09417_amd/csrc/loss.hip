@@ -113,19 +113,26 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ x, const f
 
 // Loads the (TY + 10) x (TX + 10) halo of one channel into LDS: wave w takes halo rows w, w + 4,
 // ..., a lane per column; every load is issued before the first store so their latencies overlap.
+// The loads are range-checked buffer loads over the channel plane: a lane outside the image (or
+// the halo) asks for an offset past the plane and reads 0, so no lane needs its own branch.
 template <int NF>
 __device__ __forceinline__ void load_halo(const float* const (&src)[NF], int W, int H, int ox, int oy,
                                           float (*dst)[EY][EX + 1]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int gx = ox + lane;
+  const int plane_bytes = W * H * 4;   // the plan bounds a view to 16384^2 pixels: below 2^31
+  __amdgpu_buffer_rsrc_t rs[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+    rs[f] = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(src[f]), (short)0, plane_bytes, 0x00020000);
   float v[NF][kRowLoads];
 #pragma unroll
   for (int k = 0; k < kRowLoads; ++k) {
     const int r = w + 4 * k, gy = oy + r;
     const bool in = lane < EX && r < EY && gx >= 0 && gx < W && gy >= 0 && gy < H;
-    const int64_t off = static_cast<int64_t>(gy) * W + gx;
+    const int off = in ? 4 * (gy * W + gx) : plane_bytes;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) v[f][k] = in ? src[f][off] : 0.0f;
+    for (int f = 0; f < NF; ++f) v[f][k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs[f], off, 0, 0));
   }
 #pragma unroll
   for (int k = 0; k < kRowLoads; ++k) {
@@ -226,6 +233,11 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
   }
   __syncthreads();
   const int gx = bx * TX + col;
+  // the three partial maps of this channel plane, stored through range-checked buffer stores
+  const int plane_bytes = W * H * 4;
+  const __amdgpu_buffer_rsrc_t r1 = __builtin_amdgcn_make_buffer_rsrc(p1 + chan, (short)0, plane_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t r2 = __builtin_amdgcn_make_buffer_rsrc(p2 + chan, (short)0, plane_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t r3 = __builtin_amdgcn_make_buffer_rsrc(p3 + chan, (short)0, plane_bytes, 0x00020000);
   float m[RPT][4];
 #pragma unroll
   for (int o = 0; o < RPT; ++o)
@@ -254,10 +266,11 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
       const float iA1 = __builtin_amdgcn_rcpf(A1), iA2 = __builtin_amdgcn_rcpf(A2);
       const float iB1 = __builtin_amdgcn_rcpf(B1), iB2 = __builtin_amdgcn_rcpf(B2);
       const float sv = (A1 * A2) * (iB1 * iB2);
-      const int64_t pix = chan + static_cast<int64_t>(gy) * W + gx;
-      p1[pix] = 2.0f * sv * (my * (iA1 - iA2) + mx * (iB2 - iB1));
-      p2[pix] = -sv * iB2;
-      p3[pix] = 2.0f * sv * iA2;
+      const int off = 4 * (gy * W + gx);
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, 2.0f * sv * (my * (iA1 - iA2) + mx * (iB2 - iB1))),
+                                            r1, off, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, -sv * iB2), r2, off, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, 2.0f * sv * iA2), r3, off, 0, 0);
       sval += sv;
     }
   }
@@ -356,15 +369,24 @@ __global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ x, 
     }
   }
   if (gx >= W) return;
+  const int plane_bytes = W * H * 4;
+  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(x + chan), (short)0,
+                                                                      plane_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(y + chan), (short)0,
+                                                                      plane_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(grad + chan, (short)0, plane_bytes, 0x00020000);
 #pragma unroll
   for (int o = 0; o < RPT; ++o) {
     const int gy = by * TY + r0 + o;
     if (gy >= H) continue;
-    const int64_t pix = chan + static_cast<int64_t>(gy) * W + gx;
-    const float xv = x[pix], yv = y[pix];
+    const int off = 4 * (gy * W + gx);
+    const float xv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, off, 0, 0));
+    const float yv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ry, off, 0, 0));
     const float d = xv - yv;
     const float sg = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
-    grad[pix] = w_l1 * sg - w_ssim * (b[o][0] + 2.0f * xv * b[o][1] + yv * b[o][2]);
+    __builtin_amdgcn_raw_buffer_store_b32(
+        __builtin_bit_cast(uint32_t, w_l1 * sg - w_ssim * (b[o][0] + 2.0f * xv * b[o][1] + yv * b[o][2])), rg, off, 0,
+        0);
   }
 }
 
