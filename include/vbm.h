@@ -274,9 +274,13 @@ typedef struct {
                                   * group k (pixel rows k*64/tile .. of the tile) of the pair, which
                                   * vbm_render_bwd reads */
 #define VBM_REGION_RANGES 8      /* uint32 [n_tiles][2]: [start, end) of each tile's list */
-#define VBM_REGION_GRAD2D 9      /* float32 [n_items][16]: dmean2d.xy, dconic.abc, dopacity, drgb in
-                                  * columns 0..8 after vbm_render_bwd (rows of items never binned
-                                  * stay 0; columns 9..15 are padding) */
+#define VBM_REGION_GRAD2D 9      /* float32 [n_items][16] after vbm_render_bwd: columns 0..5 hold the
+                                  * sums over the item's pixels of dL/dpower times dx, dy, dx^2,
+                                  * dx dy, dy^2 and 1 (d = mean2d - pixel centre), columns 6..8
+                                  * drgb; with the item's conic (A, B, C) and opacity o the 2D
+                                  * gradients are dmean2d = -(A m0 + B m1, B m0 + C m1), dconic =
+                                  * (-m2/2, -m3, -m4/2), dopacity = m5 / o.  Rows of items never
+                                  * binned stay 0; columns 9..15 are padding */
 #define VBM_REGION_ITEM_COEF 19  /* float32 [n_items][8]: compositing record mean2d.xy, -A/2 log2e,
                                   * -B log2e, -C/2 log2e, log2(opacity), r, g (conic A, B, C) */
 

@@ -629,7 +629,6 @@ __device__ __forceinline__ void project_bwd_one(const DevView& v, const float m[
 // the 2D gradients linear in them:
 //   dmean.x = -(A m0 + B m1), dmean.y = -(B m0 + C m1), dA = -m2 / 2, dB = -m3, dC = -m4 / 2,
 //   dopacity = m5 / o.
-// They are written back in place, so the region holds the 2D gradients afterwards.
 __device__ __forceinline__ void moments_to_grad2d(const float4 ra, const float4 rb, float g2[9]) {
   const float A = ra.z, B = ra.w, Cc = rb.x, o = rb.y;
   const float m0 = g2[0], m1 = g2[1];
@@ -641,45 +640,101 @@ __device__ __forceinline__ void moments_to_grad2d(const float4 ra, const float4 
   g2[5] = g2[5] / o;
 }
 
+// Adds one view's contribution of a Gaussian: the item's raw moments (accumulator row, nine
+// columns) turned into 2D gradients with its record, then the chain rule to the 3D parameters.
+__device__ __forceinline__ void project_bwd_view(const DevView& v, const float m[3], const float sc3[3],
+                                                 const float q[4], float4 q0, float4 q1, float4 q2, float4 ra,
+                                                 float4 rb, float am[3], float as[3], float aq[4], float& ao,
+                                                 float ac[3]) {
+  float g2[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x};
+  moments_to_grad2d(ra, rb, g2);
+  ao += g2[5];
+  ac[0] += g2[6];
+  ac[1] += g2[7];
+  ac[2] += g2[8];
+  if (g2[0] == 0.0f && g2[1] == 0.0f && g2[2] == 0.0f && g2[3] == 0.0f && g2[4] == 0.0f) return;
+  float dm[3], ds[3], dq[4];
+  project_bwd_one(v, m, sc3, q, g2, dm, ds, dq);
+  for (int k = 0; k < 3; ++k) {
+    am[k] += dm[k];
+    as[k] += ds[k];
+  }
+  for (int k = 0; k < 4; ++k) aq[k] += dq[k];
+}
+
+// One thread per Gaussian, its views in order (deterministic).  When a wave's 64 Gaussians all
+// belong to one scene, their items in a view are 64 consecutive accumulator rows (4 KB) and
+// records (2 KB): the wave reads them as coalesced 16-byte vectors and hands each lane its own row
+// through LDS, instead of 64 strided row reads, which keep the texture units busy far longer
+// than the bytes need.  A wave that straddles a scene boundary or the end reads per lane.
 __global__ __launch_bounds__(256) void k_project_bwd(const DevView* __restrict__ views, int n_views,
                                                      const DevScene* __restrict__ scenes, int n_scenes,
                                                      vbm_gaussians_c g, float* __restrict__ grad2d,
                                                      const float4* __restrict__ rec, int64_t n_items,
                                                      const uint32_t* __restrict__ ntiles, vbm_gaussians grads,
                                                      int accumulate, int64_t n_total) {
+  constexpr int kRowPitch = 5, kRecPitch = 3;   // float4 per LDS row (padded: spreads the banks)
+  __shared__ float4 s_row[4][64 * kRowPitch];
+  __shared__ float4 s_rec[4][64 * kRecPitch];
   const int64_t gi = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (gi >= n_total) return;
+  const int lane = static_cast<int>(threadIdx.x) & 63, wv = static_cast<int>(threadIdx.x) >> 6;
+  const bool valid = gi < n_total;
   int sc = 0;
   for (int s = 1; s < n_scenes; ++s)
     if (scenes[s].gauss_offset <= gi) sc = s;
+  const int sc0 = __builtin_amdgcn_readfirstlane(sc);
+  const bool uniform_wave = __ballot(valid && sc == sc0) == ~0ull;
+  if (!valid) return;
   const int64_t S = g.stride;
   const float m[3] = {g.means[gi], g.means[S + gi], g.means[2 * S + gi]};
   const float sc3[3] = {g.scales[gi], g.scales[S + gi], g.scales[2 * S + gi]};
   const float q[4] = {g.quats[gi], g.quats[S + gi], g.quats[2 * S + gi], g.quats[3 * S + gi]};
   float am[3] = {0, 0, 0}, as[3] = {0, 0, 0}, aq[4] = {0, 0, 0, 0}, ao = 0.0f, ac[3] = {0, 0, 0};
-  for (int vi = 0; vi < n_views; ++vi) {
-    const DevView& v = views[vi];
-    if (v.scene != sc) continue;
-    const int64_t item = v.item_offset + (gi - v.gauss_offset);
-    if (ntiles[item] == 0) continue;
-    float4* row = reinterpret_cast<float4*>(grad2d + 16 * item);
-    const float4 q0 = row[0], q1 = row[1], q2 = row[2];
-    float g2[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x};
-    moments_to_grad2d(rec[2 * item], rec[2 * item + 1], g2);
-    row[0] = make_float4(g2[0], g2[1], g2[2], g2[3]);
-    row[1] = make_float4(g2[4], g2[5], g2[6], g2[7]);
-    ao += g2[5];
-    ac[0] += g2[6];
-    ac[1] += g2[7];
-    ac[2] += g2[8];
-    if (g2[0] == 0.0f && g2[1] == 0.0f && g2[2] == 0.0f && g2[3] == 0.0f && g2[4] == 0.0f) continue;
-    float dm[3], ds[3], dq[4];
-    project_bwd_one(v, m, sc3, q, g2, dm, ds, dq);
-    for (int k = 0; k < 3; ++k) {
-      am[k] += dm[k];
-      as[k] += ds[k];
+  if (uniform_wave) {
+    const int64_t g0 = gi - lane;
+    for (int vi = 0; vi < n_views; ++vi) {
+      const DevView& v = views[vi];
+      if (v.scene != sc0) continue;   // uniform
+      const int64_t item0 = v.item_offset + (g0 - v.gauss_offset);
+      const float4* rsrc = reinterpret_cast<const float4*>(grad2d + 16 * item0);
+      const float4* csrc = rec + 2 * item0;
+      float4 t[4], c[2];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) t[k] = rsrc[lane + 64 * k];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) c[k] = csrc[lane + 64 * k];
+      const uint32_t nt = ntiles[item0 + lane];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int e = lane + 64 * k;   // float4 e of the wave's rows: row e / 4, quarter e % 4
+        s_row[wv][kRowPitch * (e >> 2) + (e & 3)] = t[k];
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int e = lane + 64 * k;   // float4 e of the wave's records: record e / 2, half e % 2
+        s_rec[wv][kRecPitch * (e >> 1) + (e & 1)] = c[k];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (nt != 0) {
+        const float4* my = &s_row[wv][kRowPitch * lane];
+        const float4* mr = &s_rec[wv][kRecPitch * lane];
+        project_bwd_view(v, m, sc3, q, my[0], my[1], my[2], mr[0], mr[1], am, as, aq, ao, ac);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    for (int k = 0; k < 4; ++k) aq[k] += dq[k];
+  } else {
+    for (int vi = 0; vi < n_views; ++vi) {
+      const DevView& v = views[vi];
+      if (v.scene != sc) continue;
+      const int64_t item = v.item_offset + (gi - v.gauss_offset);
+      if (ntiles[item] == 0) continue;
+      const float4* row = reinterpret_cast<const float4*>(grad2d + 16 * item);
+      project_bwd_view(v, m, sc3, q, row[0], row[1], row[2], rec[2 * item], rec[2 * item + 1], am, as, aq, ao, ac);
+    }
   }
   const int64_t GS = grads.stride;
   if (accumulate) {

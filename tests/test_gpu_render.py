@@ -164,7 +164,15 @@ def test_forward_backward_parity(tile, W, H, lds):
         e = group_error(G[rows], g_ref[name].reshape(rows.stop - rows.start, -1))
         say(f"  grad {name}: {e:.2e}")
         assert e <= GRAD_TOL, name
-    g2 = rp.region("grad2d", torch.float32).cpu().numpy().reshape(-1, 16)[:, :9].T
+    # the region keeps the raw moments of dL/dpower; with power = -(A dx^2 + 2 B dx dy + C dy^2) / 2
+    # and alpha = o exp(power) the 2D gradients are linear in them, given the item's conic and opacity
+    mo = rp.region("grad2d", torch.float32).cpu().numpy().reshape(-1, 16)[:, :9].astype(np.float64)
+    rec = rp.region("item_rec", torch.float32).cpu().numpy().reshape(-1, 8)[: len(mo)].astype(np.float64)
+    nt = rp.region("item_ntiles", torch.int32).cpu().numpy()[: len(mo)]
+    A, B, C, o = rec[:, 2], rec[:, 3], rec[:, 4], np.where(nt > 0, rec[:, 5], 1.0)
+    g2 = np.stack([-(A * mo[:, 0] + B * mo[:, 1]), -(B * mo[:, 0] + C * mo[:, 1]), -0.5 * mo[:, 2], -mo[:, 3],
+                   -0.5 * mo[:, 4], mo[:, 5] / o, mo[:, 6], mo[:, 7], mo[:, 8]])
+    g2[:, nt == 0] = 0.0
     for name, rows, ref2 in (("mean2d", slice(0, 2), g2_ref["mean2d"].T), ("conic", slice(2, 5), g2_ref["conic"].T),
                              ("opacity", slice(5, 6), g2_ref["opacity"][None]), ("rgb", slice(6, 9), g2_ref["rgb"].T)):
         e = group_error(g2[rows], ref2)
