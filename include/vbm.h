@@ -268,11 +268,13 @@ typedef struct {
 #define VBM_REGION_ITEM_REC 4    /* float32 [n_items][8]: mean2d.xy, conic.abc, opacity, r, g */
 #define VBM_REGION_ITEM_BLUE 5   /* float32 [n_items]: blue */
 #define VBM_REGION_PAIR_TILE 6   /* uint32 [pair_capacity]: sorted global tile of each pair */
-#define VBM_REGION_PAIR_ITEM 7   /* uint32 [pair_capacity]: sorted item of each pair (bits 0..26; the
-                                  * bits above are 0).  With 8x8 and 16x16 tiles vbm_render_fwd keeps
-                                  * a copy elsewhere in ws with bit 27 + k set when it evaluated lane
-                                  * group k (pixel rows k*64/tile .. of the tile) of the pair, which
-                                  * vbm_render_bwd reads */
+#define VBM_REGION_PAIR_ITEM 7   /* uint32 [pair_capacity]: sorted item of each pair in bits 0..26;
+                                  * bit 27 + k is set when the footprint can reach lane group k of
+                                  * the tile (with 16x16 tiles pixel rows 4k .. 4k + 3; every group
+                                  * with other tiles); bit 31 is 0.  With 8x8 and 16x16 tiles
+                                  * vbm_render_fwd keeps a copy elsewhere in ws with bit 27 + k set
+                                  * when it evaluated lane group k (pixel rows k*64/tile .. of the
+                                  * tile) of the pair, which vbm_render_bwd reads */
 #define VBM_REGION_RANGES 8      /* uint32 [n_tiles][2]: [start, end) of each tile's list */
 #define VBM_REGION_GRAD2D 9      /* float32 [n_items][16] after vbm_render_bwd: columns 0..5 hold the
                                   * sums over the item's pixels of dL/dpower times dx, dy, dx^2,

@@ -65,6 +65,14 @@ struct DevScene {
   int32_t gauss_offset, n_gauss;
 };
 
+// ------------------------------------------------------------------ pair values
+// A pair value holds the item id in bits 0..26 (the plan keeps items below 2^27) and a 4-bit mask
+// of the tile's lane groups in bits 27..30.  With 16x16 tiles lane group k is pixel rows
+// 4k .. 4k + 3 of the tile.  The emission sets the groups the footprint can reach (all four with
+// other tiles), and the forward's marked copy the groups it evaluated.
+constexpr int kItemBits = 27;
+constexpr uint32_t kItemMask = (1u << kItemBits) - 1u;
+
 // ------------------------------------------------------------------ wave helpers
 __device__ __forceinline__ uint32_t lane_id() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));

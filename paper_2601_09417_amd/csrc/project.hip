@@ -88,6 +88,37 @@ __device__ __forceinline__ bool tile_reached(float mx, float my, float A, float 
   return q <= tau;
 }
 
+// Lane groups of a 16x16 tile are its 4-row bands.  The footprint {q <= tau} spans the pixel rows
+// whose centre lies within ey of the mean, ey^2 = tau A / (A C - B^2) for the conic (A, B, C) as
+// rounded (the determinant in float64, where both products are exact, so a thin ellipse loses
+// nothing to cancellation), widened by 0.2% and 0.1 pixel.  Returns the first band it can reach in
+// the rectangle's first tile row y0 (bits 12..13) and the last band in its last tile row y1 - 1
+// (bits 28..29), to be ORed into the bin entry's row word (tile rows stay below 2^12); every band
+// of the rows between can be reached.
+__device__ __forceinline__ uint32_t band_bits(float py, float A, float B, float C, float tau, uint32_t y0,
+                                              uint32_t y1) {
+  constexpr uint32_t kAll = 3u << 28;   // first band 0, last band 3
+  const double den = fma(static_cast<double>(A), static_cast<double>(C),
+                         -(static_cast<double>(B) * static_cast<double>(B)));
+  const float e2 = tau * A / static_cast<float>(den);
+  if (!(den > 0.0 && e2 >= 0.0f && e2 < 1e30f)) return kAll;
+  const float ey = sqrtf(e2) * 1.002f + 0.1f;
+  const float f = floorf((py - ey - 0.5f - 16.0f * static_cast<float>(y0)) * 0.25f);
+  const float l = floorf((py + ey - 0.5f - 16.0f * static_cast<float>(y1 - 1)) * 0.25f);
+  const uint32_t kf = static_cast<uint32_t>(fminf(fmaxf(f, 0.0f), 3.0f));
+  const uint32_t kl = static_cast<uint32_t>(fminf(fmaxf(l, 0.0f), 3.0f));
+  return (kf << 12) | (kl << 28);
+}
+
+// The pair-value group mask (bits kItemBits..) of tile row r (0-based) of a rectangle h rows tall
+// whose bin entry row word is by.
+__device__ __forceinline__ uint32_t band_mask(uint32_t by, uint32_t r, uint32_t h) {
+  uint32_t m = 0xFu;
+  if (r == 0) m &= 0xFu << ((by >> 12) & 3u);
+  if (r + 1 == h) m &= 0xFu >> (3u - ((by >> 28) & 3u));
+  return (m & 0xFu) << kItemBits;
+}
+
 // Rectangles of more than this many tiles are tested by a whole wave (64 tiles per round) after
 // the per-thread pass of the block, so that one large footprint does not hold up 63 lanes.
 constexpr uint32_t kSmallRect = 32;
@@ -213,6 +244,7 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
   __shared__ uint8_t s_map[256 * kSmallRect];   // test number -> thread of its rectangle
   __shared__ uint32_t s_q[256];        // threads with a large rectangle
   __shared__ uint32_t s_wofs[256];     // first ballot word of a large rectangle, within the block's
+  __shared__ uint32_t s_band[256];     // band bits of a large rectangle (band_bits)
   __shared__ uint32_t s_n, s_words;
   __shared__ unsigned long long s_wbase;
   if (threadIdx.x == 0) {
@@ -224,7 +256,7 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
   const DevView& v = views[blockIdx.y];
   const int i = blockIdx.x * 256 + threadIdx.x;
   const int64_t item = v.item_offset + i;
-  uint32_t small_area = 0, rx = 0, ry = 0;
+  uint32_t small_area = 0, rx = 0, ry = 0, band = 3u << 28;
   bool deferred = false;
   if (i < v.n_gauss) {
     const int64_t gi = v.gauss_offset + i;
@@ -243,6 +275,8 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
       s_h[threadIdx.x] = p.y1 - p.y0;
       s_invw[threadIdx.x] = 1.0f / static_cast<float>(p.x1 - p.x0);
       const uint32_t area = (p.x1 - p.x0) * (p.y1 - p.y0);
+      if (tile == 16) band = band_bits(p.py, p.ca, p.cb, p.cc, par[5], p.y0, p.y1);
+      s_band[threadIdx.x] = band;
       if (area <= kSmallRect) {
         small_area = area;
       } else {
@@ -292,7 +326,7 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
     // small or invisible rectangles here; a large one is completed below by the wave that tests it
     const uint32_t mask = small_area ? s_mask[threadIdx.x] : 0u;
     const uint32_t nt = static_cast<uint32_t>(__popc(mask));
-    bin[item] = make_uint4(rx, ry, mask, nt);
+    bin[item] = make_uint4(rx, ry | band, mask, nt);
     ntiles[item] = nt;
     vis_flag[item] = nt ? 1u : 0u;
   }
@@ -323,7 +357,7 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
     if (lane == 0) {
       ntiles[it] = nt;
       vis_flag[it] = nt ? 1u : 0u;
-      bin[it] = make_uint4(x0 | ((x0 + w) << 16), y0 | ((y0 + h) << 16),
+      bin[it] = make_uint4(x0 | ((x0 + w) << 16), (y0 | ((y0 + h) << 16)) | s_band[o],
                            keep ? static_cast<uint32_t>(first) : kNoWords, nt);
     }
   }
@@ -373,9 +407,11 @@ __global__ __launch_bounds__(256) void k_gather_bins(const uint32_t* __restrict_
 }
 
 // Writes each visible item's tiles in the items' depth order (views interleaved; the stable tile
-// sort that follows yields (tile, depth, item)).  Pairs past the capacity are dropped and flagged.  Rectangles of at most 32 tiles walk the projection's reach mask per thread;
-// larger ones are queued in the block and emitted by whole waves afterwards (64 tiles per round,
-// positions from the ballot of reached tiles).
+// sort that follows yields (tile, depth, item)).  Pairs past the capacity are dropped and flagged.
+// Rectangles of at most 32 tiles walk the projection's reach mask per thread; larger ones are
+// queued in the block and emitted by whole waves afterwards (64 tiles per round, positions from
+// the ballot of reached tiles).  Each pair value carries the lane groups (row bands) of its tile
+// that the footprint can reach (band_mask).
 __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views, int n_views,
                                               const uint32_t* __restrict__ vals, const uint32_t* __restrict__ offs,
                                               const uint4* __restrict__ sorted_bin, const float4* __restrict__ rec,
@@ -395,9 +431,9 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
       const uint32_t item = vals[p];
       const DevView& v = views[view_of_item(views, n_views, item)];
       const uint4 b = sorted_bin[p];
-      const uint32_t x0 = b.x & 0xFFFFu, x1 = b.x >> 16, y0 = b.y & 0xFFFFu, y1 = b.y >> 16;
-      const uint32_t w = x1 - x0;
-      if (w * (y1 - y0) <= kSmallRect) {
+      const uint32_t x0 = b.x & 0xFFFFu, x1 = b.x >> 16, y0 = b.y & 0xFFFu, y1 = (b.y >> 16) & 0xFFFu;
+      const uint32_t w = x1 - x0, h = y1 - y0;
+      if (w * h <= kSmallRect) {
         // The mask lists the reached tiles in row-major order; it is walked row by row (w bits per
         // row), which needs no integer division.
         int64_t o = offs[p];
@@ -405,11 +441,12 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
         uint32_t m = b.z;
         const uint32_t row_mask = w >= 32 ? 0xFFFFFFFFu : (1u << w) - 1u;
         uint32_t t_row = static_cast<uint32_t>(v.tile_offset) + y0 * static_cast<uint32_t>(v.tiles_x) + x0;
-        for (; m; m >>= w, t_row += static_cast<uint32_t>(v.tiles_x)) {
+        for (uint32_t row = 0; m; m >>= w, t_row += static_cast<uint32_t>(v.tiles_x), ++row) {
+          const uint32_t pv = item | band_mask(b.y, row, h);
           for (uint32_t r = m & row_mask; r; r &= r - 1) {
             if (o < capacity) {
               pair_tile[o] = t_row + static_cast<uint32_t>(__builtin_ctz(r));
-              pair_item[o] = item;
+              pair_item[o] = pv;
             } else {
               over = true;
             }
@@ -432,8 +469,8 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
       const uint32_t item = __builtin_amdgcn_readfirstlane(vals[q]);
       const DevView& v = views[__builtin_amdgcn_readfirstlane(view_of_item(views, n_views, item))];
       const uint4 b = sorted_bin[q];
-      const uint32_t x0 = b.x & 0xFFFFu, x1 = b.x >> 16, y0 = b.y & 0xFFFFu, y1 = b.y >> 16;
-      const uint32_t w = x1 - x0, area = w * (y1 - y0);
+      const uint32_t x0 = b.x & 0xFFFFu, x1 = b.x >> 16, y0 = b.y & 0xFFFu, y1 = (b.y >> 16) & 0xFFFu;
+      const uint32_t h = y1 - y0, w = x1 - x0, area = w * h;
       const float inv_w = 1.0f / static_cast<float>(w);
       int64_t o = offs[q];
       bool over = false;
@@ -450,7 +487,7 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
             if (oo < capacity) {
               pair_tile[oo] = static_cast<uint32_t>(v.tile_offset) + (y0 + ty) * static_cast<uint32_t>(v.tiles_x) +
                               x0 + tx;
-              pair_item[oo] = item;
+              pair_item[oo] = item | band_mask(b.y, ty, h);
             } else {
               over = true;
             }
@@ -468,6 +505,7 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
         const uint32_t t = t0 + static_cast<uint32_t>(lane);
         uint32_t tx, ty;
         rect_tile(t, w, inv_w, tx, ty);
+        const uint32_t pv = item | band_mask(b.y, ty, h);
         tx += x0;
         ty += y0;
         const bool hit = t < area && tile_reached(ra.x, ra.y, ra.z, ra.w, rb.x, nBA, nBC, tau, static_cast<int>(tx),
@@ -477,7 +515,7 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
           const int64_t oo = o + lanes_below(m);
           if (oo < capacity) {
             pair_tile[oo] = static_cast<uint32_t>(v.tile_offset) + ty * static_cast<uint32_t>(v.tiles_x) + tx;
-            pair_item[oo] = item;
+            pair_item[oo] = pv;
           } else {
             over = true;
           }

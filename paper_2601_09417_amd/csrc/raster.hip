@@ -40,10 +40,6 @@ namespace vbm {
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
-// Item ids stay below 2^27 (the plan enforces it); the forward keeps per-pair lane-group marks in
-// the bits above.
-constexpr int kItemBits = 27;
-constexpr uint32_t kItemMask = (1u << kItemBits) - 1u;
 
 template <int TILE>
 struct TileCfg {
@@ -254,10 +250,12 @@ __device__ __forceinline__ bool any_live(const float (&fy)[PPL]) {
 // One list step (0-based list position pos) of the forward for the lane's pixels:
 // alpha = min(0.99, 2^e2); a pixel takes the Gaussian when alpha >= 1/255, unless the new
 // transmittance would fall below 1e-4, in which case the pixel stops without it and records pos as
-// the number of list entries its compositing took into account.  Returns the mask of lane groups k
-// that were evaluated: every group with a pixel that took the Gaussian is among them.
+// the number of list entries its compositing took into account.  Only the lane groups in `reach`
+// (the pair value's groups that the footprint can reach, uniform) are looked at.  Returns the mask
+// of lane groups k that were evaluated: every group with a pixel that took the Gaussian is among
+// them.
 template <int PPL, bool STATS>
-__device__ __forceinline__ uint32_t fwd_step(const Rec& r, int pos, float fx, float (&fy)[PPL],
+__device__ __forceinline__ uint32_t fwd_step(const Rec& r, uint32_t reach, int pos, float fx, float (&fy)[PPL],
                                              float (&T)[PPL], float (&cr)[PPL], float (&cg)[PPL], float (&cb)[PPL],
                                              int (&nvis)[PPL], uint32_t& n_eval, uint32_t& n_used) {
   uint32_t groups = 0;
@@ -266,6 +264,11 @@ __device__ __forceinline__ uint32_t fwd_step(const Rec& r, int pos, float fx, fl
   const float vb = r.hB * dx;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
+    // a group out of the footprint's rows: nothing to evaluate (a scalar bit test)
+    if (!((reach >> k) & 1u)) {
+      if (STATS) n_eval += fy[k] < kLiveBound ? 1u : 0u;
+      continue;
+    }
     const float dy = r.my - fy[k];
     const float e2 = exponent2(r, u, vb, dy);
     // A lane group where every pixel has 2^e2 clearly below 1/255 (or is terminated, e2 = -inf)
@@ -309,17 +312,25 @@ __device__ __forceinline__ uint32_t fwd_step(const Rec& r, int pos, float fx, fl
 template <int B>
 struct LdsBatch {
   float4 a[2][B], b[2][B];
-  float4 c[2][B];   // c.x: blue (a 16-byte slot, so that one address serves all three reads)
+  float4 c[2][B];   // c.x: blue, c.y: the pair value's bits (a 16-byte slot, so that one address
+                    // serves all the reads of an entry)
 };
 
 template <int B>
 __device__ __forceinline__ void lds_put(LdsBatch<B>& L, int buf, int lane, const float4& ra, const float4& rb,
-                                        float bl) {
+                                        float bl, uint32_t pv) {
   if (lane < B) {
     L.a[buf][lane] = ra;
     L.b[buf][lane] = rb;
     L.c[buf][lane].x = bl;
+    L.c[buf][lane].y = __uint_as_float(pv);
   }
+}
+
+// The pair value of entry b, in a scalar register.
+template <int B>
+__device__ __forceinline__ uint32_t lds_pv(const LdsBatch<B>& L, int buf, int b) {
+  return uniform(__float_as_uint(L.c[buf][b].y));
 }
 
 template <int B>
@@ -446,7 +457,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
     float4 ra, rb;
     float bl;
     lds_fetch(pair_item, crec, blue, imax, start + lane, lane < LDSB && start + lane < end, pvc, ra, rb, bl);
-    lds_put<LDSB>(L, 0, lane, ra, rb, bl);
+    lds_put<LDSB>(L, 0, lane, ra, rb, bl, pvc);
     int buf = 0;
     for (int base = start; base < end; base += LDSB) {
       if (!any_live(fy)) break;
@@ -458,13 +469,14 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
       MarkWords<LDSB> mw;
       for (int b = 0; b < n; ++b) {
         const Rec r = lds_get<LDSB>(L, buf, b);
-        mw.set(b, fwd_step<PPL, STATS>(r, pos0 + b, fx, fy, T, cr, cg, cb, nvis, n_eval, n_used));
+        const uint32_t reach = lds_pv<LDSB>(L, buf, b) >> kItemBits;
+        mw.set(b, fwd_step<PPL, STATS>(r, reach, pos0 + b, fx, fy, T, cr, cg, cb, nvis, n_eval, n_used));
       }
       mw.finish(n);
       if (lane < n) pair_marked[base + lane] = (pvc & kItemMask) | (mw.of_lane(lane) << kItemBits);
       buf ^= 1;
       pvc = pv;
-      lds_put<LDSB>(L, buf, lane, ra, rb, bl);
+      lds_put<LDSB>(L, buf, lane, ra, rb, bl, pv);
     }
   } else {
   // Records through the scalar cache one list step ahead of their use, pair values by vector loads
@@ -483,7 +495,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
     u1 = uniform(L1);
     R1 = load_rec_s(crec, blue, u1, imax);
     L1 = load_item(irs, min(j + 4, lastj));
-    const uint32_t m0 = (u0 & kItemMask) | (fwd_step<PPL, STATS>(R0, j - start, fx, fy, T, cr, cg, cb, nvis,
+    const uint32_t m0 = (u0 & kItemMask) | (fwd_step<PPL, STATS>(R0, u0 >> kItemBits, j - start, fx, fy, T, cr, cg, cb, nvis,
                                                                   n_eval, n_used) << kItemBits);
     wait_scalar_loads();
     R1.lo = j + 1 < end ? R1.lo : -__builtin_inff();
@@ -491,13 +503,13 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_fwd(
     R2 = load_rec_s(crec, blue, u2, imax);
     L2 = load_item(irs, min(j + 5, lastj));
     const uint32_t un = uniform(L0);
-    const uint32_t m1 = (u1 & kItemMask) | (fwd_step<PPL, STATS>(R1, j - start + 1, fx, fy, T, cr, cg, cb, nvis,
+    const uint32_t m1 = (u1 & kItemMask) | (fwd_step<PPL, STATS>(R1, u1 >> kItemBits, j - start + 1, fx, fy, T, cr, cg, cb, nvis,
                                                                   n_eval, n_used) << kItemBits);
     wait_scalar_loads();
     R2.lo = j + 2 < end ? R2.lo : -__builtin_inff();
     R0 = load_rec_s(crec, blue, un, imax);
     L0 = load_item(irs, min(j + 6, lastj));
-    const uint32_t m2 = (u2 & kItemMask) | (fwd_step<PPL, STATS>(R2, j - start + 2, fx, fy, T, cr, cg, cb, nvis,
+    const uint32_t m2 = (u2 & kItemMask) | (fwd_step<PPL, STATS>(R2, u2 >> kItemBits, j - start + 2, fx, fy, T, cr, cg, cb, nvis,
                                                                   n_eval, n_used) << kItemBits);
     if (kMark) store_pair_values(pair_marked, lane, j, min(end - j, 3), m0, m1, m2);
     u0 = un;
@@ -649,14 +661,12 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
     // The forward's LDS batches walked in reverse: the batch ending at list position hi holds
     // positions hi, hi - 1, ... in lanes 0, 1, ...
     __shared__ LdsBatch<LDSB> L;
-    __shared__ uint32_t s_pv[2][LDSB];
     uint32_t pv;
     float4 ra, rb;
     float bl;
     int hi = maxn - 1;
     lds_fetch(pair_values, crec, blue, imax, start + hi - lane, lane < LDSB && hi - lane >= 0, pv, ra, rb, bl);
-    lds_put<LDSB>(L, 0, lane, ra, rb, bl);
-    if (lane < LDSB) s_pv[0][lane] = pv;
+    lds_put<LDSB>(L, 0, lane, ra, rb, bl, pv);
     int buf = 0;
     for (; hi >= 0; hi -= LDSB) {
       const int nh = hi - LDSB;
@@ -664,12 +674,11 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_composite_bwd(
       const int n = min(LDSB, hi + 1);
       for (int b = 0; b < n; ++b) {
         const Rec r = lds_get<LDSB>(L, buf, b);
-        bwd_step<PPL, kMarked, kCols, STATS>(r, uniform(s_pv[buf][b]), hi - b, fx, P, lane, out_k, out_lane,
+        bwd_step<PPL, kMarked, kCols, STATS>(r, lds_pv<LDSB>(L, buf, b), hi - b, fx, P, lane, out_k, out_lane,
                                              grad2d, n_eval, n_used);
       }
       buf ^= 1;
-      lds_put<LDSB>(L, buf, lane, ra, rb, bl);
-      if (lane < LDSB) s_pv[buf][lane] = pv;
+      lds_put<LDSB>(L, buf, lane, ra, rb, bl, pv);
     }
   } else {
   // Records through the scalar cache one step ahead of their use, pair values through the scalar
