@@ -263,9 +263,18 @@ typedef struct {
 #define VBM_REGION_COUNTERS 0    /* uint32 [16]: [0] visible items, [1] pairs, [2] overflow, [4..5]
                                   * uint64 ballot words taken by large footprints */
 #define VBM_REGION_ITEM_DEPTH 1  /* float32 [n_items] camera depth (0 when culled) */
-#define VBM_REGION_ITEM_RECT 2   /* uint32 [2][n_items]: x0 | x1 << 16, y0 | y1 << 16 */
+#define VBM_REGION_ITEM_RECT 2   /* uint32 [n_items][4], the binning entry of each item:
+                                  * [0] x0 | x1 << 16 and [1] y0 | y1 << 16, the candidate
+                                  * rectangle in tiles (12 bits each; with 16x16 tiles bits
+                                  * 12..13 and 28..29 of [1] hold the first row band the footprint
+                                  * can reach in tile row y0 and the last in tile row y1 - 1),
+                                  * [2] the reached-tile mask of a rectangle of at most 32 tiles
+                                  * (row-major) or the first ballot word of a larger one
+                                  * (0xFFFFFFFF when the word buffer was full), [3] the number of
+                                  * reached tiles */
 #define VBM_REGION_ITEM_NTILES 3 /* uint32 [n_items] */
-#define VBM_REGION_ITEM_REC 4    /* float32 [n_items][8]: mean2d.xy, conic.abc, opacity, r, g */
+#define VBM_REGION_ITEM_REC 4    /* float32 [n_items][4]: conic.abc, opacity (mean2d is in
+                                  * VBM_REGION_ITEM_COEF) */
 #define VBM_REGION_ITEM_BLUE 5   /* float32 [n_items]: blue */
 #define VBM_REGION_PAIR_TILE 6   /* uint32 [pair_capacity]: sorted global tile of each pair */
 #define VBM_REGION_PAIR_ITEM 7   /* uint32 [pair_capacity]: sorted item of each pair in bits 0..26;

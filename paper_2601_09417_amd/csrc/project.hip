@@ -228,11 +228,10 @@ __device__ __forceinline__ ProjResult project_one(const DevView& v, int tile, fl
 // which set the reached bits of the items' row-major masks; larger rectangles are tested by whole
 // waves, 64 tiles per round.
 __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ views, int tile, vbm_gaussians_c g,
-                                                 float* __restrict__ depth, uint32_t* __restrict__ rect,
-                                                 uint32_t* __restrict__ ntiles, float4* __restrict__ rec,
-                                                 float4* __restrict__ coef, float* __restrict__ blue,
-                                                 uint32_t* __restrict__ vis_flag, uint4* __restrict__ bin,
-                                                 int64_t n_items, unsigned long long* __restrict__ word_count,
+                                                 float* __restrict__ depth, uint32_t* __restrict__ ntiles,
+                                                 float4* __restrict__ rec, float4* __restrict__ coef,
+                                                 float* __restrict__ blue, uint32_t* __restrict__ vis_flag,
+                                                 uint4* __restrict__ bin, unsigned long long* __restrict__ word_count,
                                                  unsigned long long* __restrict__ words, uint32_t word_cap) {
   __shared__ float s_par[8][256];      // per thread: mean2d.xy, conic A B C, tau, nBA, nBC
   __shared__ uint32_t s_org[256];      // rectangle origin x0 | y0 << 16
@@ -288,10 +287,7 @@ __global__ __launch_bounds__(256) void k_project(const DevView* __restrict__ vie
     depth[item] = p.visible ? p.depth : 0.0f;
     rx = p.x0 | (p.x1 << 16);
     ry = p.y0 | (p.y1 << 16);
-    rect[item] = rx;
-    rect[n_items + item] = ry;
-    rec[2 * item] = make_float4(p.px, p.py, p.ca, p.cb);
-    rec[2 * item + 1] = make_float4(p.cc, op, g.rgb[gi], g.rgb[S + gi]);
+    rec[item] = make_float4(p.ca, p.cb, p.cc, op);
     // Compositing record: the exponent in base 2 with log2(opacity) folded in,
     // e2 = hA dx^2 + hB dx dy + hC dy^2 + log2(o) = log2(o) - (A dx^2 + 2 B dx dy + C dy^2) log2(e) / 2.
     constexpr float kLog2e = 1.44269504088896341f;
@@ -415,6 +411,7 @@ __global__ __launch_bounds__(256) void k_gather_bins(const uint32_t* __restrict_
 __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views, int n_views,
                                               const uint32_t* __restrict__ vals, const uint32_t* __restrict__ offs,
                                               const uint4* __restrict__ sorted_bin, const float4* __restrict__ rec,
+                                              const float4* __restrict__ coef,
                                               const unsigned long long* __restrict__ words,
                                               int tile, uint32_t* __restrict__ counters, int64_t n_max,
                                               int64_t capacity, uint32_t* __restrict__ pair_tile,
@@ -497,10 +494,11 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
         if (over) counters[2] = 1u;
         continue;
       }
-      const float4 ra = rec[2 * static_cast<int64_t>(item)];
-      const float4 rb = rec[2 * static_cast<int64_t>(item) + 1];
-      const float tau = footprint_tau(rb.y);
-      const float nBA = -__fdiv_rn(ra.w, ra.z), nBC = -__fdiv_rn(ra.w, rb.x);
+      // the conic and opacity (binning record) and the mean (compositing record), as projected
+      const float4 cr = rec[item];
+      const float4 cm = coef[2 * static_cast<int64_t>(item)];
+      const float tau = footprint_tau(cr.w);
+      const float nBA = -__fdiv_rn(cr.y, cr.x), nBC = -__fdiv_rn(cr.y, cr.z);
       for (uint32_t t0 = 0; t0 < area; t0 += 64) {
         const uint32_t t = t0 + static_cast<uint32_t>(lane);
         uint32_t tx, ty;
@@ -508,7 +506,7 @@ __global__ __launch_bounds__(256) void k_emit(const DevView* __restrict__ views,
         const uint32_t pv = item | band_mask(b.y, ty, h);
         tx += x0;
         ty += y0;
-        const bool hit = t < area && tile_reached(ra.x, ra.y, ra.z, ra.w, rb.x, nBA, nBC, tau, static_cast<int>(tx),
+        const bool hit = t < area && tile_reached(cm.x, cm.y, cr.x, cr.y, cr.z, nBA, nBC, tau, static_cast<int>(tx),
                                                   static_cast<int>(ty), tile, v.width, v.height);
         const uint64_t m = __ballot(hit);
         if (hit) {
@@ -667,8 +665,8 @@ __device__ __forceinline__ void project_bwd_one(const DevView& v, const float m[
 // the 2D gradients linear in them:
 //   dmean.x = -(A m0 + B m1), dmean.y = -(B m0 + C m1), dA = -m2 / 2, dB = -m3, dC = -m4 / 2,
 //   dopacity = m5 / o.
-__device__ __forceinline__ void moments_to_grad2d(const float4 ra, const float4 rb, float g2[9]) {
-  const float A = ra.z, B = ra.w, Cc = rb.x, o = rb.y;
+__device__ __forceinline__ void moments_to_grad2d(const float4 cr, float g2[9]) {
+  const float A = cr.x, B = cr.y, Cc = cr.z, o = cr.w;
   const float m0 = g2[0], m1 = g2[1];
   g2[0] = -(A * m0 + B * m1);
   g2[1] = -(B * m0 + Cc * m1);
@@ -679,13 +677,13 @@ __device__ __forceinline__ void moments_to_grad2d(const float4 ra, const float4 
 }
 
 // Adds one view's contribution of a Gaussian: the item's raw moments (accumulator row, nine
-// columns) turned into 2D gradients with its record, then the chain rule to the 3D parameters.
+// columns) turned into 2D gradients with its conic and opacity (cr), then the chain rule to the 3D
+// parameters.
 __device__ __forceinline__ void project_bwd_view(const DevView& v, const float m[3], const float sc3[3],
-                                                 const float q[4], float4 q0, float4 q1, float4 q2, float4 ra,
-                                                 float4 rb, float am[3], float as[3], float aq[4], float& ao,
-                                                 float ac[3]) {
+                                                 const float q[4], float4 q0, float4 q1, float4 q2, float4 cr,
+                                                 float am[3], float as[3], float aq[4], float& ao, float ac[3]) {
   float g2[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x};
-  moments_to_grad2d(ra, rb, g2);
+  moments_to_grad2d(cr, g2);
   ao += g2[5];
   ac[0] += g2[6];
   ac[1] += g2[7];
@@ -701,19 +699,19 @@ __device__ __forceinline__ void project_bwd_view(const DevView& v, const float m
 }
 
 // One thread per Gaussian, its views in order (deterministic).  When a wave's 64 Gaussians all
-// belong to one scene, their items in a view are 64 consecutive accumulator rows (4 KB) and
-// records (2 KB): the wave reads them as coalesced 16-byte vectors and hands each lane its own row
-// through LDS, instead of 64 strided row reads, which keep the texture units busy far longer
-// than the bytes need.  A wave that straddles a scene boundary or the end reads per lane.
+// belong to one scene, their items in a view are 64 consecutive accumulator rows (4 KB): the wave
+// reads them as coalesced 16-byte vectors and hands each lane its own row through LDS, instead of
+// 64 strided row reads, which keep the texture units busy far longer than the bytes need (the
+// 16-byte records are coalesced as they are).  A wave that straddles a scene boundary or the end
+// reads per lane.
 __global__ __launch_bounds__(256) void k_project_bwd(const DevView* __restrict__ views, int n_views,
                                                      const DevScene* __restrict__ scenes, int n_scenes,
                                                      vbm_gaussians_c g, float* __restrict__ grad2d,
                                                      const float4* __restrict__ rec, int64_t n_items,
                                                      const uint32_t* __restrict__ ntiles, vbm_gaussians grads,
                                                      int accumulate, int64_t n_total) {
-  constexpr int kRowPitch = 5, kRecPitch = 3;   // float4 per LDS row (padded: spreads the banks)
+  constexpr int kRowPitch = 5;   // float4 per LDS row (padded: spreads the banks)
   __shared__ float4 s_row[4][64 * kRowPitch];
-  __shared__ float4 s_rec[4][64 * kRecPitch];
   const int64_t gi = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   const int lane = static_cast<int>(threadIdx.x) & 63, wv = static_cast<int>(threadIdx.x) >> 6;
   const bool valid = gi < n_total;
@@ -735,30 +733,22 @@ __global__ __launch_bounds__(256) void k_project_bwd(const DevView* __restrict__
       if (v.scene != sc0) continue;   // uniform
       const int64_t item0 = v.item_offset + (g0 - v.gauss_offset);
       const float4* rsrc = reinterpret_cast<const float4*>(grad2d + 16 * item0);
-      const float4* csrc = rec + 2 * item0;
-      float4 t[4], c[2];
+      float4 t[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) t[k] = rsrc[lane + 64 * k];
-#pragma unroll
-      for (int k = 0; k < 2; ++k) c[k] = csrc[lane + 64 * k];
+      const float4 cr = rec[item0 + lane];
       const uint32_t nt = ntiles[item0 + lane];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int e = lane + 64 * k;   // float4 e of the wave's rows: row e / 4, quarter e % 4
         s_row[wv][kRowPitch * (e >> 2) + (e & 3)] = t[k];
       }
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const int e = lane + 64 * k;   // float4 e of the wave's records: record e / 2, half e % 2
-        s_rec[wv][kRecPitch * (e >> 1) + (e & 1)] = c[k];
-      }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       if (nt != 0) {
         const float4* my = &s_row[wv][kRowPitch * lane];
-        const float4* mr = &s_rec[wv][kRecPitch * lane];
-        project_bwd_view(v, m, sc3, q, my[0], my[1], my[2], mr[0], mr[1], am, as, aq, ao, ac);
+        project_bwd_view(v, m, sc3, q, my[0], my[1], my[2], cr, am, as, aq, ao, ac);
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -771,7 +761,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(const DevView* __restrict__
       const int64_t item = v.item_offset + (gi - v.gauss_offset);
       if (ntiles[item] == 0) continue;
       const float4* row = reinterpret_cast<const float4*>(grad2d + 16 * item);
-      project_bwd_view(v, m, sc3, q, row[0], row[1], row[2], rec[2 * item], rec[2 * item + 1], am, as, aq, ao, ac);
+      project_bwd_view(v, m, sc3, q, row[0], row[1], row[2], rec[item], am, as, aq, ao, ac);
     }
   }
   const int64_t GS = grads.stride;

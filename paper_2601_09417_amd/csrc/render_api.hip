@@ -19,14 +19,14 @@
 
 namespace vbm {
 
-__global__ void k_project(const DevView*, int, vbm_gaussians_c, float*, uint32_t*, uint32_t*, float4*, float4*,
-                          float*, uint32_t*, uint4*, int64_t, unsigned long long*, unsigned long long*, uint32_t);
+__global__ void k_project(const DevView*, int, vbm_gaussians_c, float*, uint32_t*, float4*, float4*, float*,
+                          uint32_t*, uint4*, unsigned long long*, unsigned long long*, uint32_t);
 __global__ void k_compact_visible(const DevView*, const uint32_t*, const float*, const uint32_t*, uint32_t*,
                                   uint32_t*);
 __global__ void k_gather_bins(const uint32_t*, const uint4*, const uint32_t*, int64_t, uint32_t*, uint4*);
 __global__ void k_emit(const DevView*, int, const uint32_t*, const uint32_t*, const uint4*,
-                       const float4*, const unsigned long long*, int, uint32_t*, int64_t, int64_t, uint32_t*,
-                       uint32_t*);
+                       const float4*, const float4*, const unsigned long long*, int, uint32_t*, int64_t, int64_t,
+                       uint32_t*, uint32_t*);
 __global__ void k_ranges(const uint32_t*, const uint32_t*, int64_t, uint2*);
 __global__ void k_status(const uint32_t*, int32_t*);
 __global__ void k_tile_keys(const uint2*, int64_t, uint32_t*, uint32_t*);
@@ -48,7 +48,7 @@ namespace {
 enum Region {
   R_COUNTERS = VBM_REGION_COUNTERS,
   R_DEPTH = VBM_REGION_ITEM_DEPTH,
-  R_RECT = VBM_REGION_ITEM_RECT,
+  R_BIN = VBM_REGION_ITEM_RECT,   // uint4 [n_items]: the projection's bin entries (see vbm.h)
   R_NTILES = VBM_REGION_ITEM_NTILES,
   R_REC = VBM_REGION_ITEM_REC,
   R_BLUE = VBM_REGION_ITEM_BLUE,
@@ -66,8 +66,7 @@ enum Region {
   R_SCRATCH = 17,
   R_VISFLAG = 18,
   R_COEF = VBM_REGION_ITEM_COEF,
-  R_BIN = 20,      // uint4 [n_items]: x0 | x1 << 16, y0 | y1 << 16, reached-tile mask of a small
-                   // rectangle or first ballot word of a large one, tile count
+  R_UNUSED20 = 20,
   R_TORDER = 21,   // uint32 [4][n_tiles]: sort keys, tiles, and the sorted keys and tiles (the launch order)
   R_WORDS = 22,    // uint64 [ballot_words(n_items)]: large rectangles' reached-tile ballots
   R_SBIN = 23,     // uint4 [n_items]: the visible items' bin entries in depth order
@@ -93,9 +92,9 @@ void layout(vbm_plan* p) {
   size_t sz[R_COUNT];
   sz[R_COUNTERS] = 16 * 4;
   sz[R_DEPTH] = I * 4;
-  sz[R_RECT] = 2 * I * 4;
+  sz[R_BIN] = I * 16;
   sz[R_NTILES] = I * 4;
-  sz[R_REC] = I * 32;
+  sz[R_REC] = I * 16;
   sz[R_BLUE] = I * 4;
   sz[R_PTILE] = P * 4;
   sz[R_PITEM] = P * 4;
@@ -118,7 +117,7 @@ void layout(vbm_plan* p) {
   sz[R_SCRATCH] = scr;
   sz[R_VISFLAG] = I * 4;
   sz[R_COEF] = I * 32;
-  sz[R_BIN] = I * 16;
+  sz[R_UNUSED20] = 0;
   sz[R_TORDER] = 4 * NT * 4;
   sz[R_WORDS] = 8 * ballot_words(I);
   sz[R_SBIN] = I * 16;
@@ -328,7 +327,6 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
   const int64_t cap = p->pair_capacity;
   uint32_t* counters = region<uint32_t>(p, ws, R_COUNTERS);
   float* depth = region<float>(p, ws, R_DEPTH);
-  uint32_t* rect = region<uint32_t>(p, ws, R_RECT);
   uint32_t* ntiles = region<uint32_t>(p, ws, R_NTILES);
   float4* rec = region<float4>(p, ws, R_REC);
   float4* coef = region<float4>(p, ws, R_COEF);
@@ -346,8 +344,8 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
   // grid.x covers the largest scene (bounded by the total Gaussian count); grid.y is the view
   const int gx = static_cast<int>(ceil_div(p->n_gaussians > 0 ? p->n_gaussians : 1, 256));
   if (I > 0) {
-    hipLaunchKernelGGL(k_project, dim3(gx, p->n_views), dim3(256), 0, s, views, p->tile, g, depth, rect, ntiles, rec,
-                       coef, blue, visflag, region<uint4>(p, ws, R_BIN), I,
+    hipLaunchKernelGGL(k_project, dim3(gx, p->n_views), dim3(256), 0, s, views, p->tile, g, depth, ntiles, rec,
+                       coef, blue, visflag, region<uint4>(p, ws, R_BIN),
                        reinterpret_cast<unsigned long long*>(counters + 4), region<unsigned long long>(p, ws, R_WORDS),
                        static_cast<uint32_t>(ballot_words(I)));
     VBM_LAUNCH_CHECK("project");
@@ -387,7 +385,7 @@ extern "C" vbm_status vbm_render_fwd(const vbm_plan* p, const void* view_table, 
   const int pfirst = tile_passes % 2;
   if (I > 0 && emit_grid_n > 0) {
     hipLaunchKernelGGL(k_emit, dim3(grid_cap(emit_grid_n, 16384)), dim3(256), 0, s, views, p->n_views, vv[0], poffs,
-                       region<uint4>(p, ws, R_SBIN), rec, region<unsigned long long>(p, ws, R_WORDS), p->tile,
+                       region<uint4>(p, ws, R_SBIN), rec, coef, region<unsigned long long>(p, ws, R_WORDS), p->tile,
                        counters, I, cap, pt[pfirst], pi[pfirst]);
     VBM_LAUNCH_CHECK("emit");
   }

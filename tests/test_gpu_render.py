@@ -45,23 +45,27 @@ def test_projection_and_pair_lists_bit_exact(tile, bits, opacity):
     P_ref = ref["tile"].size
     assert int(out.status[1]) == P_ref
     depth = rp.region("item_depth", torch.float32).cpu().numpy()
-    rect = rp.region("item_rect", torch.int32).cpu().numpy().view(np.uint32)
+    bins = rp.region("item_rect", torch.int32).cpu().numpy().view(np.uint32).reshape(-1, 4)
     ntl = rp.region("item_ntiles", torch.int32).cpu().numpy()
-    rec = rp.region("item_rec", torch.float32).cpu().numpy().reshape(-1, 8)
+    rec = rp.region("item_rec", torch.float32).cpu().numpy().reshape(-1, 4)
+    coef = rp.region("item_coef", torch.float32).cpu().numpy().reshape(-1, 8)
     I = int(rp.plan.n_items)
+    rx, ry = bins[:I, 0], bins[:I, 1] & 0x0FFF0FFF      # (the row-band bits sit above bit 11 of each half)
+    assert np.array_equal(bins[:I, 3], ntl[:I])
     for v in range(3):
         pr = ref["proj"][v]
         sl = slice(v * gs.n, (v + 1) * gs.n)
         vis = pr["n_tiles"] > 0
         assert np.array_equal(ntl[sl], pr["n_tiles"])
         # the float32 spec values themselves (quaternion norm, divisions, square roots in one order)
-        for col, val in ((0, pr["px"]), (1, pr["py"]), (2, pr["conic"][0]), (3, pr["conic"][1]), (4, pr["conic"][2])):
-            assert np.array_equal(rec[sl][vis, col].view(np.uint32), np.asarray(val, np.float32)[vis].view(np.uint32))
+        for arr, col, val in ((coef, 0, pr["px"]), (coef, 1, pr["py"]), (rec, 0, pr["conic"][0]),
+                              (rec, 1, pr["conic"][1]), (rec, 2, pr["conic"][2])):
+            assert np.array_equal(arr[sl][vis, col].view(np.uint32), np.asarray(val, np.float32)[vis].view(np.uint32))
         assert np.array_equal(depth[sl][vis].view(np.uint32), pr["depth"][vis].view(np.uint32))
-        assert np.array_equal(rect[sl][vis] & 0xFFFF, pr["x0"][vis])
-        assert np.array_equal(rect[sl][vis] >> 16, pr["x1"][vis])
-        assert np.array_equal(rect[I:][sl][vis] & 0xFFFF, pr["y0"][vis])
-        assert np.array_equal(rect[I:][sl][vis] >> 16, pr["y1"][vis])
+        assert np.array_equal(rx[sl][vis] & 0xFFFF, pr["x0"][vis])
+        assert np.array_equal(rx[sl][vis] >> 16, pr["x1"][vis])
+        assert np.array_equal(ry[sl][vis] & 0xFFFF, pr["y0"][vis])
+        assert np.array_equal(ry[sl][vis] >> 16, pr["y1"][vis])
     ptile = rp.region("pair_tile", torch.int32).cpu().numpy()[:P_ref]
     pitem = rp.region("pair_item", torch.int32).cpu().numpy()[:P_ref] & ITEM_MASK   # marks above bit 26
     assert np.array_equal(ptile, ref["tile"])
@@ -71,6 +75,53 @@ def test_projection_and_pair_lists_bit_exact(tile, bits, opacity):
     nonempty = ref_r[:, 1] > ref_r[:, 0]
     assert np.array_equal(ranges[nonempty], ref_r[nonempty])
     assert np.all(ranges[~nonempty, 0] == ranges[~nonempty, 1])      # empty tiles hold an empty range
+
+
+def test_row_bands_cover_every_contributing_pixel():
+    """With 16x16 tiles each pair value carries, in bits 27..30, the 4-row bands of its tile that the
+    footprint can reach, and the forward evaluates only those.  Every pixel of the tile where the
+    Gaussian reaches alpha >= 1/255 (float64, from the oracle's float32 projection) must lie in a set
+    band; the bands must also skip something, or the test would pass on an all-ones mask."""
+    api = _api()
+    gs, cams = _scene(3000, 21, 3, 131, 77, log_scale=-3.3)
+    P = to_dev(gs)
+    rp = api.plan_batch(cams, [0, gs.n], tile=16, pair_capacity=1 << 20)
+    out = api.render_fwd(rp, P)
+    torch.cuda.synchronize()
+    ref = binning.pair_lists(gs, cams, 16)
+    n = ref["tile"].size
+    assert int(out.status[0]) == 0 and int(out.status[1]) == n
+    pv = rp.region("pair_item", torch.int32).cpu().numpy()[:n].view(np.uint32)
+    assert np.array_equal(pv & ITEM_MASK, ref["item"])
+    bands = (pv >> 27) & 0xF
+    W, H = cams[0].width, cams[0].height
+    tx_n, ty_n = -(-W // 16), -(-H // 16)
+    tile = ref["tile"].astype(np.int64)
+    view, local = tile // (tx_n * ty_n), tile % (tx_n * ty_n)
+    tx, ty = local % tx_n, local // tx_n
+    gi = ref["item"].astype(np.int64) - view * gs.n
+    px = np.empty(n); py = np.empty(n); A = np.empty(n); B = np.empty(n); C = np.empty(n)
+    for v in range(len(cams)):
+        sel = view == v
+        pr = ref["proj"][v]
+        px[sel], py[sel] = pr["px"][gi[sel]], pr["py"][gi[sel]]
+        A[sel], B[sel], C[sel] = (np.asarray(c, np.float64)[gi[sel]] for c in pr["conic"])
+    o = np.asarray(gs.opacity, np.float64)[gi]
+    need = np.zeros(n, np.uint32)
+    r = np.arange(16)
+    xs = (tx[:, None] * 16 + r[None, :]).astype(np.float64) + 0.5          # [n, 16] pixel-centre columns
+    xin = xs < W
+    for row in range(16):
+        y = ty * 16 + row
+        dy = (y + 0.5) - py
+        dx = xs - px[:, None]
+        q = A[:, None] * dx * dx + 2 * B[:, None] * dx * dy[:, None] + C[:, None] * dy[:, None] ** 2
+        hit = ((o[:, None] * np.exp(-0.5 * q) >= 1 / 255) & xin).any(1) & (y < H)
+        need |= np.where(hit, np.uint32(1 << (row // 4)), np.uint32(0))
+    say(f"row bands: {n} pairs, {(bands != 0xF).mean():.2f} with a band skipped, "
+        f"{np.count_nonzero(need & ~bands)} pairs missing a needed band")
+    assert not np.any(need & ~bands)
+    assert (bands != 0xF).mean() > 0.2
 
 
 @pytest.mark.parametrize("tile", [8, 16])
@@ -90,9 +141,10 @@ def test_pair_lists_large_footprints(tile):
     ref = binning.pair_lists(gs, cams, tile)
     assert int(out.status[0]) == 0 and int(out.status[1]) == ref["tile"].size
     ntl = rp.region("item_ntiles", torch.int32).cpu().numpy()
-    rect = rp.region("item_rect", torch.int32).cpu().numpy().view(np.uint32)
     I = int(rp.plan.n_items)
-    area = ((rect[:I] >> 16) - (rect[:I] & 0xFFFF)) * ((rect[I:] >> 16) - (rect[I:] & 0xFFFF))
+    bins = rp.region("item_rect", torch.int32).cpu().numpy().view(np.uint32).reshape(-1, 4)[:I]
+    rx, ry = bins[:, 0], bins[:, 1] & 0x0FFF0FFF
+    area = ((rx >> 16) - (rx & 0xFFFF)) * ((ry >> 16) - (ry & 0xFFFF))
     assert (area > 32).sum() > 300 and (area[ntl > 0] <= 32).sum() > 1000
     for v in range(2):
         assert np.array_equal(ntl[v * gs.n:(v + 1) * gs.n], ref["proj"][v]["n_tiles"])
@@ -120,12 +172,12 @@ def test_large_footprints_beyond_the_ballot_word_buffer():
     cap = int(rp.plan.region_bytes[22]) // 8
     assert cap == max(I // 4, 1024)
     taken = int(rp.region("counters", torch.int32).cpu().numpy().view(np.uint64)[2])
-    rect = rp.region("item_rect", torch.int32).cpu().numpy().view(np.uint32)
-    area = ((rect[:I] >> 16) - (rect[:I] & 0xFFFF)) * ((rect[I:2 * I] >> 16) - (rect[I:2 * I] & 0xFFFF))
+    bins = rp.region("item_rect", torch.int32).cpu().numpy().view(np.uint32).reshape(-1, 4)[:I]
+    rx, ry = bins[:, 0], bins[:, 1] & 0x0FFF0FFF
+    area = ((rx >> 16) - (rx & 0xFFFF)) * ((ry >> 16) - (ry & 0xFFFF))
     large = (area > 32) & (ref["proj"][0]["n_tiles"] > 0)
     assert taken == int(((area[area > 32] + 63) // 64).sum()) and taken > cap
-    off = int(rp.plan.region_offset[20])
-    first = rp.ws[off:off + 16 * I].view(torch.int32).cpu().numpy().view(np.uint32).reshape(I, 4)[:, 2]
+    first = bins[:, 2]
     stored = large & (first != 0xFFFFFFFF)
     assert stored.sum() > 10 and (large & ~stored).sum() > 10
     assert np.array_equal(rp.region("item_ntiles", torch.int32).cpu().numpy()[:I], ref["proj"][0]["n_tiles"])
@@ -167,9 +219,9 @@ def test_forward_backward_parity(tile, W, H, lds):
     # the region keeps the raw moments of dL/dpower; with power = -(A dx^2 + 2 B dx dy + C dy^2) / 2
     # and alpha = o exp(power) the 2D gradients are linear in them, given the item's conic and opacity
     mo = rp.region("grad2d", torch.float32).cpu().numpy().reshape(-1, 16)[:, :9].astype(np.float64)
-    rec = rp.region("item_rec", torch.float32).cpu().numpy().reshape(-1, 8)[: len(mo)].astype(np.float64)
+    rec = rp.region("item_rec", torch.float32).cpu().numpy().reshape(-1, 4)[: len(mo)].astype(np.float64)
     nt = rp.region("item_ntiles", torch.int32).cpu().numpy()[: len(mo)]
-    A, B, C, o = rec[:, 2], rec[:, 3], rec[:, 4], np.where(nt > 0, rec[:, 5], 1.0)
+    A, B, C, o = rec[:, 0], rec[:, 1], rec[:, 2], np.where(nt > 0, rec[:, 3], 1.0)
     g2 = np.stack([-(A * mo[:, 0] + B * mo[:, 1]), -(B * mo[:, 0] + C * mo[:, 1]), -0.5 * mo[:, 2], -mo[:, 3],
                    -0.5 * mo[:, 4], mo[:, 5] / o, mo[:, 6], mo[:, 7], mo[:, 8]])
     g2[:, nt == 0] = 0.0
