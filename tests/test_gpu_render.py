@@ -77,20 +77,39 @@ def test_projection_and_pair_lists_bit_exact(tile, bits, opacity):
     assert np.all(ranges[~nonempty, 0] == ranges[~nonempty, 1])      # empty tiles hold an empty range
 
 
-def test_row_bands_cover_every_contributing_pixel():
+def _band_scene(kind):
+    if kind == "small":
+        return _scene(3000, 21, 3, 131, 77, log_scale=-3.3)
+    if kind == "needles":
+        # one axis stretched 30x and another shrunk 5x: thin ellipses at every orientation, the case
+        # where the footprint's row extent depends most on the conic's cross term
+        gs, cams = _scene(2500, 22, 3, 160, 112, log_scale=-3.4)
+        gs.scales[0] *= np.float32(30.0)
+        gs.scales[1] *= np.float32(0.2)
+        return gs, cams
+    # large footprints that overflow the ballot-word buffer, so that the emission re-tests them
+    gs = vi.random_gaussians(1200, 23, log_scale_mean=-1.5, log_scale_std=0.3)
+    return gs, vi.orbit_cameras(1, 256, 192, azimuth0=0.4)
+
+
+@pytest.mark.parametrize("kind", ["small", "needles", "overflow"])
+def test_row_bands_cover_every_contributing_pixel(kind):
     """With 16x16 tiles each pair value carries, in bits 27..30, the 4-row bands of its tile that the
     footprint can reach, and the forward evaluates only those.  Every pixel of the tile where the
     Gaussian reaches alpha >= 1/255 (float64, from the oracle's float32 projection) must lie in a set
     band; the bands must also skip something, or the test would pass on an all-ones mask."""
     api = _api()
-    gs, cams = _scene(3000, 21, 3, 131, 77, log_scale=-3.3)
+    gs, cams = _band_scene(kind)
     P = to_dev(gs)
-    rp = api.plan_batch(cams, [0, gs.n], tile=16, pair_capacity=1 << 20)
+    rp = api.plan_batch(cams, [0, gs.n], tile=16, pair_capacity=1 << 21)
     out = api.render_fwd(rp, P)
     torch.cuda.synchronize()
     ref = binning.pair_lists(gs, cams, 16)
     n = ref["tile"].size
     assert int(out.status[0]) == 0 and int(out.status[1]) == n
+    if kind == "overflow":
+        taken = int(rp.region("counters", torch.int32).cpu().numpy().view(np.uint64)[2])
+        assert taken > int(rp.plan.region_bytes[22]) // 8
     pv = rp.region("pair_item", torch.int32).cpu().numpy()[:n].view(np.uint32)
     assert np.array_equal(pv & ITEM_MASK, ref["item"])
     bands = (pv >> 27) & 0xF
@@ -118,10 +137,11 @@ def test_row_bands_cover_every_contributing_pixel():
         q = A[:, None] * dx * dx + 2 * B[:, None] * dx * dy[:, None] + C[:, None] * dy[:, None] ** 2
         hit = ((o[:, None] * np.exp(-0.5 * q) >= 1 / 255) & xin).any(1) & (y < H)
         need |= np.where(hit, np.uint32(1 << (row // 4)), np.uint32(0))
-    say(f"row bands: {n} pairs, {(bands != 0xF).mean():.2f} with a band skipped, "
+    say(f"row bands ({kind}): {n} pairs, {(bands != 0xF).mean():.2f} with a band skipped, "
         f"{np.count_nonzero(need & ~bands)} pairs missing a needed band")
     assert not np.any(need & ~bands)
-    assert (bands != 0xF).mean() > 0.2
+    # (large footprints skip bands only in their first and last tile rows)
+    assert (bands != 0xF).mean() > dict(small=0.5, needles=0.01, overflow=0.02)[kind]
 
 
 @pytest.mark.parametrize("tile", [8, 16])
