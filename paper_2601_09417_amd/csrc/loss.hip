@@ -305,6 +305,24 @@ __global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ x, 
     const float* const src[3] = {p1 + chan, p2 + chan, p3 + chan};
     load_halo<3>(src, W, H, ox, oy, sp);
   }
+  // The thread's own outputs need x and y at its RPT pixels: requested now, so that the loads
+  // complete while the block filters (range-checked: a pixel outside the plane reads 0, unused).
+  const int col = threadIdx.x % TX;
+  const int r0 = (threadIdx.x / TX) * RPT;
+  const int gx = bx * TX + col;
+  const int plane_bytes = W * H * 4;
+  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(x + chan), (short)0,
+                                                                      plane_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(y + chan), (short)0,
+                                                                      plane_bytes, 0x00020000);
+  float xv[RPT], yv[RPT];
+#pragma unroll
+  for (int o = 0; o < RPT; ++o) {
+    const int gy = by * TY + r0 + o;
+    const int off = gx < W && gy < H ? 4 * (gy * W + gx) : plane_bytes;
+    xv[o] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, off, 0, 0));
+    yv[o] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ry, off, 0, 0));
+  }
   __syncthreads();
   constexpr int CPT = 4;
   constexpr int kTasks = EY * (TX / CPT);
@@ -350,9 +368,6 @@ __global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ x, 
     }
   }
   __syncthreads();
-  const int col = threadIdx.x % TX;
-  const int r0 = (threadIdx.x / TX) * RPT;
-  const int gx = bx * TX + col;
   float b[RPT][3];
 #pragma unroll
   for (int o = 0; o < RPT; ++o)
@@ -369,24 +384,17 @@ __global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ x, 
     }
   }
   if (gx >= W) return;
-  const int plane_bytes = W * H * 4;
-  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(x + chan), (short)0,
-                                                                      plane_bytes, 0x00020000);
-  const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(y + chan), (short)0,
-                                                                      plane_bytes, 0x00020000);
   const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(grad + chan, (short)0, plane_bytes, 0x00020000);
 #pragma unroll
   for (int o = 0; o < RPT; ++o) {
     const int gy = by * TY + r0 + o;
     if (gy >= H) continue;
     const int off = 4 * (gy * W + gx);
-    const float xv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, off, 0, 0));
-    const float yv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ry, off, 0, 0));
-    const float d = xv - yv;
+    const float d = xv[o] - yv[o];
     const float sg = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
     __builtin_amdgcn_raw_buffer_store_b32(
-        __builtin_bit_cast(uint32_t, w_l1 * sg - w_ssim * (b[o][0] + 2.0f * xv * b[o][1] + yv * b[o][2])), rg, off, 0,
-        0);
+        __builtin_bit_cast(uint32_t, w_l1 * sg - w_ssim * (b[o][0] + 2.0f * xv[o] * b[o][1] + yv[o] * b[o][2])), rg,
+        off, 0, 0);
   }
 }
 
