@@ -83,7 +83,7 @@ def test_fullsize_gradient_central_differences():
     top = max(float(np.abs(fd).max(initial=0.0)) for _, fd in res.values())
     for name, (gpu, fd) in res.items():
         # relative to the group's largest difference quotient, floored at 1e-3 of the largest of all
-        # groups so that a group of near-zero derivatives is not judged against its own noise
+        # groups so that a group of near-zero derivatives is not measured against its own noise
         scale = max(float(np.abs(fd).max(initial=0.0)), 1e-3 * top)
         err = float(np.abs(gpu - fd).max(initial=0.0)) / scale
         say(f"  {name}: {gpu.size} scalars, max |gpu - fd| / scale = {err:.2e}")
