@@ -2,7 +2,7 @@
 //
 // Scan: reduce -> single-workgroup scan of the block sums -> per-block scan with the block
 // offset added.  Sort: one histogram kernel counts the digits of every pass in one read of the
-// keys, then each pass is a single kernel over 4096-key tiles that ranks equal digits inside each
+// keys, then each pass is a single kernel over 8192-key tiles that ranks equal digits inside each
 // wave with ballots (a lane's rank = set bits of its digit-match mask below it) and across a
 // wave's rounds through per-wave LDS counters, learns the earlier tiles' digit counts by
 // decoupled look-back, partitions the tile in LDS, and writes it out in digit order (coalesced
@@ -491,7 +491,7 @@ namespace {
 // Scratch of one sort: per-block digit counts of the histogram kernel, digit totals, then the
 // look-back status words of every pass, which the histogram kernel clears.
 struct RadixLayout {
-  int64_t nb;        // 4096-key tiles
+  int64_t nb;        // 4096-key tiles (status words are sized for them, twice what a pass uses)
   int passes_max;    // passes of a 32-bit key
   int radix;         // 1 << digit width
   int G;             // histogram blocks
