@@ -179,9 +179,9 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
   float l1 = 0.0f;   // |x - y| of the thread's outputs (zero outside the image)
 #pragma unroll
   for (int o = 0; o < RPT; ++o) l1 += fabsf(sx[r0 + o + RAD][col + RAD] - sy[r0 + o + RAD][col + RAD]);
-  // Horizontal pass: a task filters four adjacent columns of one halo row, so each of the 14 input
-  // values it reads forms its two products once for all four outputs.
-  constexpr int CPT = 4;                          // columns per task
+  // Horizontal pass: a task filters eight adjacent columns of one halo row, so each of the 18 input
+  // values it reads forms its two products once for all eight outputs (one round of 168 tasks).
+  constexpr int CPT = 8;                          // columns per task
   constexpr int kTasks = EY * (TX / CPT);
   static_assert(kTasks <= 512, "two rounds of tasks");
   float keep[2][2][CPT];
@@ -262,10 +262,10 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
       const float mm = mx * mx + my * my, cxy = m[o][3] - mx * my;
       const float A1 = 2.0f * mx * my + kC1, A2 = 2.0f * cxy + kC2;
       const float B1 = mm + kC1, B2 = (m[o][2] - mm) + kC2;   // sigma_x^2 + sigma_y^2 + C2
-      // four hardware reciprocals (about 1 ulp) instead of six divisions
-      const float iA1 = __builtin_amdgcn_rcpf(A1), iA2 = __builtin_amdgcn_rcpf(A2);
-      const float iB1 = __builtin_amdgcn_rcpf(B1), iB2 = __builtin_amdgcn_rcpf(B2);
-      const float sv = (A1 * A2) * (iB1 * iB2);
+      // two hardware reciprocals (about 1 ulp), of A1 A2 and B1 B2, instead of six divisions
+      const float AA = A1 * A2, iA = __builtin_amdgcn_rcpf(AA), iB = __builtin_amdgcn_rcpf(B1 * B2);
+      const float iA1 = A2 * iA, iA2 = A1 * iA, iB1 = B2 * iB, iB2 = B1 * iB;
+      const float sv = AA * iB;
       const int off = 4 * (gy * W + gx);
       __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, 2.0f * sv * (my * (iA1 - iA2) + mx * (iB2 - iB1))),
                                             r1, off, 0, 0);
