@@ -179,9 +179,9 @@ __global__ __launch_bounds__(256) void k_ssim_maps(const float* __restrict__ x, 
   float l1 = 0.0f;   // |x - y| of the thread's outputs (zero outside the image)
 #pragma unroll
   for (int o = 0; o < RPT; ++o) l1 += fabsf(sx[r0 + o + RAD][col + RAD] - sy[r0 + o + RAD][col + RAD]);
-  // Horizontal pass: a task filters eight adjacent columns of one halo row, so each of the 18 input
-  // values it reads forms its two products once for all eight outputs (one round of 168 tasks).
-  constexpr int CPT = 8;                          // columns per task
+  // Horizontal pass: a task filters four adjacent columns of one halo row, so each of the 14 input
+  // values it reads forms its two products once for all four outputs.
+  constexpr int CPT = 4;                          // columns per task
   constexpr int kTasks = EY * (TX / CPT);
   static_assert(kTasks <= 512, "two rounds of tasks");
   float keep[2][2][CPT];
