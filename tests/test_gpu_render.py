@@ -205,12 +205,20 @@ def test_large_footprints_beyond_the_ballot_word_buffer():
     assert np.array_equal(rp.region("pair_item", torch.int32).cpu().numpy()[:n] & ITEM_MASK, ref["item"])
 
 
-# (the last three stage the compositing lists in LDS batches of 32 or 64 entries)
-@pytest.mark.parametrize("tile,W,H,lds", [(16, 64, 64, 0), (16, 101, 67, 0), (8, 50, 37, 0), (32, 96, 80, 0),
-                                          (16, 101, 67, 32), (16, 64, 64, 64), (8, 50, 37, 64)])
-def test_forward_backward_parity(tile, W, H, lds):
+# Opacities up to 1 and larger footprints: Gaussians whose alpha reaches the 0.99 clamp near their
+# centre (a few pixels per view), mixed with ones that cannot reach it.
+HIGH_OPACITY = dict(opacity=(0.9, 1.0), log_scale=-2.0)
+
+
+# (the cases with lds > 0 stage the compositing lists in LDS batches of 32 or 64 entries)
+@pytest.mark.parametrize("tile,W,H,lds,opacity", [(16, 64, 64, 0, None), (16, 101, 67, 0, None), (8, 50, 37, 0, None),
+                                                  (32, 96, 80, 0, None), (16, 101, 67, 32, None),
+                                                  (16, 64, 64, 64, None), (8, 50, 37, 64, None),
+                                                  (16, 101, 67, 0, HIGH_OPACITY), (16, 101, 67, 32, HIGH_OPACITY),
+                                                  (8, 50, 37, 0, HIGH_OPACITY), (32, 96, 80, 0, HIGH_OPACITY)])
+def test_forward_backward_parity(tile, W, H, lds, opacity):
     api = _api()
-    gs, cams = _scene(600, 3, 2, W, H)
+    gs, cams = _scene(600, 3, 2, W, H, **(opacity or {}))
     say(f"fwd/bwd parity tile={tile} {W}x{H} n={gs.n} lds batch {lds}")
     P = to_dev(gs)
     rp = api.plan_batch(cams, [0, gs.n], tile=tile, pair_capacity=1 << 18, lds_batch=lds, lds_batch_bwd=lds)
